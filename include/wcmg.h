@@ -1,0 +1,204 @@
+/*
+ * wcmg — Wilson-clover multigrid on AMD MI355X (gfx950).
+ *
+ * C ABI of the library.  It follows the structure of the multigrid solver of
+ * D. Richtmann, P. A. Boyle, T. Wettig, "Multigrid for Wilson Clover Fermions
+ * in Grid" (LATTICE2018, arXiv:1904.08678):
+ *   - Sec. 2.1: intergrid operators (restriction / prolongation), creation and
+ *     application of the coarse-grid operator through its site-diagonal part
+ *     (Mdiag) and single-direction hops (Mdir), recursion to more levels,
+ *     initial setup (smoother iterated on random vectors), iterative
+ *     refinement setup, MR / GMRES / flexible GMRES, double-precision outer
+ *     solver with a single-precision preconditioner;
+ *   - Sec. 2.2: the chirality-preserving prolongator
+ *     P = [ (1+gamma5)/2 psi_i , (1-gamma5)/2 psi_i ];
+ *   - Sec. 3: restriction owned per coarse site through a coarse-to-fine lookup
+ *     table (no races), fine data linearised aggregate by aggregate.
+ * The paper gives no formula for the Dirac operator; the conventions used are:
+ * chiral Euclidean gamma basis (gamma5 = diag(1,1,-1,-1)), mass form
+ *   D = (4+m0) + C - 1/2 sum_mu [(1-gamma_mu) U_mu(x) T_mu + (1+gamma_mu) U_mu(x-mu)^dag T_-mu],
+ * Sheikholeslami-Wohlert clover C = c_sw (i/4) sum sigma_{mu nu} F_{mu nu}
+ * with clover-leaf F = (Q - Q^dag)/8, antiperiodic t boundary as a sign on
+ * t-hops crossing the boundary.
+ *
+ * Memory and execution
+ *   - Every data pointer is a caller-owned DEVICE pointer unless named *_host.
+ *     The library never frees caller memory; it copies what it keeps.
+ *   - The context owns every internal buffer.  All work is enqueued on the HIP
+ *     stream given at creation.  Calls that need a value on the host
+ *     (setup, refine, solve, get_*) synchronise that stream before returning.
+ *   - One context per host thread.
+ *
+ * Layouts at the ABI (interleaved complex, lexicographic sites with x fastest,
+ * i = x + Lx*(y + Ly*(z + Lz*t))):
+ *   gauge U          complex128 [V][4][3][3]   (direction mu = x,y,z,t; row, col)
+ *   clover blocks    complex128 [V][2][6][6]   (chirality +, -; index 3*spin'+colour)
+ *   fine field       [nrhs][V][4][3]            (spin, colour; spins 0,1 have gamma5 = +1)
+ *   coarse field     [nrhs][Vc][Nb]             (b < Nb/2: sigma3 = +1, then sigma3 = -1)
+ *   coarse operator  complex128 [Vc][9][Nb][Nb] (0 = site, then +x,-x,+y,-y,+z,-z,+t,-t;
+ *                                                block d maps the field at the
+ *                                                neighbour in direction d to site x)
+ *   near-null vectors complex128 [nv][V_l][ns_l] (ns_0 = 12, ns_l = Nb_l)
+ * The complex type of a field follows the precision argument: WCMG_F64 ->
+ * complex128; WCMG_F32 and WCMG_BF16 -> complex64 (BF16 refers to the storage
+ * of coarse-operator blocks only; vectors and accumulation stay FP32).
+ *
+ * Errors: every call returns a wcmg_status; nothing throws or aborts.
+ * wcmg_last_error() gives a message for the last failing call on a context.
+ */
+#ifndef WCMG_H
+#define WCMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WCMG_OK = 0,
+  WCMG_ERR_ARG = 1,        /* null pointer, bad enum, bad size */
+  WCMG_ERR_DIMS = 2,       /* lattice not divisible by a block, coarse extent < 2 */
+  WCMG_ERR_STATE = 3,      /* call out of order (e.g. solve before setup) */
+  WCMG_ERR_HIP = 4,        /* a HIP runtime call failed */
+  WCMG_ERR_NOMEM = 5,      /* device allocation failed */
+  WCMG_ERR_BREAKDOWN = 6,  /* Gram-Schmidt breakdown: dependent near-null vectors */
+  WCMG_ERR_NOCONV = 7,     /* solver reached its iteration limit; info and x are filled */
+  WCMG_ERR_NAN = 8         /* NaN or Inf detected in a norm */
+} wcmg_status;
+
+typedef enum { WCMG_F64 = 0, WCMG_F32 = 1, WCMG_BF16 = 2 } wcmg_prec;
+
+typedef struct {
+  int32_t dims[4];         /* fine lattice extents x, y, z, t */
+  double m0;               /* bare mass in D = (4 + m0) + ... */
+  double c_sw;             /* clover coefficient */
+  int32_t antiperiodic_t;  /* 1: antiperiodic fermion boundary in t */
+  int32_t n_levels;        /* 1 (no multigrid) .. 3 */
+  int32_t block[3][4];     /* aggregate extents from level l to l+1 */
+  int32_t n_vec[3];        /* near-null vectors at level l; Nb_{l+1} = 2 n_vec[l] */
+  int32_t relax_sweeps;    /* MR sweeps on D x = 0 in the initial setup */
+  int32_t refine_iters;    /* iterative-setup iterations run by wcmg_setup */
+  int32_t post_smooth;     /* MR post-smoothing steps in the cycle */
+  int32_t coarse_restart, coarse_maxit, coarse_fixed_iters; /* coarsest GMRES; fixed > 0 disables early exit */
+  double coarse_tol;       /* relative residual target of the coarsest GMRES */
+  int32_t kcycle;          /* 1: K-cycle (FGMRES on intermediate levels), 0: V-cycle */
+  int32_t kcycle_maxit;
+  double kcycle_tol;
+  int32_t outer_restart, outer_maxit;
+  double outer_tol;        /* true relative residual ||b - D x|| / ||b|| */
+  int32_t cycle_prec;      /* WCMG_F64 or WCMG_F32: arithmetic of the preconditioner */
+  int32_t coarse_store_prec; /* storage of coarse blocks inside the cycle: F64, F32 or BF16 */
+  int32_t setup_prec;      /* arithmetic of the relaxation in the setup: F64 or F32 */
+  int32_t reserved[5];
+} wcmg_params;
+
+typedef struct wcmg_ctx wcmg_ctx;
+
+/* Fill *p with the defaults (two levels, 4^4 aggregates, 12 vectors, 20 sweeps,
+ * MR(4), GMRES(20) to 0.05 / 100 on the coarsest level, FGMRES(20) to 1e-10,
+ * FP64 everywhere). */
+void wcmg_default_params(wcmg_params* p);
+
+/* Create a context for the lattice in *p; stream is a hipStream_t (may be NULL
+ * for the default stream).  Validates dimensions: WCMG_ERR_DIMS when a block
+ * does not divide its level or a coarse extent falls below 2. */
+int wcmg_create(const wcmg_params* p, void* stream, wcmg_ctx** out);
+int wcmg_destroy(wcmg_ctx* ctx);
+const char* wcmg_last_error(const wcmg_ctx* ctx);
+
+/* Gauge field U (complex128 [V][4][3][3], device).  Copied.  Also builds the
+ * clover term from U with c_sw (Sec. 2.1 names the operator; the clover-leaf
+ * construction is the standard one). */
+int wcmg_set_gauge(wcmg_ctx* ctx, const void* U);
+/* Replace the clover term by caller blocks (complex128 [V][2][6][6], device,
+ * Hermitian, without the 4+m0 mass term). */
+int wcmg_set_clover(wcmg_ctx* ctx, const void* blocks);
+/* Read the clover term back (complex128 [V][2][6][6], device). */
+int wcmg_get_clover(wcmg_ctx* ctx, void* blocks);
+
+/* Start vectors of the initial setup at level l: complex128 [nv][V_l][ns_l]. */
+int wcmg_set_null_vectors(wcmg_ctx* ctx, int level, const void* v, int nv);
+/* Current near-null vectors (normalised, before orthonormalisation). */
+int wcmg_get_null_vectors(wcmg_ctx* ctx, int level, void* v);
+/* The orthonormalised chirality halves defining P_l (Sec. 2.2), [nv][V_l][ns_l]. */
+int wcmg_get_prolongator(wcmg_ctx* ctx, int level, void* v);
+
+/* Initial setup of every level (Sec. 2.1) from the start vectors, then
+ * refine_iters iterations of the iterative setup. */
+int wcmg_setup(wcmg_ctx* ctx);
+/* Iterative refinement setup (Sec. 2.1, DDalphaAMG-style): each vector is
+ * replaced by the current preconditioner applied to it, then P and the coarse
+ * operators are rebuilt. */
+int wcmg_refine(wcmg_ctx* ctx, int iterations);
+/* Replace the near-null vectors of level l (complex128 [nv][V_l][ns_l]) and
+ * rebuild P_l, D_{l+1} and the Galerkin products below. */
+int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v);
+
+/* Aggregation map of level l -> l+1 (a1): per site of level l (lexicographic),
+ * the coarse site and the offset inside its aggregate.  Host int32 arrays of V_l. */
+int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host);
+
+/* Coarse operator of level l >= 1 as complex128 [Vc][9][Nb][Nb] (device). */
+int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks);
+int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks);
+
+/* out = D_l in for nrhs fields (level 0: Wilson-clover, Sec. 2.1 "Dirac
+ * operator"; level >= 1: Mdiag + the eight Mdir blocks, Sec. 2.1).  prec: the
+ * arithmetic, and the complex type of in/out; WCMG_BF16 only for level >= 1. */
+int wcmg_apply_D(wcmg_ctx* ctx, int level, const void* in, void* out, int nrhs, int prec);
+/* coarse = R_l fine = P_l^dag fine (Sec. 3 blockProject), fine at level l. */
+int wcmg_restrict(wcmg_ctx* ctx, int level, const void* fine, void* coarse, int nrhs, int prec);
+/* fine = P_l coarse. */
+int wcmg_prolong(wcmg_ctx* ctx, int level, const void* coarse, void* fine, int nrhs, int prec);
+/* x = K r: one application of the multigrid preconditioner rooted at level 0
+ * (complex128 fields; arithmetic per cycle_prec). */
+int wcmg_cycle(wcmg_ctx* ctx, const void* r, void* x);
+
+typedef struct {
+  int32_t outer_iters;
+  int32_t converged;
+  double true_rel_res;     /* ||b - D x|| / ||b||, recomputed in FP64 at exit */
+  double t_solve_s;        /* wall time of the call */
+  int64_t coarse_iters;    /* total coarsest-level GMRES iterations */
+  int64_t cycles;          /* preconditioner applications */
+} wcmg_solve_info;
+
+/* Solve D x = b with FP64 flexible GMRES preconditioned by the MG cycle
+ * (Sec. 2.1).  b, x: complex128 [nrhs][V][4][3]; x holds the initial guess.
+ * info: host array of nrhs entries (may be NULL). */
+int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info* info);
+
+/* Per-phase timers in seconds: [0] setup total, [1] relaxation, [2] Gram-Schmidt,
+ * [3] coarsening, [4] refinement, [5] last solve.  n entries are written. */
+int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
+
+/* Kernel timing: when enabled, launches of the named kernel family are
+ * bracketed by HIP events on the context stream.  Families: "dslash",
+ * "coarse_apply", "restrict", "prolong".  Stats return the number of timed
+ * launches and their total duration in milliseconds, then reset. */
+int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable);
+int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms);
+
+/* ---- standalone coarse operator (CoarsenedMatrix without a hierarchy) ---- */
+typedef struct wcmg_coarse wcmg_coarse;
+/* dims: coarse lattice extents (each >= 2); nb: block size (even);
+ * store_prec: WCMG_F64, WCMG_F32 or WCMG_BF16 storage of the blocks. */
+int wcmg_coarse_create(const int32_t dims[4], int nb, int store_prec, void* stream, wcmg_coarse** out);
+int wcmg_coarse_destroy(wcmg_coarse* op);
+/* Load blocks [Vc][9][Nb][Nb] from device memory: complex128 when src_prec is
+ * WCMG_F64, complex64 when WCMG_F32.  Converted to the storage precision
+ * (BF16: round to nearest even). */
+int wcmg_coarse_set(wcmg_coarse* op, const void* blocks, int src_prec);
+/* out = D_c in for nrhs fields [nrhs][Vc][Nb]: complex128 for F64 storage,
+ * complex64 otherwise (FP32 accumulation). */
+int wcmg_coarse_apply(wcmg_coarse* op, const void* in, void* out, int nrhs);
+/* Time `reps` back-to-back applies between HIP events on the op's stream;
+ * *avg_ms receives the mean launch duration. */
+int wcmg_coarse_time(wcmg_coarse* op, const void* in, void* out, int nrhs, int reps, double* avg_ms);
+const char* wcmg_coarse_last_error(const wcmg_coarse* op);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCMG_H */

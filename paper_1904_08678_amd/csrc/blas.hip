@@ -1,0 +1,420 @@
+// Vector kernels for the Krylov solvers (Sec. 2.1: MR, GMRES, FGMRES).
+//
+// Reductions are deterministic: a fixed grid of workgroups writes one FP64
+// partial per workgroup, and a single workgroup adds the partials in index
+// order.  Scalars (inner products, Givens rotations, step lengths) stay in
+// device memory; the update kernels read them there, so a solver iteration
+// needs no host round trip.  Every kernel takes a `run` flag: when it is 0 the
+// kernel returns at once (this is how converged solves skip their remaining,
+// already enqueued work).
+#include "kernels.h"
+
+namespace wcmg {
+
+constexpr int kRedBlocks = 512;  // partials per reduction (fixed: results do not depend on timing)
+
+inline int red_blocks(long n) { return (int)std::min<long>(kRedBlocks, std::max<long>(1, (n + 1023) / 1024)); }
+
+__device__ inline cd64 wave_sum(cd64 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  return v;
+}
+
+// partial[blk][k] = sum over this block's range of conj(a_k[i]) b[i], k < m
+template <typename R>
+__global__ void __launch_bounds__(256) k_dot_partial(const cplx<R>* __restrict__ a, long astride, int m,
+                                                      const int* __restrict__ m_dev, const cplx<R>* __restrict__ b,
+                                                      long n, cd64* __restrict__ partial, int mstride,
+                                                      const int* __restrict__ run) {
+  if (run && !*run) return;
+  if (m_dev) m = *m_dev;
+  __shared__ cd64 lds[4];
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < m; ++k) {
+    const cplx<R>* ak = a + k * astride;
+    cd64 s = mkc(0.0, 0.0);
+    for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      cplx<R> x = ak[i], y = b[i];
+      s.re += (double)x.re * y.re + (double)x.im * y.im;
+      s.im += (double)x.re * y.im - (double)x.im * y.re;
+    }
+    s = wave_sum(s);
+    if (lane == 0) lds[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      cd64 t = mkc(0.0, 0.0);
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
+      partial[(long)blockIdx.x * mstride + k] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// out[k * ostride] (op)= sum_g partial[g][k]; mode 0: store, 1: add, 2: subtract
+__global__ void k_dot_finish(const cd64* __restrict__ partial, int G, int m, const int* __restrict__ m_dev,
+                             int mstride, cd64* __restrict__ out, int ostride, int mode,
+                             const int* __restrict__ run) {
+  if (run && !*run) return;
+  if (m_dev) m = *m_dev;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    cd64 s = mkc(0.0, 0.0);
+    for (int g = 0; g < G; ++g) s = cadd(s, partial[(long)g * mstride + k]);
+    cd64* o = out + (long)k * ostride;
+    if (mode == 0) *o = s;
+    else if (mode == 1) *o = cadd(*o, s);
+    else *o = csub(*o, s);
+  }
+}
+
+// y[i] += sign * sum_{k<m} coef[k * cstride] * V_k[i]
+template <typename R>
+__global__ void __launch_bounds__(256) k_multi_axpy(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ V,
+                                                     long vstride, int m, const int* __restrict__ m_dev,
+                                                     const cd64* __restrict__ coef, int cstride, double sign, long n,
+                                                     const int* __restrict__ run) {
+  if (run && !*run) return;
+  if (m_dev) m = *m_dev;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx<R> acc = y[i];
+  for (int k = 0; k < m; ++k) {
+    cd64 c = coef[(long)k * cstride];
+    cplx<R> cc = mkc((R)(sign * c.re), (R)(sign * c.im));
+    cfma(acc, cc, V[k * vstride + i]);
+  }
+  y[i] = acc;
+}
+
+// y = a * x + b * y with real constants
+template <typename R>
+__global__ void k_axpby(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, R a, R b, long n,
+                        const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx<R> v = x[i];
+  if (b == (R)0) {
+    y[i] = mkc(a * v.re, a * v.im);
+  } else {
+    cplx<R> w = y[i];
+    y[i] = mkc(a * v.re + b * w.re, a * v.im + b * w.im);
+  }
+}
+
+// y = x * (1 / sqrt(nrm2->re))  (nrm2 holds a squared norm)
+template <typename R>
+__global__ void k_scale_inv_norm(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, const cd64* __restrict__ nrm2,
+                                 long n, const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = 1.0 / sqrt(nrm2->re);
+  cplx<R> v = x[i];
+  y[i] = mkc((R)(s * v.re), (R)(s * v.im));
+}
+
+template <typename R>
+__global__ void k_zero(cplx<R>* __restrict__ y, long n, const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = mkc((R)0, (R)0);
+}
+
+// y = a - b
+template <typename R>
+__global__ void k_sub(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ b, long n,
+                      const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = csub(a[i], b[i]);
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert(const cplx<Ti>* __restrict__ x, cplx<To>* __restrict__ y, long n, const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = ccast<To>(x[i]);
+}
+
+// MR update: dots[0] = <p, r>, dots[1] = <p, p>; alpha = dots0 / dots1;
+// x += alpha r; r -= alpha p.
+template <typename R>
+__global__ void k_mr_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+                            const cd64* __restrict__ dots, long n, const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double pp = dots[1].re;
+  const cd64 al = pp > 0.0 ? mkc(dots[0].re / pp, dots[0].im / pp) : mkc(0.0, 0.0);
+  const cplx<R> a = mkc((R)al.re, (R)al.im);
+  cplx<R> xi = x[i], ri = r[i], pi = p[i];
+  cfma(xi, a, ri);
+  cfma(ri, cneg(a), pi);
+  x[i] = xi;
+  r[i] = ri;
+}
+
+// partial[blk][0] = <p, r>, partial[blk][1] = <p, p>
+template <typename R>
+__global__ void __launch_bounds__(256) k_dot2_partial(const cplx<R>* __restrict__ p, const cplx<R>* __restrict__ r,
+                                                       long n, cd64* __restrict__ partial,
+                                                       const int* __restrict__ run) {
+  if (run && !*run) return;
+  __shared__ cd64 lds[8];
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  cd64 s = mkc(0.0, 0.0), q = mkc(0.0, 0.0);
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    cplx<R> x = p[i], y = r[i];
+    s.re += (double)x.re * y.re + (double)x.im * y.im;
+    s.im += (double)x.re * y.im - (double)x.im * y.re;
+    q.re += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  s = wave_sum(s);
+  q = wave_sum(q);
+  if (lane == 0) {
+    lds[wave] = s;
+    lds[4 + wave] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cd64 a = mkc(0.0, 0.0), b = mkc(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a = cadd(a, lds[w]);
+      b = cadd(b, lds[4 + w]);
+    }
+    partial[blockIdx.x * 2] = a;
+    partial[blockIdx.x * 2 + 1] = b;
+  }
+}
+
+// ---------------------------------------------------------------- GMRES control (single lane)
+// State block (int): [0] run, [1] live, [2] jdone, [3] total, [4] reason.
+// Scalar block (cd64): H [(m+1) x m], cs [m], sn [m], g [m+1], y [m],
+//   then misc: [0] bnorm^2 (re), [1] beta^2 (re), [2] est (re), [3] hn^2 (re).
+__global__ void k_gmres_init(int* st, const int* parent) {
+  st[1] = parent ? *parent : 1;
+  st[0] = st[1];
+  st[2] = 0;
+  st[3] = 0;
+  st[4] = 0;
+}
+
+// Start of a restart cycle: beta = ||r||; decide whether to iterate.
+__global__ void k_gmres_cycle_start(int* st, cd64* S, int m, double tol, int limit, int fixed) {
+  st[0] = 0;
+  st[2] = 0;
+  if (!st[1]) return;
+  cd64* g = S + (m + 1) * m + 2 * m;
+  cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+  const double bn = sqrt(misc[0].re), beta = sqrt(misc[1].re);
+  misc[2].re = bn > 0 ? beta / bn : 0.0;
+  if (st[3] >= limit || bn == 0.0 || beta == 0.0 || (!fixed && beta <= tol * bn) || !(beta == beta)) {
+    st[1] = 0;
+    st[4] = !(beta == beta) ? 3 : 1;
+    return;
+  }
+  for (int i = 0; i <= m; ++i) g[i] = mkc(0.0, 0.0);
+  g[0] = mkc(beta, 0.0);
+  st[0] = 1;
+}
+
+// Givens update for column j (after H[0..j][j] and hn^2 = misc[3]).
+__global__ void k_gmres_givens(int* st, cd64* S, int m, int j, double tol, int limit, int fixed,
+                               int stop_on_estimate) {
+  if (!st[0]) return;
+  cd64* H = S;
+  cd64* cs = S + (m + 1) * m;
+  cd64* sn = cs + m;
+  cd64* g = sn + m;
+  cd64* misc = g + (m + 1) + m;
+  const double hn = sqrt(misc[3].re);
+  H[(j + 1) * m + j] = mkc(hn, 0.0);
+  for (int i = 0; i < j; ++i) {
+    cd64 a = H[i * m + j], b = H[(i + 1) * m + j];
+    cd64 t = cmul(cs[i], a);
+    cfma(t, sn[i], b);
+    cd64 u = cmul(cneg(cconj(sn[i])), a);
+    cfma(u, cconj(cs[i]), b);
+    H[i * m + j] = t;
+    H[(i + 1) * m + j] = u;
+  }
+  const cd64 a = H[j * m + j];
+  const double den = sqrt(a.re * a.re + a.im * a.im + hn * hn);
+  cd64 c = den == 0.0 ? mkc(1.0, 0.0) : mkc(a.re / den, -a.im / den);  // conj(a)/den
+  cd64 s = den == 0.0 ? mkc(0.0, 0.0) : mkc(hn / den, 0.0);
+  cs[j] = c;
+  sn[j] = s;
+  H[j * m + j] = mkc(den, 0.0);
+  H[(j + 1) * m + j] = mkc(0.0, 0.0);
+  const cd64 gj = g[j];
+  g[j + 1] = cmul(cneg(cconj(s)), gj);
+  g[j] = cmul(c, gj);
+  st[2] = j + 1;
+  st[3] += 1;
+  const double bn = sqrt(misc[0].re);
+  const double est = bn > 0 ? sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im) / bn : 0.0;
+  misc[2].re = est;
+  bool stop = false;
+  if (st[3] >= limit) {
+    stop = true;
+    st[1] = 0;
+    st[4] = 2;
+  }
+  if (!fixed && est <= tol) {
+    stop = true;
+    if (stop_on_estimate) {
+      st[1] = 0;
+      st[4] = 1;
+    }
+  }
+  if (hn == 0.0 || !(est == est)) {
+    stop = true;
+    st[1] = 0;
+    st[4] = (est == est) ? 1 : 3;
+  }
+  if (stop || j + 1 == m) st[0] = 0;
+}
+
+// Back substitution H y = g on the leading jdone x jdone triangle.
+__global__ void k_gmres_solve_y(const int* st, cd64* S, int m) {
+  const int jd = st[2];
+  if (jd == 0) return;
+  cd64* H = S;
+  cd64* g = S + (m + 1) * m + 2 * m;
+  cd64* y = g + (m + 1);
+  for (int i = jd - 1; i >= 0; --i) {
+    cd64 s = g[i];
+    for (int k = i + 1; k < jd; ++k) {
+      cd64 t = cmul(H[i * m + k], y[k]);
+      s = csub(s, t);
+    }
+    const cd64 d = H[i * m + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    y[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
+  }
+}
+
+__global__ void k_gmres_cycle_end(int* st) {
+  st[2] = 0;
+  st[0] = 0;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R>
+void launch_dot(const cplx<R>* a, long astride, int m, const int* m_dev, const cplx<R>* b, long n, cd64* partial,
+                int mstride, cd64* out, int ostride, int mode, const int* run, hipStream_t st) {
+  int G = red_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial<R>, dim3(G), dim3(kBlock), 0, st, a, astride, m, m_dev, b, n, partial, mstride, run);
+  WCMG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, m, m_dev, mstride, out, ostride, mode, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+int reduction_blocks(long n) { return red_blocks(n); }
+
+void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out, int ostride, int mode,
+                       const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, m, (const int*)nullptr, mstride, out, ostride,
+                     mode, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_multi_axpy(cplx<R>* y, const cplx<R>* V, long vstride, int m, const int* m_dev, const cd64* coef,
+                       int cstride, double sign, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_axpy<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, V, vstride, m, m_dev, coef, cstride,
+                     sign, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, x, (R)a, (R)b, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_scale_inv_norm(cplx<R>* y, const cplx<R>* x, const cd64* nrm2, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_inv_norm<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, x, nrm2, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_zero(cplx<R>* y, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_sub(cplx<R>* y, const cplx<R>* a, const cplx<R>* b, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, a, b, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename Ti, typename To>
+void launch_convert(const cplx<Ti>* x, cplx<To>* y, long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Ti, To>), dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
+                           const int* run, hipStream_t st) {
+  int G = red_blocks(n);
+  hipLaunchKernelGGL(k_dot2_partial<R>, dim3(G), dim3(kBlock), 0, st, p, r, n, partial, run);
+  WCMG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, 2, (const int*)nullptr, 2, dots, 1, 0, run);
+  WCMG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_mr_update<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, r, p, dots, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+#define INST_BLAS(R)                                                                                                \
+  template void launch_dot<R>(const cplx<R>*, long, int, const int*, const cplx<R>*, long, cd64*, int, cd64*, int,   \
+                              int, const int*, hipStream_t);                                                        \
+  template void launch_multi_axpy<R>(cplx<R>*, const cplx<R>*, long, int, const int*, const cd64*, int, double, long, \
+                                     const int*, hipStream_t);                                                      \
+  template void launch_axpby<R>(cplx<R>*, const cplx<R>*, double, double, long, const int*, hipStream_t);            \
+  template void launch_zero<R>(cplx<R>*, long, const int*, hipStream_t);                                             \
+  template void launch_sub<R>(cplx<R>*, const cplx<R>*, const cplx<R>*, long, const int*, hipStream_t);              \
+  template void launch_scale_inv_norm<R>(cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t);      \
+  template void launch_mr_dots_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, cd64*, cd64*, const int*,         \
+                                         hipStream_t);
+INST_BLAS(double)
+INST_BLAS(float)
+template void launch_convert<double, float>(const cd64*, cf32*, long, const int*, hipStream_t);
+template void launch_convert<float, double>(const cf32*, cd64*, long, const int*, hipStream_t);
+template void launch_convert<double, double>(const cd64*, cd64*, long, const int*, hipStream_t);
+template void launch_convert<float, float>(const cf32*, cf32*, long, const int*, hipStream_t);
+
+void launch_gmres_init(int* st_, const int* parent, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(1), 0, st, st_, parent);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_gmres_cycle_start(int* st_, cd64* S, int m, double tol, int limit, int fixed, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_cycle_start, dim3(1), dim3(1), 0, st, st_, S, m, tol, limit, fixed);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit, int fixed, int stop_on_est,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, st, st_, S, m, j, tol, limit, fixed, stop_on_est);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_solve_y, dim3(1), dim3(1), 0, st, st_, S, m);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_gmres_cycle_end(int* st_, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_cycle_end, dim3(1), dim3(1), 0, st, st_);
+  WCMG_CHECK_LAUNCH();
+}
+
+}  // namespace wcmg

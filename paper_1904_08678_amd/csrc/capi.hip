@@ -1,0 +1,494 @@
+// extern "C" boundary of the wcmg library (declared in include/wcmg.h).
+// Every entry point converts internal exceptions into a wcmg_status and keeps
+// the message for wcmg_last_error.
+#include <chrono>
+#include <cstring>
+
+#include "engine.h"
+
+using namespace wcmg;
+
+struct wcmg_ctx {
+  std::unique_ptr<Context> c;
+  std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+namespace {
+
+template <typename F>
+int guarded(wcmg_ctx* h, F&& f) {
+  if (!h || !h->c) return WCMG_ERR_ARG;
+  try {
+    f(*h->c);
+    h->err.clear();
+    return WCMG_OK;
+  } catch (const Error& e) {
+    h->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return WCMG_ERR_HIP;
+  }
+}
+
+void check_level(const Context& c, int level, bool need_coarse) {
+  require(level >= 0 && level < c.nlev, WCMG_ERR_ARG, "level out of range");
+  if (need_coarse) require(level + 1 < c.nlev, WCMG_ERR_ARG, "level has no coarser level");
+}
+
+void check_prec(int prec, bool allow_bf16) {
+  require(prec == WCMG_F64 || prec == WCMG_F32 || (allow_bf16 && prec == WCMG_BF16), WCMG_ERR_ARG,
+          "unsupported precision");
+}
+
+}  // namespace
+
+extern "C" {
+
+void wcmg_default_params(wcmg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dims[0] = p->dims[1] = p->dims[2] = p->dims[3] = 8;
+  p->m0 = -0.05;
+  p->c_sw = 1.0;
+  p->antiperiodic_t = 1;
+  p->n_levels = 2;
+  for (int l = 0; l < 3; ++l)
+    for (int m = 0; m < 4; ++m) p->block[l][m] = 4;
+  p->n_vec[0] = p->n_vec[1] = p->n_vec[2] = 12;
+  p->relax_sweeps = 20;
+  p->refine_iters = 0;
+  p->post_smooth = 4;
+  p->coarse_restart = 20;
+  p->coarse_maxit = 100;
+  p->coarse_fixed_iters = 0;
+  p->coarse_tol = 0.05;
+  p->kcycle = 0;
+  p->kcycle_maxit = 5;
+  p->kcycle_tol = 0.1;
+  p->outer_restart = 20;
+  p->outer_maxit = 1000;
+  p->outer_tol = 1e-10;
+  p->cycle_prec = WCMG_F64;
+  p->coarse_store_prec = WCMG_F64;
+  p->setup_prec = WCMG_F64;
+}
+
+int wcmg_create(const wcmg_params* p, void* stream, wcmg_ctx** out) {
+  if (!p || !out) return WCMG_ERR_ARG;
+  *out = nullptr;
+  wcmg_ctx* h = new wcmg_ctx();
+  try {
+    h->c.reset(new Context(*p, (hipStream_t)stream));
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    delete h;
+    return e.code;
+  }
+  *out = h;
+  return WCMG_OK;
+}
+
+int wcmg_destroy(wcmg_ctx* ctx) {
+  if (!ctx) return WCMG_ERR_ARG;
+  if (ctx->c) (void)hipStreamSynchronize(ctx->c->stream);
+  delete ctx;
+  return WCMG_OK;
+}
+
+const char* wcmg_last_error(const wcmg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+int wcmg_set_gauge(wcmg_ctx* ctx, const void* U) {
+  return guarded(ctx, [&](Context& c) {
+    require(U != nullptr, WCMG_ERR_ARG, "null gauge field");
+    c.set_gauge((const cd64*)U);
+  });
+}
+
+int wcmg_set_clover(wcmg_ctx* ctx, const void* blocks) {
+  return guarded(ctx, [&](Context& c) {
+    require(c.gauge_set, WCMG_ERR_STATE, "set the gauge field first");
+    if (blocks) c.set_clover((const cd64*)blocks);
+    else c.set_gauge(c.U_lex.as<cd64>());
+  });
+}
+
+int wcmg_get_clover(wcmg_ctx* ctx, void* blocks) {
+  return guarded(ctx, [&](Context& c) {
+    require(c.gauge_set && blocks, WCMG_ERR_STATE, "no clover term");
+    WCMG_HIP(hipMemcpyAsync(blocks, c.clover_lex.p, c.geo[0].V * 72 * sizeof(cd64), hipMemcpyDeviceToDevice,
+                            c.stream));
+    c.sync();
+  });
+}
+
+static void level_vectors_in(Context& c, int level, const cd64* src, cd64* dst, int nv) {
+  const LevelGeom& G = c.geo[level];
+  if (level == 0) launch_pack_fermion<double, double>(src, c.perm0.as<int>(), G.V, nv, dst, c.stream);
+  else WCMG_HIP(hipMemcpyAsync(dst, src, (size_t)nv * G.n() * sizeof(cd64), hipMemcpyDeviceToDevice, c.stream));
+}
+static void level_vectors_out(Context& c, int level, const cd64* src, cd64* dst, int nv) {
+  const LevelGeom& G = c.geo[level];
+  if (level == 0) launch_unpack_fermion<double, double>(src, c.perm0.as<int>(), G.V, nv, dst, c.stream);
+  else WCMG_HIP(hipMemcpyAsync(dst, src, (size_t)nv * G.n() * sizeof(cd64), hipMemcpyDeviceToDevice, c.stream));
+}
+
+int wcmg_set_null_vectors(wcmg_ctx* ctx, int level, const void* v, int nv) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    require(v && nv == c.tr[level].nv, WCMG_ERR_ARG, "expected n_vec start vectors");
+    level_vectors_in(c, level, (const cd64*)v, c.tr[level].start64.as<cd64>(), nv);
+    c.tr[level].has_start = true;
+    c.sync();
+  });
+}
+
+int wcmg_get_null_vectors(wcmg_ctx* ctx, int level, void* v) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    require(c.tr[level].built && v, WCMG_ERR_STATE, "near-null vectors not built");
+    level_vectors_out(c, level, c.tr[level].vecs64.as<cd64>(), (cd64*)v, c.tr[level].nv);
+    c.sync();
+  });
+}
+
+int wcmg_get_prolongator(wcmg_ctx* ctx, int level, void* v) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    require(c.tr[level].built && v, WCMG_ERR_STATE, "prolongator not built");
+    level_vectors_out(c, level, c.tr[level].P64.as<cd64>(), (cd64*)v, c.tr[level].nv);
+    c.sync();
+  });
+}
+
+int wcmg_setup(wcmg_ctx* ctx) {
+  return guarded(ctx, [&](Context& c) { c.setup_all(); });
+}
+
+int wcmg_refine(wcmg_ctx* ctx, int iterations) {
+  return guarded(ctx, [&](Context& c) {
+    require(c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
+    require(iterations >= 0, WCMG_ERR_ARG, "negative iteration count");
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < iterations; ++i) c.refine_iteration(0);
+    c.sync();
+    c.timers[4] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    require(c.gauge_set && v, WCMG_ERR_STATE, "gauge field not set");
+    for (int l = 0; l < level; ++l) require(c.tr[l].built, WCMG_ERR_STATE, "finer levels not built");
+    level_vectors_in(c, level, (const cd64*)v, c.tr[level].vecs64.as<cd64>(), c.tr[level].nv);
+    c.rebuild(level);
+    c.regalerkin_below(level);
+  });
+}
+
+int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    require(coarse_host && offset_host, WCMG_ERR_ARG, "null output");
+    const Transfer& T = c.tr[level];
+    std::memcpy(coarse_host, T.agg_host.data(), T.agg_host.size() * sizeof(int32_t));
+    std::memcpy(offset_host, T.off_host.data(), T.off_host.size() * sizeof(int32_t));
+  });
+}
+
+int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks) {
+  return guarded(ctx, [&](Context& c) {
+    require(level >= 1 && level < c.nlev && blocks, WCMG_ERR_ARG, "level must name a coarse level");
+    CoarseOp& C = *c.cop[level - 1];
+    WCMG_HIP(hipMemcpyAsync(blocks, C.M64.p, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    c.sync();
+  });
+}
+
+int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks) {
+  return guarded(ctx, [&](Context& c) {
+    require(level >= 1 && level < c.nlev && blocks, WCMG_ERR_ARG, "level must name a coarse level");
+    CoarseOp& C = *c.cop[level - 1];
+    WCMG_HIP(hipMemcpyAsync(C.M64.p, blocks, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    for (int q = 0; q < 3; ++q) C.fresh[q] = false;
+    C.refresh(WCMG_F64, c.stream);
+    C.refresh(WCMG_F32, c.stream);
+    if (C.nb % 4 == 0) C.refresh(WCMG_BF16, c.stream);
+    c.sync();
+  });
+}
+
+int wcmg_apply_D(wcmg_ctx* ctx, int level, const void* in, void* out, int nrhs, int prec) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, false);
+    check_prec(prec, level > 0);
+    require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    if (level == 0) {
+      require(c.gauge_set, WCMG_ERR_STATE, "gauge field not set");
+      const long V = c.geo[0].V, nn = c.n(0);
+      if (prec == WCMG_F64) {
+        cd64* a = c.buf<cd64>("abi_a64", nn * nrhs);
+        cd64* b = c.buf<cd64>("abi_b64", nn * nrhs);
+        launch_pack_fermion<double, double>((const cd64*)in, c.perm0.as<int>(), V, nrhs, a, c.stream);
+        c.apply_op<double>(0, a, b, nrhs, nullptr);
+        launch_unpack_fermion<double, double>(b, c.perm0.as<int>(), V, nrhs, (cd64*)out, c.stream);
+      } else {
+        cf32* a = c.buf<cf32>("abi_a32", nn * nrhs);
+        cf32* b = c.buf<cf32>("abi_b32", nn * nrhs);
+        launch_pack_fermion<float, float>((const cf32*)in, c.perm0.as<int>(), V, nrhs, a, c.stream);
+        c.apply_op<float>(0, a, b, nrhs, nullptr);
+        launch_unpack_fermion<float, float>(b, c.perm0.as<int>(), V, nrhs, (cf32*)out, c.stream);
+      }
+    } else {
+      CoarseOp& C = *c.cop[level - 1];
+      require(C.fresh[WCMG_F64], WCMG_ERR_STATE, "coarse operator not built");
+      if (prec != WCMG_F64) C.refresh(prec, c.stream);
+      c.prof.begin("coarse_apply", c.stream);
+      C.apply(prec, in, out, 0x1ff, 0, nrhs, nullptr, c.stream);
+      c.prof.end("coarse_apply", c.stream);
+    }
+    WCMG_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int wcmg_restrict(wcmg_ctx* ctx, int level, const void* fine, void* coarse, int nrhs, int prec) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    check_prec(prec, false);
+    require(fine && coarse && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    require(c.tr[level].built, WCMG_ERR_STATE, "prolongator not built");
+    const long V = c.geo[level].V, nn = c.n(level);
+    if (prec == WCMG_F64) {
+      const cd64* f = (const cd64*)fine;
+      if (level == 0) {
+        cd64* a = c.buf<cd64>("abi_a64", nn * nrhs);
+        launch_pack_fermion<double, double>(f, c.perm0.as<int>(), V, nrhs, a, c.stream);
+        f = a;
+      }
+      c.restrict_<double>(level, f, (cd64*)coarse, nrhs, nullptr);
+    } else {
+      const cf32* f = (const cf32*)fine;
+      if (level == 0) {
+        cf32* a = c.buf<cf32>("abi_a32", nn * nrhs);
+        launch_pack_fermion<float, float>(f, c.perm0.as<int>(), V, nrhs, a, c.stream);
+        f = a;
+      }
+      c.restrict_<float>(level, f, (cf32*)coarse, nrhs, nullptr);
+    }
+    WCMG_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int wcmg_prolong(wcmg_ctx* ctx, int level, const void* coarse, void* fine, int nrhs, int prec) {
+  return guarded(ctx, [&](Context& c) {
+    check_level(c, level, true);
+    check_prec(prec, false);
+    require(fine && coarse && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    require(c.tr[level].built, WCMG_ERR_STATE, "prolongator not built");
+    const long V = c.geo[level].V, nn = c.n(level);
+    if (prec == WCMG_F64) {
+      cd64* f = (cd64*)fine;
+      if (level == 0) f = c.buf<cd64>("abi_b64", nn * nrhs);
+      c.prolong_<double>(level, (const cd64*)coarse, f, 0, nrhs, nullptr);
+      if (level == 0) launch_unpack_fermion<double, double>(f, c.perm0.as<int>(), V, nrhs, (cd64*)fine, c.stream);
+    } else {
+      cf32* f = (cf32*)fine;
+      if (level == 0) f = c.buf<cf32>("abi_b32", nn * nrhs);
+      c.prolong_<float>(level, (const cf32*)coarse, f, 0, nrhs, nullptr);
+      if (level == 0) launch_unpack_fermion<float, float>(f, c.perm0.as<int>(), V, nrhs, (cf32*)fine, c.stream);
+    }
+    WCMG_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+int wcmg_cycle(wcmg_ctx* ctx, const void* r, void* x) {
+  return guarded(ctx, [&](Context& c) {
+    require(c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
+    require(c.nlev >= 2, WCMG_ERR_STATE, "no coarse level");
+    require(r && x, WCMG_ERR_ARG, "bad fields");
+    const long V = c.geo[0].V, nn = c.n(0);
+    cd64* a = c.buf<cd64>("cyc_in", nn);
+    cd64* b = c.buf<cd64>("cyc_out", nn);
+    launch_pack_fermion<double, double>((const cd64*)r, c.perm0.as<int>(), V, 1, a, c.stream);
+    c.precondition64(0, a, b, nullptr);
+    launch_unpack_fermion<double, double>(b, c.perm0.as<int>(), V, 1, (cd64*)x, c.stream);
+    c.sync();
+  });
+}
+
+int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info* info) {
+  int status = WCMG_OK;
+  int rc = guarded(ctx, [&](Context& c) {
+    require(c.gauge_set, WCMG_ERR_STATE, "gauge field not set");
+    require(c.nlev == 1 || c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
+    require(b && x && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    const long V = c.geo[0].V, nn = c.n(0);
+    cd64* b64 = c.buf<cd64>("solve_b", nn);
+    cd64* x64 = c.buf<cd64>("solve_x", nn);
+    cd64* r64 = c.buf<cd64>("solve_r", nn);
+    std::function<void(const cd64*, cd64*, const int*)> A = [&c](const cd64* i, cd64* o, const int* rn) {
+      c.apply_op<double>(0, i, o, 1, rn);
+    };
+    std::function<void(const cd64*, cd64*, const int*)> M = [&c](const cd64* i, cd64* o, const int* rn) {
+      if (c.nlev >= 2) c.precondition64(0, i, o, rn);
+      else launch_convert<double, double>(i, o, c.n(0), rn, c.stream);
+    };
+    for (int k = 0; k < nrhs; ++k) {
+      auto t0 = std::chrono::steady_clock::now();
+      c.coarse_iters = 0;
+      c.cycles = 0;
+      launch_pack_fermion<double, double>((const cd64*)b + k * nn, c.perm0.as<int>(), V, 1, b64, c.stream);
+      launch_pack_fermion<double, double>((const cd64*)x + k * nn, c.perm0.as<int>(), V, 1, x64, c.stream);
+      GmresState& G = c.gmres_state("outer", c.p.outer_restart, nn, 0, true);
+      int its = c.gmres<double>(G, A, &M, b64, x64, false, c.p.outer_restart, c.p.outer_maxit, c.p.outer_tol, 0,
+                                false, nullptr, 1);
+      // true residual in FP64
+      c.apply_op<double>(0, x64, r64, 1, nullptr);
+      launch_sub<double>(r64, b64, r64, nn, nullptr, c.stream);
+      double rr = c.norm2_host<double>(r64, nn);
+      double bb = c.norm2_host<double>(b64, nn);
+      launch_unpack_fermion<double, double>(x64, c.perm0.as<int>(), V, 1, (cd64*)x + k * nn, c.stream);
+      c.sync();
+      double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      c.timers[5] = dt;
+      bool conv = rel <= c.p.outer_tol;
+      if (!(rel == rel)) status = WCMG_ERR_NAN;
+      else if (!conv && status == WCMG_OK) status = WCMG_ERR_NOCONV;
+      if (info) {
+        info[k].outer_iters = its;
+        info[k].converged = conv ? 1 : 0;
+        info[k].true_rel_res = rel;
+        info[k].t_solve_s = dt;
+        info[k].coarse_iters = c.coarse_iters;
+        info[k].cycles = c.cycles;
+      }
+    }
+  });
+  if (rc != WCMG_OK) return rc;
+  if (status != WCMG_OK) ctx->err = status == WCMG_ERR_NAN ? "NaN in residual" : "solver did not converge";
+  return status;
+}
+
+int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n) {
+  return guarded(ctx, [&](Context& c) {
+    require(out_host != nullptr && n >= 0, WCMG_ERR_ARG, "bad output");
+    for (int i = 0; i < n && i < 8; ++i) out_host[i] = c.timers[i];
+  });
+}
+
+int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable) {
+  return guarded(ctx, [&](Context& c) {
+    require(family != nullptr, WCMG_ERR_ARG, "null family");
+    c.prof.enable(family, enable != 0);
+  });
+}
+
+int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms) {
+  return guarded(ctx, [&](Context& c) {
+    require(family && launches && total_ms, WCMG_ERR_ARG, "null argument");
+    c.prof.stats(family, launches, total_ms);
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- standalone coarse operator
+struct wcmg_coarse {
+  CoarseOp op;
+  int store = WCMG_F32;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+template <typename F>
+static int guarded_c(wcmg_coarse* h, F&& f) {
+  if (!h) return WCMG_ERR_ARG;
+  try {
+    f(*h);
+    h->err.clear();
+    return WCMG_OK;
+  } catch (const Error& e) {
+    h->err = e.what();
+    return e.code;
+  }
+}
+
+extern "C" {
+
+int wcmg_coarse_create(const int32_t dims[4], int nb, int store_prec, void* stream, wcmg_coarse** out) {
+  if (!dims || !out) return WCMG_ERR_ARG;
+  *out = nullptr;
+  for (int m = 0; m < 4; ++m)
+    if (dims[m] < 2) return WCMG_ERR_DIMS;
+  if (nb < 2 || nb % 2 || (store_prec == WCMG_BF16 && nb % 4)) return WCMG_ERR_ARG;
+  if (store_prec < 0 || store_prec > 2) return WCMG_ERR_ARG;
+  wcmg_coarse* h = new wcmg_coarse();
+  try {
+    int L[4] = {dims[0], dims[1], dims[2], dims[3]};
+    h->op.init_geometry(L, nb, (hipStream_t)stream);
+    h->store = store_prec;
+    h->stream = (hipStream_t)stream;
+  } catch (const Error& e) {
+    delete h;
+    return e.code;
+  }
+  *out = h;
+  return WCMG_OK;
+}
+
+int wcmg_coarse_destroy(wcmg_coarse* op) {
+  if (!op) return WCMG_ERR_ARG;
+  (void)hipStreamSynchronize(op->stream);
+  delete op;
+  return WCMG_OK;
+}
+
+int wcmg_coarse_set(wcmg_coarse* h, const void* blocks, int src_prec) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(blocks && (src_prec == WCMG_F64 || src_prec == WCMG_F32), WCMG_ERR_ARG, "bad blocks");
+    const long n = o.op.V * 9L * o.op.nb * o.op.nb;
+    if (src_prec == WCMG_F64)
+      WCMG_HIP(hipMemcpyAsync(o.op.M64.p, blocks, n * sizeof(cd64), hipMemcpyDeviceToDevice, o.stream));
+    else
+      launch_c64_to_c128((const cf32*)blocks, o.op.M64.as<cd64>(), n, o.stream);
+    for (int q = 0; q < 3; ++q) o.op.fresh[q] = false;
+    o.op.refresh(o.store, o.stream);
+    WCMG_HIP(hipStreamSynchronize(o.stream));
+    // the canonical master is only needed to build the device layout
+    o.op.M64.release();
+    o.op.M64.alloc(16);
+  });
+}
+
+int wcmg_coarse_apply(wcmg_coarse* h, const void* in, void* out, int nrhs) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    o.op.apply(o.store, in, out, 0x1ff, 0, nrhs, nullptr, o.stream);
+  });
+}
+
+int wcmg_coarse_time(wcmg_coarse* h, const void* in, void* out, int nrhs, int reps, double* avg_ms) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(in && out && nrhs >= 1 && reps >= 1 && avg_ms, WCMG_ERR_ARG, "bad arguments");
+    hipEvent_t a, b;
+    WCMG_HIP(hipEventCreate(&a));
+    WCMG_HIP(hipEventCreate(&b));
+    WCMG_HIP(hipEventRecord(a, o.stream));
+    for (int i = 0; i < reps; ++i) o.op.apply(o.store, in, out, 0x1ff, 0, nrhs, nullptr, o.stream);
+    WCMG_HIP(hipEventRecord(b, o.stream));
+    WCMG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    WCMG_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
+  });
+}
+
+const char* wcmg_coarse_last_error(const wcmg_coarse* op) { return op ? op->err.c_str() : "null operator"; }
+
+}  // extern "C"

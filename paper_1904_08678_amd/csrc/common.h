@@ -1,0 +1,149 @@
+// Shared device helpers of the wcmg HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "wcmg.h"
+
+namespace wcmg {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define WCMG_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::wcmg::Error(e_ == hipErrorOutOfMemory ? WCMG_ERR_NOMEM : WCMG_ERR_HIP,   \
+                          std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define WCMG_CHECK_LAUNCH() WCMG_HIP(hipGetLastError())
+
+inline void require(bool ok, int code, const std::string& msg) {
+  if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------- complex
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+  R re, im;
+};
+typedef cplx<double> cd64;
+typedef cplx<float> cf32;
+
+template <typename R>
+__host__ __device__ inline cplx<R> mkc(R a, R b) {
+  cplx<R> c;
+  c.re = a;
+  c.im = b;
+  return c;
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cadd(cplx<R> a, cplx<R> b) { return mkc(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ inline cplx<R> csub(cplx<R> a, cplx<R> b) { return mkc(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ inline cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return mkc(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// acc += a * b
+template <typename R>
+__host__ __device__ inline void cfma(cplx<R>& acc, cplx<R> a, cplx<R> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += conj(a) * b
+template <typename R>
+__host__ __device__ inline void cfmac(cplx<R>& acc, cplx<R> a, cplx<R> b) {
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cscale(R s, cplx<R> a) { return mkc(s * a.re, s * a.im); }
+// i * a
+template <typename R>
+__host__ __device__ inline cplx<R> ci(cplx<R> a) { return mkc(-a.im, a.re); }
+template <typename R>
+__host__ __device__ inline cplx<R> cneg(cplx<R> a) { return mkc(-a.re, -a.im); }
+template <typename R>
+__host__ __device__ inline cplx<R> cconj(cplx<R> a) { return mkc(a.re, -a.im); }
+
+template <typename R, typename S>
+__host__ __device__ inline cplx<R> ccast(cplx<S> a) { return mkc((R)a.re, (R)a.im); }
+
+// ---------------------------------------------------------------- bf16 (round to nearest even)
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// ---------------------------------------------------------------- device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() {}
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    if (n == bytes && p) return;
+    release();
+    if (n == 0) return;
+    WCMG_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <typename T>
+  T* as() const { return (T*)p; }
+};
+
+// precision helpers
+inline size_t cbytes(int prec) { return prec == WCMG_F64 ? 16 : 8; }
+
+// ---------------------------------------------------------------- launch helpers
+constexpr int kBlock = 256;
+inline unsigned nblocks(long n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }
+
+// Site geometry of one level as the kernels see it.
+//   layout SoA (level 0): element (site s, component k) at k * V + s
+//   layout AoS (levels >= 1): element at s * ns + k
+struct FieldLayout {
+  long V;
+  int ns;
+  bool soa;
+  __host__ __device__ long at(long s, int k) const { return soa ? (long)k * V + s : s * ns + k; }
+  __host__ __device__ long size() const { return V * ns; }
+};
+
+}  // namespace wcmg

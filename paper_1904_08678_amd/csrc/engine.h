@@ -1,0 +1,144 @@
+// Host-side multigrid engine: levels, operators, setup, solvers.
+#pragma once
+
+#include <array>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace wcmg {
+
+// HIP-event timing of kernel families on the context stream.
+struct Profiler {
+  struct Family {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+  };
+  std::map<std::string, Family> fam;
+  ~Profiler();
+  void enable(const std::string& f, bool on);
+  void begin(const char* f, hipStream_t st);
+  void end(const char* f, hipStream_t st);
+  void stats(const std::string& f, int64_t* launches, double* ms);
+  size_t pending_ = 0;
+};
+
+// Geometry of one level as laid out on the device.
+struct LevelGeom {
+  int L[4] = {0, 0, 0, 0};
+  long V = 0;
+  int ns = 0;
+  FieldLayout lay{};
+  DevBuf nbr;                  // int32 [8][V] in device site order
+  std::vector<int> perm;       // device site -> lexicographic site (identity for coarse levels)
+  long n() const { return V * ns; }
+};
+
+// Intergrid transfer from level l to l+1 (Sec. 2.1 Aggregation).
+struct Transfer {
+  int block[4] = {1, 1, 1, 1};
+  int A = 1;
+  long Vc = 0;
+  int nv = 0;
+  int nb = 0;
+  DevBuf agg_sites;  // int32 [Vc][A]: device site of level l for (c, o)
+  DevBuf coarse_of;  // int32 [V_l]
+  std::vector<int> agg_host, off_host;  // per lexicographic site of level l
+  DevBuf start64, vecs64, P64, P32;     // [nv][n_l]
+  bool has_start = false, built = false;
+};
+
+// Coarse operator of one level: canonical FP64 master plus device layouts.
+struct CoarseOp {
+  int L[4] = {0, 0, 0, 0};
+  long V = 0;
+  int nb = 0;
+  DevBuf nbr;   // int32 [8][V]
+  DevBuf M64;   // canonical [V][9][nb][nb]
+  DevBuf dev[3];
+  bool fresh[3] = {false, false, false};
+  void init_geometry(const int Lc[4], int nb_, hipStream_t st);
+  void refresh(int prec, hipStream_t st);  // canonical -> device layout of prec
+  void apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
+};
+
+struct GmresState {
+  int m = 0;
+  long n = 0;
+  int prec = 0;  // 0: double, 1: float
+  bool flex = false;
+  DevBuf V, Z, w, r, S, st;
+};
+
+struct Context {
+  wcmg_params p{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int nlev = 1;
+  std::vector<LevelGeom> geo;
+  std::vector<Transfer> tr;
+  std::vector<std::unique_ptr<CoarseOp>> cop;  // cop[l-1] is the operator of level l
+  // fine operator
+  DevBuf perm0;                 // int32 device site -> lexicographic
+  DevBuf U_lex, clover_lex;     // canonical copies (FP64)
+  DevBuf U64, U32, clov64, clov32;
+  bool gauge_set = false, setup_done = false;
+  // workspaces
+  std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  std::map<std::string, std::unique_ptr<GmresState>> gm;
+  DevBuf partial, scratch64;
+  int* pinned = nullptr;  // host-pinned status words
+  double timers[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t coarse_iters = 0, cycles = 0;
+  Profiler prof;
+
+  Context(const wcmg_params& prm, hipStream_t s);
+  ~Context();
+
+  template <typename T>
+  T* buf(const std::string& tag, long count);
+  GmresState& gmres_state(const std::string& tag, int m, long n, int prec, bool flex);
+
+  long n(int l) const { return geo[l].n(); }
+
+  // operators
+  template <typename R>
+  void apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms = 0x1ff);
+  int store_prec_for(int l, bool single) const;
+
+  // building blocks
+  void set_gauge(const cd64* U);
+  void set_clover(const cd64* blocks);
+  void pack_clover();
+  void initial_setup(int l);
+  void rebuild(int l);
+  void galerkin(int l);
+  void regalerkin_below(int l);
+  void refine_iteration(int l);
+  void setup_all();
+
+  template <typename R>
+  void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run);
+  template <typename R>
+  void cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run);
+  void precondition64(int l, const cd64* r, cd64* x, const int* run);
+  template <typename R>
+  int gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<R>*, const int*)>& A,
+            const std::function<void(const cplx<R>*, cplx<R>*, const int*)>* M, const cplx<R>* b, cplx<R>* x,
+            bool x0_zero, int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent,
+            int check_every);
+  template <typename R>
+  void restrict_(int l, const cplx<R>* fine, cplx<R>* coarse, int nrhs, const int* run);
+  template <typename R>
+  void prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumulate, int nrhs, const int* run);
+  template <typename R>
+  double norm2_host(const cplx<R>* v, long n);
+  void sync();
+};
+
+}  // namespace wcmg

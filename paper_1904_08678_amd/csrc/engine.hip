@@ -1,0 +1,626 @@
+// Multigrid engine: geometry, operators, setup (initial and iterative),
+// MR smoother, (flexible) GMRES, V- and K-cycles (Sec. 2.1 of the paper).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+namespace wcmg {
+
+// ---------------------------------------------------------------- profiler
+Profiler::~Profiler() {
+  for (auto& kv : fam)
+    for (auto& e : kv.second.ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+}
+void Profiler::enable(const std::string& f, bool on) { fam[f].on = on; }
+void Profiler::begin(const char* f, hipStream_t st) {
+  auto it = fam.find(f);
+  if (it == fam.end() || !it->second.on) return;
+  Family& F = it->second;
+  if (F.used == F.ev.size()) {
+    hipEvent_t a, b;
+    WCMG_HIP(hipEventCreate(&a));
+    WCMG_HIP(hipEventCreate(&b));
+    F.ev.push_back({a, b});
+  }
+  WCMG_HIP(hipEventRecord(F.ev[F.used].first, st));
+}
+void Profiler::end(const char* f, hipStream_t st) {
+  auto it = fam.find(f);
+  if (it == fam.end() || !it->second.on) return;
+  Family& F = it->second;
+  WCMG_HIP(hipEventRecord(F.ev[F.used].second, st));
+  F.used++;
+}
+void Profiler::stats(const std::string& f, int64_t* launches, double* ms) {
+  auto it = fam.find(f);
+  *launches = 0;
+  *ms = 0.0;
+  if (it == fam.end()) return;
+  Family& F = it->second;
+  for (size_t i = 0; i < F.used; ++i) {
+    WCMG_HIP(hipEventSynchronize(F.ev[i].second));
+    float t = 0.f;
+    WCMG_HIP(hipEventElapsedTime(&t, F.ev[i].first, F.ev[i].second));
+    *ms += t;
+  }
+  *launches = (int64_t)F.used;
+  F.used = 0;
+}
+
+// ---------------------------------------------------------------- geometry helpers
+namespace {
+long vol4(const int L[4]) { return (long)L[0] * L[1] * L[2] * L[3]; }
+void lex_coords(long i, const int L[4], int x[4]) {
+  for (int m = 0; m < 4; ++m) {
+    x[m] = (int)(i % L[m]);
+    i /= L[m];
+  }
+}
+long lex_index(const int x[4], const int L[4]) { return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3])); }
+long lex_neighbour(long i, const int L[4], int d) {
+  int x[4];
+  lex_coords(i, L, x);
+  int mu = (d - 1) / 2, step = ((d - 1) % 2 == 0) ? 1 : -1;
+  x[mu] = (x[mu] + step + L[mu]) % L[mu];
+  return lex_index(x, L);
+}
+void upload(DevBuf& b, const std::vector<int>& v) {
+  b.alloc(v.size() * sizeof(int));
+  WCMG_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+}  // namespace
+
+void CoarseOp::init_geometry(const int Lc[4], int nb_, hipStream_t) {
+  for (int m = 0; m < 4; ++m) L[m] = Lc[m];
+  V = vol4(L);
+  nb = nb_;
+  std::vector<int> nb_host(8 * V);
+  for (int d = 1; d <= 8; ++d)
+    for (long s = 0; s < V; ++s) nb_host[(d - 1) * V + s] = (int)lex_neighbour(s, L, d);
+  upload(nbr, nb_host);
+  M64.alloc((size_t)V * 9 * nb * nb * sizeof(cd64));
+}
+
+void CoarseOp::refresh(int prec, hipStream_t st) {
+  if (fresh[prec]) return;
+  dev[prec].alloc(device_block_bytes(V, nb, prec));
+  launch_blocks_to_device(M64.as<cd64>(), V, nb, prec, dev[prec].p, st);
+  fresh[prec] = true;
+}
+
+void CoarseOp::apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run,
+                     hipStream_t st) {
+  require(fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  launch_coarse_apply(prec, dev[prec].p, in, out, nbr.as<int>(), V, nb, dmask, accumulate, nrhs, run, st);
+}
+
+// ---------------------------------------------------------------- context
+Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
+  nlev = p.n_levels;
+  require(nlev >= 1 && nlev <= 3, WCMG_ERR_ARG, "n_levels must be 1, 2 or 3");
+  for (int m = 0; m < 4; ++m) require(p.dims[m] >= 2, WCMG_ERR_DIMS, "lattice extents must be >= 2");
+  require(p.cycle_prec == WCMG_F64 || p.cycle_prec == WCMG_F32, WCMG_ERR_ARG, "cycle_prec must be F64 or F32");
+  require(p.setup_prec == WCMG_F64 || p.setup_prec == WCMG_F32, WCMG_ERR_ARG, "setup_prec must be F64 or F32");
+  require(p.coarse_store_prec >= 0 && p.coarse_store_prec <= 2, WCMG_ERR_ARG, "bad coarse_store_prec");
+  require(p.outer_restart >= 1 && p.outer_restart <= 40 && p.coarse_restart >= 1 && p.coarse_restart <= 40 &&
+              p.kcycle_maxit >= 1 && p.kcycle_maxit <= 40,
+          WCMG_ERR_ARG, "restart lengths must lie in 1..40");
+  geo.resize(nlev);
+  tr.resize(nlev - 1);
+  // level extents
+  int L[3][4];
+  for (int m = 0; m < 4; ++m) L[0][m] = p.dims[m];
+  for (int l = 0; l + 1 < nlev; ++l) {
+    for (int m = 0; m < 4; ++m) {
+      require(p.block[l][m] >= 1 && L[l][m] % p.block[l][m] == 0, WCMG_ERR_DIMS,
+              "block does not divide the lattice at level " + std::to_string(l));
+      L[l + 1][m] = L[l][m] / p.block[l][m];
+      require(L[l + 1][m] >= 2, WCMG_ERR_DIMS, "coarse lattice extent below 2 at level " + std::to_string(l + 1));
+    }
+    require(p.n_vec[l] >= 1 && supported_nb(2 * p.n_vec[l]), WCMG_ERR_ARG,
+            "unsupported number of near-null vectors at level " + std::to_string(l));
+  }
+  for (int l = 0; l < nlev; ++l) {
+    LevelGeom& G = geo[l];
+    for (int m = 0; m < 4; ++m) G.L[m] = L[l][m];
+    G.V = vol4(G.L);
+    G.ns = l == 0 ? 12 : 2 * p.n_vec[l - 1];
+    G.lay.V = G.V;
+    G.lay.ns = G.ns;
+    G.lay.soa = (l == 0);
+  }
+  // device order of level 0: aggregate-major under block[0] (Sec. 3: the fine
+  // lattice linearised per aggregate); lexicographic without multigrid.
+  {
+    LevelGeom& G = geo[0];
+    int b[4] = {1, 1, 1, 1};
+    if (nlev > 1)
+      for (int m = 0; m < 4; ++m) b[m] = p.block[0][m];
+    int Lc[4];
+    for (int m = 0; m < 4; ++m) Lc[m] = G.L[m] / b[m];
+    const int A = b[0] * b[1] * b[2] * b[3];
+    G.perm.assign(G.V, 0);
+    std::vector<int> iperm(G.V);
+    for (long i = 0; i < G.V; ++i) {
+      int x[4], cx[4], ox[4];
+      lex_coords(i, G.L, x);
+      for (int m = 0; m < 4; ++m) {
+        cx[m] = x[m] / b[m];
+        ox[m] = x[m] % b[m];
+      }
+      long c = lex_index(cx, Lc);
+      long o = ox[0] + (long)b[0] * (ox[1] + (long)b[1] * (ox[2] + (long)b[2] * ox[3]));
+      long s = c * A + o;
+      G.perm[s] = (int)i;
+      iperm[i] = (int)s;
+    }
+    std::vector<int> nb_host(8 * G.V);
+    for (int d = 1; d <= 8; ++d)
+      for (long s = 0; s < G.V; ++s) nb_host[(d - 1) * G.V + s] = iperm[lex_neighbour(G.perm[s], G.L, d)];
+    upload(G.nbr, nb_host);
+    upload(perm0, G.perm);
+  }
+  for (int l = 1; l < nlev; ++l) {
+    LevelGeom& G = geo[l];
+    G.perm.resize(G.V);
+    for (long s = 0; s < G.V; ++s) G.perm[s] = (int)s;
+    cop.emplace_back(new CoarseOp());
+    cop.back()->init_geometry(G.L, G.ns, stream);
+    // coarse level vectors and operator share the lexicographic neighbour table
+  }
+  // transfers
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Transfer& T = tr[l];
+    LevelGeom& G = geo[l];
+    for (int m = 0; m < 4; ++m) T.block[m] = p.block[l][m];
+    T.A = T.block[0] * T.block[1] * T.block[2] * T.block[3];
+    T.Vc = geo[l + 1].V;
+    T.nv = p.n_vec[l];
+    T.nb = 2 * T.nv;
+    std::vector<int> agg_sites(T.Vc * T.A), coarse_of(G.V);
+    T.agg_host.assign(G.V, 0);
+    T.off_host.assign(G.V, 0);
+    std::vector<int> iperm(G.V);
+    for (long s = 0; s < G.V; ++s) iperm[G.perm[s]] = (int)s;
+    for (long i = 0; i < G.V; ++i) {
+      int x[4], cx[4], ox[4];
+      lex_coords(i, G.L, x);
+      for (int m = 0; m < 4; ++m) {
+        cx[m] = x[m] / T.block[m];
+        ox[m] = x[m] % T.block[m];
+      }
+      long c = lex_index(cx, geo[l + 1].L);
+      long o = ox[0] + (long)T.block[0] * (ox[1] + (long)T.block[1] * (ox[2] + (long)T.block[2] * ox[3]));
+      T.agg_host[i] = (int)c;
+      T.off_host[i] = (int)o;
+      agg_sites[c * T.A + o] = iperm[i];
+      coarse_of[iperm[i]] = (int)c;
+    }
+    upload(T.agg_sites, agg_sites);
+    upload(T.coarse_of, coarse_of);
+    const size_t nbytes = (size_t)T.nv * G.n() * sizeof(cd64);
+    T.start64.alloc(nbytes);
+    T.vecs64.alloc(nbytes);
+    T.P64.alloc(nbytes);
+    T.P32.alloc(nbytes / 2);
+  }
+  for (int l = 1; l < nlev; ++l) {
+    // coarse-level geometry for the level operators (neighbour table equals cop's)
+    geo[l].nbr.alloc(8 * geo[l].V * sizeof(int));
+    WCMG_HIP(hipMemcpy(geo[l].nbr.p, cop[l - 1]->nbr.p, 8 * geo[l].V * sizeof(int), hipMemcpyDeviceToDevice));
+  }
+  partial.alloc(kPartialSlots * sizeof(cd64));
+  scratch64.alloc(64 * sizeof(cd64));
+  WCMG_HIP(hipHostMalloc((void**)&pinned, 64 * sizeof(int), hipHostMallocDefault));
+  const long V0 = geo[0].V;
+  U_lex.alloc(V0 * 36 * sizeof(cd64));
+  clover_lex.alloc(V0 * 72 * sizeof(cd64));
+  U64.alloc(V0 * 36 * sizeof(cd64));
+  U32.alloc(V0 * 36 * sizeof(cf32));
+  clov64.alloc(V0 * 72 * sizeof(double));
+  clov32.alloc(V0 * 72 * sizeof(float));
+}
+
+Context::~Context() {
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+template <typename T>
+T* Context::buf(const std::string& tag, long count) {
+  auto& b = ws[tag];
+  if (!b) b.reset(new DevBuf());
+  size_t need = (size_t)count * sizeof(T);
+  if (b->bytes < need) b->alloc(need);
+  return b->as<T>();
+}
+
+GmresState& Context::gmres_state(const std::string& tag, int m, long n, int prec, bool flex) {
+  auto& g = gm[tag];
+  if (!g) g.reset(new GmresState());
+  GmresState& G = *g;
+  if (G.m != m || G.n != n || G.prec != prec || G.flex != flex) {
+    const size_t cb = prec == 0 ? sizeof(cd64) : sizeof(cf32);
+    G.m = m;
+    G.n = n;
+    G.prec = prec;
+    G.flex = flex;
+    G.V.alloc((size_t)(m + 1) * n * cb);
+    if (flex) G.Z.alloc((size_t)m * n * cb);
+    G.w.alloc((size_t)n * cb);
+    G.S.alloc((size_t)((m + 1) * m + 2 * m + (m + 1) + m + 8 + (m + 1)) * sizeof(cd64));
+    G.st.alloc(8 * sizeof(int));
+  }
+  return G;
+}
+
+void Context::sync() { WCMG_HIP(hipStreamSynchronize(stream)); }
+
+int Context::store_prec_for(int l, bool single) const {
+  (void)l;
+  if (!single) return WCMG_F64;
+  return p.coarse_store_prec == WCMG_BF16 ? WCMG_BF16 : WCMG_F32;
+}
+
+template <typename R>
+void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms) {
+  const bool single = sizeof(R) == 4;
+  if (l == 0) {
+    prof.begin("dslash", stream);
+    if (single)
+      launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
+                           geo[0].V, terms, nrhs, run, stream);
+    else
+      launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
+                            geo[0].V, terms, nrhs, run, stream);
+    prof.end("dslash", stream);
+  } else {
+    const int prec = store_prec_for(l, single);
+    prof.begin("coarse_apply", stream);
+    cop[l - 1]->apply(prec, in, out, terms, 0, nrhs, run, stream);
+    prof.end("coarse_apply", stream);
+  }
+}
+
+template <typename R>
+double Context::norm2_host(const cplx<R>* v, long n) {
+  cd64* s = scratch64.as<cd64>() + 8;
+  launch_dot<R>(v, 0, 1, nullptr, v, n, partial.as<cd64>(), 1, s, 1, 0, nullptr, stream);
+  cd64 h;
+  WCMG_HIP(hipMemcpyAsync(&h, s, sizeof(cd64), hipMemcpyDeviceToHost, stream));
+  sync();
+  return h.re;
+}
+
+// ---------------------------------------------------------------- gauge and clover
+void Context::set_gauge(const cd64* U) {
+  const long V0 = geo[0].V;
+  WCMG_HIP(hipMemcpyAsync(U_lex.p, U, V0 * 36 * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  launch_clover_build(U_lex.as<cd64>(), geo[0].L, p.c_sw, clover_lex.as<cd64>(), stream);
+  launch_pack_links<double>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U64.as<cd64>(), stream);
+  launch_pack_links<float>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U32.as<cf32>(), stream);
+  pack_clover();
+  gauge_set = true;
+  setup_done = false;
+}
+
+void Context::set_clover(const cd64* blocks) {
+  WCMG_HIP(hipMemcpyAsync(clover_lex.p, blocks, geo[0].V * 72 * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  pack_clover();
+  setup_done = false;
+}
+
+void Context::pack_clover() {
+  launch_pack_clover<double>(clover_lex.as<cd64>(), perm0.as<int>(), geo[0].V, p.m0, clov64.as<double>(), stream);
+  launch_pack_clover<float>(clover_lex.as<cd64>(), perm0.as<int>(), geo[0].V, p.m0, clov32.as<float>(), stream);
+}
+
+// ---------------------------------------------------------------- transfers
+template <typename R>
+void Context::restrict_(int l, const cplx<R>* fine, cplx<R>* coarse, int nrhs, const int* run) {
+  Transfer& T = tr[l];
+  const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
+  prof.begin("restrict", stream);
+  launch_restrict<R>(fine, coarse, P, geo[l].lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nb, nrhs, run, stream);
+  prof.end("restrict", stream);
+}
+
+template <typename R>
+void Context::prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumulate, int nrhs, const int* run) {
+  Transfer& T = tr[l];
+  const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
+  prof.begin("prolong", stream);
+  launch_prolong<R>(coarse, fine, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, accumulate, nrhs, run, stream);
+  prof.end("prolong", stream);
+}
+
+// ---------------------------------------------------------------- smoother
+// MinimalResidual (Sec. 2.1): from x and r = b - D x, `steps` times
+//   p = D r; alpha = <p,r>/<p,p>; x += alpha r; r -= alpha p.
+// b == nullptr means b = 0 (relaxation on D x = 0).
+template <typename R>
+void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run) {
+  const long nn = n(l);
+  const std::string t = std::to_string(l) + (sizeof(R) == 8 ? "d" : "f");
+  cplx<R>* r = buf<cplx<R>>("mr_r" + t, nn);
+  cplx<R>* pp = buf<cplx<R>>("mr_p" + t, nn);
+  cd64* dots = buf<cd64>("mr_dots" + t, 2);
+  if (x0_zero) {
+    launch_zero<R>(x, nn, run, stream);
+    if (b) launch_convert<R, R>(b, r, nn, run, stream);
+    else launch_zero<R>(r, nn, run, stream);
+  } else {
+    apply_op<R>(l, x, pp, 1, run);
+    if (b) launch_sub<R>(r, b, pp, nn, run, stream);
+    else launch_axpby<R>(r, pp, -1.0, 0.0, nn, run, stream);
+  }
+  for (int k = 0; k < steps; ++k) {
+    apply_op<R>(l, r, pp, 1, run);
+    launch_mr_dots_update<R>(x, r, pp, nn, partial.as<cd64>(), dots, run, stream);
+  }
+}
+
+// ---------------------------------------------------------------- GMRES / FGMRES
+// Restarted GMRES with classical Gram-Schmidt applied twice (CGS2) and Givens
+// rotations kept on the device.  With a preconditioner M the flexible variant
+// stores z_j = M v_j and updates x with Z y (Sec. 2.1 FGMRES).
+// Returns the iteration count when the host checks progress, else -1.
+template <typename R>
+int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<R>*, const int*)>& A,
+                   const std::function<void(const cplx<R>*, cplx<R>*, const int*)>* M, const cplx<R>* b, cplx<R>* x,
+                   bool x0_zero, int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent,
+                   int check_every) {
+  const long nn = G.n;
+  const int m = restart;
+  cplx<R>* V = G.V.as<cplx<R>>();
+  cplx<R>* Z = M ? G.Z.as<cplx<R>>() : nullptr;
+  cplx<R>* w = G.w.as<cplx<R>>();
+  cd64* S = G.S.as<cd64>();
+  cd64* H = S;
+  cd64* g = S + (m + 1) * m + 2 * m;
+  cd64* y = g + (m + 1);
+  cd64* misc = y + m;
+  cd64* tmp = misc + 8;
+  int* st = G.st.as<int>();
+  int* run = st;
+  int* live = st + 1;
+  cd64* part = partial.as<cd64>();
+  const int Gb = reduction_blocks(nn);
+  launch_gmres_init(st, parent, stream);
+  if (x0_zero) launch_zero<R>(x, nn, live, stream);
+  launch_dot<R>(b, 0, 1, nullptr, b, nn, part, 1, misc + 0, 1, 0, live, stream);
+  const int limit = fixed > 0 ? fixed : maxit;
+  const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
+  auto read_state = [&]() {
+    WCMG_HIP(hipMemcpyAsync(pinned, st, 5 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    sync();
+  };
+  for (int cyc = 0; cyc < max_cycles; ++cyc) {
+    if (cyc == 0 && x0_zero) {
+      launch_convert<R, R>(b, V, nn, live, stream);
+    } else {
+      A(x, w, live);
+      launch_sub<R>(V, b, w, nn, live, stream);
+    }
+    launch_dot<R>(V, 0, 1, nullptr, V, nn, part, 1, misc + 1, 1, 0, live, stream);
+    launch_gmres_cycle_start(st, S, m, tol, limit, fixed, stream);
+    launch_scale_inv_norm<R>(V, V, misc + 1, nn, run, stream);
+    for (int j = 0; j < m; ++j) {
+      cplx<R>* vj = V + (long)j * nn;
+      cplx<R>* zj = M ? Z + (long)j * nn : vj;
+      if (M) (*M)(vj, zj, run);
+      A(zj, w, run);
+      launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, H + j, m, 0, run, stream);
+      launch_multi_axpy<R>(w, V, nn, j + 1, nullptr, H + j, m, -1.0, nn, run, stream);
+      launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, tmp, 1, 0, run, stream);
+      launch_dot_finish(part, Gb, j + 1, j + 1, H + j, m, 1, run, stream);
+      launch_multi_axpy<R>(w, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, run, stream);
+      launch_dot<R>(w, 0, 1, nullptr, w, nn, part, 1, misc + 3, 1, 0, run, stream);
+      launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
+      if (j + 1 < m) launch_scale_inv_norm<R>(V + (long)(j + 1) * nn, w, misc + 3, nn, run, stream);
+      if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
+        read_state();
+        if (!pinned[0]) break;
+      }
+    }
+    launch_gmres_solve_y(st, S, m, stream);
+    launch_multi_axpy<R>(x, M ? Z : V, nn, m, st + 2, y, 1, 1.0, nn, nullptr, stream);
+    launch_gmres_cycle_end(st, stream);
+    if (check_every > 0) {
+      read_state();
+      if (!pinned[1]) break;
+    }
+  }
+  if (check_every > 0) {
+    read_state();
+    return pinned[3];
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------- cycle
+// One application of the preconditioner rooted at level l: restrict, coarse
+// correction (GMRES on the coarsest level, FGMRES preconditioned by the next
+// cycle for a K-cycle, or the next V-cycle), prolong, post-smooth with MR.
+template <typename R>
+void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
+  const int lc = l + 1;
+  const std::string t = std::to_string(lc) + (sizeof(R) == 8 ? "d" : "f");
+  const long nc = n(lc);
+  cplx<R>* rc = buf<cplx<R>>("cyc_rc" + t, nc);
+  cplx<R>* ec = buf<cplx<R>>("cyc_ec" + t, nc);
+  restrict_<R>(l, r, rc, 1, run);
+  std::function<void(const cplx<R>*, cplx<R>*, const int*)> A = [this, lc](const cplx<R>* i, cplx<R>* o,
+                                                                              const int* rn) {
+    apply_op<R>(lc, i, o, 1, rn);
+  };
+  const int check = (p.reserved[0] & 1) ? 0 : 4;  // reserved[0] bit 0: no host checks inside cycles
+  if (lc + 1 >= nlev) {
+    GmresState& G = gmres_state("cg" + t, p.coarse_restart, nc, sizeof(R) == 8 ? 0 : 1, false);
+    int it = gmres<R>(G, A, nullptr, rc, ec, true, p.coarse_restart, p.coarse_maxit, p.coarse_tol,
+                      p.coarse_fixed_iters, true, run, check);
+    if (it > 0) coarse_iters += it;
+  } else if (p.kcycle) {
+    std::function<void(const cplx<R>*, cplx<R>*, const int*)> Mc = [this, lc](const cplx<R>* i, cplx<R>* o,
+                                                                               const int* rn) { cycle<R>(lc, i, o, rn); };
+    GmresState& G = gmres_state("kc" + t, p.kcycle_maxit, nc, sizeof(R) == 8 ? 0 : 1, true);
+    gmres<R>(G, A, &Mc, rc, ec, true, p.kcycle_maxit, p.kcycle_maxit, p.kcycle_tol, 0, true, run, 0);
+  } else {
+    cycle<R>(lc, rc, ec, run);
+  }
+  prolong_<R>(l, ec, x, 0, 1, run);
+  mr<R>(l, r, x, false, p.post_smooth, run);
+  cycles++;
+}
+
+void Context::precondition64(int l, const cd64* r, cd64* x, const int* run) {
+  if (p.cycle_prec == WCMG_F64) {
+    cycle<double>(l, r, x, run);
+    return;
+  }
+  const long nn = n(l);
+  const std::string t = std::to_string(l);
+  cf32* r32 = buf<cf32>("pc_r32" + t, nn);
+  cf32* x32 = buf<cf32>("pc_x32" + t, nn);
+  launch_convert<double, float>(r, r32, nn, run, stream);
+  cycle<float>(l, r32, x32, run);
+  launch_convert<float, double>(x32, x, nn, run, stream);
+}
+
+// ---------------------------------------------------------------- setup
+void Context::rebuild(int l) {
+  Transfer& T = tr[l];
+  const LevelGeom& G = geo[l];
+  const long nn = G.n();
+  auto t0 = std::chrono::steady_clock::now();
+  WCMG_HIP(hipMemcpyAsync(T.P64.p, T.vecs64.p, T.nv * nn * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  int* flag = (int*)(scratch64.as<cd64>() + 32);
+  WCMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
+  launch_block_orthonormalise(T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nv, flag, stream);
+  launch_convert<double, float>(T.P64.as<cd64>(), T.P32.as<cf32>(), T.nv * nn, nullptr, stream);
+  WCMG_HIP(hipMemcpyAsync(pinned + 8, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+  sync();
+  timers[2] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  require(pinned[8] == 0, WCMG_ERR_BREAKDOWN, "Gram-Schmidt breakdown at level " + std::to_string(l));
+  galerkin(l);
+  T.built = true;
+}
+
+// Galerkin coarse operator (Sec. 2.1 CoarsenOperator): for each term of the
+// level operator (Mdiag and the eight Mdir) apply it to every column of P and
+// project on P aggregate by aggregate.
+void Context::galerkin(int l) {
+  auto t0 = std::chrono::steady_clock::now();
+  Transfer& T = tr[l];
+  const LevelGeom& G = geo[l];
+  CoarseOp& C = *cop[l];
+  const long nn = G.n();
+  cd64* cols = buf<cd64>("gal_cols" + std::to_string(l), (long)T.nb * nn);
+  cd64* W = buf<cd64>("gal_W" + std::to_string(l), (long)T.nb * nn);
+  WCMG_HIP(hipMemsetAsync(C.M64.p, 0, C.M64.bytes, stream));
+  launch_prolongator_columns(T.P64.as<cd64>(), G.lay, T.nv, cols, stream);
+  for (int d = 0; d <= 8; ++d) {
+    apply_op<double>(l, cols, W, T.nb, nullptr, 1 << d);
+    const int* nbr_d = d == 0 ? nullptr : G.nbr.as<int>() + (long)(d - 1) * G.V;
+    launch_galerkin_project(W, T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.coarse_of.as<int>(), nbr_d, T.A,
+                            T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+  }
+  for (int q = 0; q < 3; ++q) C.fresh[q] = false;
+  C.refresh(WCMG_F64, stream);
+  if (p.cycle_prec == WCMG_F32 || p.setup_prec == WCMG_F32) C.refresh(store_prec_for(l + 1, true), stream);
+  sync();
+  timers[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void Context::regalerkin_below(int l) {
+  for (int k = l + 1; k + 1 < nlev; ++k) galerkin(k);
+}
+
+// Initial setup (Sec. 2.1): iterate the smoother on random vectors.  Reading:
+// relax_sweeps MR steps on D x = 0 from each start vector, then normalise.
+void Context::initial_setup(int l) {
+  Transfer& T = tr[l];
+  require(T.has_start, WCMG_ERR_STATE, "start vectors of level " + std::to_string(l) + " not set");
+  const long nn = n(l);
+  auto t0 = std::chrono::steady_clock::now();
+  WCMG_HIP(hipMemcpyAsync(T.vecs64.p, T.start64.p, T.nv * nn * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  cd64* nrm = scratch64.as<cd64>() + 16;
+  for (int i = 0; i < T.nv; ++i) {
+    cd64* x = T.vecs64.as<cd64>() + (long)i * nn;
+    if (p.setup_prec == WCMG_F64) {
+      mr<double>(l, nullptr, x, false, p.relax_sweeps, nullptr);
+    } else {
+      cf32* x32 = buf<cf32>("relax32" + std::to_string(l), nn);
+      launch_convert<double, float>(x, x32, nn, nullptr, stream);
+      mr<float>(l, nullptr, x32, false, p.relax_sweeps, nullptr);
+      launch_convert<float, double>(x32, x, nn, nullptr, stream);
+    }
+    launch_dot<double>(x, 0, 1, nullptr, x, nn, partial.as<cd64>(), 1, nrm, 1, 0, nullptr, stream);
+    launch_scale_inv_norm<double>(x, x, nrm, nn, nullptr, stream);
+  }
+  sync();
+  timers[1] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  rebuild(l);
+}
+
+// Iterative setup (Sec. 2.1, DDalphaAMG-style).  One iteration at level l:
+// each vector is replaced by the preconditioner rooted at l applied to it
+// (zero initial guess) and normalised; then P_l and D_{l+1} are rebuilt, the
+// Galerkin products below are re-taken and the next level is refined.
+void Context::refine_iteration(int l) {
+  Transfer& T = tr[l];
+  const long nn = n(l);
+  cd64* y = buf<cd64>("ref_y" + std::to_string(l), nn);
+  cd64* nrm = scratch64.as<cd64>() + 20;
+  for (int i = 0; i < T.nv; ++i) {
+    cd64* v = T.vecs64.as<cd64>() + (long)i * nn;
+    precondition64(l, v, y, nullptr);
+    launch_dot<double>(y, 0, 1, nullptr, y, nn, partial.as<cd64>(), 1, nrm, 1, 0, nullptr, stream);
+    launch_scale_inv_norm<double>(v, y, nrm, nn, nullptr, stream);
+  }
+  rebuild(l);
+  regalerkin_below(l);
+  if (l + 2 < nlev) refine_iteration(l + 1);
+}
+
+void Context::setup_all() {
+  require(gauge_set, WCMG_ERR_STATE, "gauge field not set");
+  auto t0 = std::chrono::steady_clock::now();
+  for (int q = 0; q < 5; ++q) timers[q] = 0.0;
+  for (int l = 0; l + 1 < nlev; ++l) initial_setup(l);
+  auto t1 = std::chrono::steady_clock::now();
+  for (int it = 0; it < p.refine_iters; ++it) refine_iteration(0);
+  sync();
+  auto t2 = std::chrono::steady_clock::now();
+  timers[4] = std::chrono::duration<double>(t2 - t1).count();
+  timers[0] = std::chrono::duration<double>(t2 - t0).count();
+  setup_done = true;
+}
+
+// ---------------------------------------------------------------- instantiations
+template void Context::apply_op<double>(int, const cd64*, cd64*, int, const int*, int);
+template void Context::apply_op<float>(int, const cf32*, cf32*, int, const int*, int);
+template void Context::restrict_<double>(int, const cd64*, cd64*, int, const int*);
+template void Context::restrict_<float>(int, const cf32*, cf32*, int, const int*);
+template void Context::prolong_<double>(int, const cd64*, cd64*, int, int, const int*);
+template void Context::prolong_<float>(int, const cf32*, cf32*, int, int, const int*);
+template void Context::mr<double>(int, const cd64*, cd64*, bool, int, const int*);
+template void Context::mr<float>(int, const cf32*, cf32*, bool, int, const int*);
+template void Context::cycle<double>(int, const cd64*, cd64*, const int*);
+template void Context::cycle<float>(int, const cf32*, cf32*, const int*);
+template int Context::gmres<double>(GmresState&, const std::function<void(const cd64*, cd64*, const int*)>&,
+                                    const std::function<void(const cd64*, cd64*, const int*)>*, const cd64*, cd64*,
+                                    bool, int, int, double, int, bool, const int*, int);
+template int Context::gmres<float>(GmresState&, const std::function<void(const cf32*, cf32*, const int*)>&,
+                                   const std::function<void(const cf32*, cf32*, const int*)>*, const cf32*, cf32*,
+                                   bool, int, int, double, int, bool, const int*, int);
+template double Context::norm2_host<double>(const cd64*, long);
+template double Context::norm2_host<float>(const cf32*, long);
+template cd64* Context::buf<cd64>(const std::string&, long);
+template cf32* Context::buf<cf32>(const std::string&, long);
+
+}  // namespace wcmg

@@ -1,0 +1,79 @@
+// Launcher declarations of the wcmg HIP kernels.
+#pragma once
+
+#include "common.h"
+
+namespace wcmg {
+
+template <int P>
+struct BlkTraits;
+
+// ---- fine level (wilson.hip)
+void launch_clover_build(const cd64* U, const int L[4], double csw, cd64* out, hipStream_t st);
+template <typename R>
+void launch_pack_clover(const cd64* blocks, const int* perm, long V, double m0, R* out, hipStream_t st);
+template <typename R>
+void launch_pack_links(const cd64* U, const int* perm, const int L[4], int antiperiodic, cplx<R>* out, hipStream_t st);
+template <typename Ti, typename To>
+void launch_pack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
+template <typename Ti, typename To>
+void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
+template <typename R>
+void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
+                   int terms, int nrhs, const int* run, hipStream_t st);
+
+// ---- coarse operator (coarse.hip)
+size_t device_block_bytes(long Vc, int nb, int prec);
+void launch_blocks_to_device(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
+void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st);
+void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
+                         int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
+
+// ---- transfer and coarsening (transfer.hip)
+bool supported_nb(int nb);
+template <typename R>
+void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
+                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st);
+template <typename R>
+void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st);
+void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
+                                 int* breakdown, hipStream_t st);
+void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st);
+void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
+                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
+                             hipStream_t st);
+
+// ---- vector algebra and solver control (blas.hip)
+template <typename R>
+void launch_dot(const cplx<R>* a, long astride, int m, const int* m_dev, const cplx<R>* b, long n, cd64* partial,
+                int mstride, cd64* out, int ostride, int mode, const int* run, hipStream_t st);
+int reduction_blocks(long n);
+void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out, int ostride, int mode,
+                       const int* run, hipStream_t st);
+template <typename R>
+void launch_multi_axpy(cplx<R>* y, const cplx<R>* V, long vstride, int m, const int* m_dev, const cd64* coef,
+                       int cstride, double sign, long n, const int* run, hipStream_t st);
+template <typename R>
+void launch_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, long n, const int* run, hipStream_t st);
+template <typename R>
+void launch_scale_inv_norm(cplx<R>* y, const cplx<R>* x, const cd64* nrm2, long n, const int* run, hipStream_t st);
+template <typename R>
+void launch_zero(cplx<R>* y, long n, const int* run, hipStream_t st);
+template <typename R>
+void launch_sub(cplx<R>* y, const cplx<R>* a, const cplx<R>* b, long n, const int* run, hipStream_t st);
+template <typename Ti, typename To>
+void launch_convert(const cplx<Ti>* x, cplx<To>* y, long n, const int* run, hipStream_t st);
+template <typename R>
+void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
+                           const int* run, hipStream_t st);
+void launch_gmres_init(int* st_, const int* parent, hipStream_t st);
+void launch_gmres_cycle_start(int* st_, cd64* S, int m, double tol, int limit, int fixed, hipStream_t st);
+void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit, int fixed, int stop_on_est,
+                         hipStream_t st);
+void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
+void launch_gmres_cycle_end(int* st_, hipStream_t st);
+
+constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
+
+}  // namespace wcmg

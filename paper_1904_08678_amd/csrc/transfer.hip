@@ -1,0 +1,311 @@
+// Intergrid operators and coarsening (Sec. 2.1 Aggregation / CoarsenedMatrix,
+// Sec. 2.2 chirality-preserving prolongator, Sec. 3 blockProject).
+//
+// Restriction is owned per coarse site (one workgroup per aggregate, the
+// race-free scheme of Sec. 3): the workgroup walks its aggregate through the
+// coarse-to-fine lookup table, every lane accumulates partial inner products,
+// and a fixed-order wave + LDS reduction produces the coarse components.
+// No atomics, so results are bitwise reproducible.
+//
+// Prolongator storage: P holds nv vectors [nv][level layout]; the chirality
+// half chi of vector i, orthonormalised aggregate by aggregate, is column
+// b = chi * nv + i of P (Sec. 2.2).  Chirality is implicit: nothing is stored
+// twice and no explicit zeros are kept.
+#include "kernels.h"
+
+namespace wcmg {
+
+// Sum over the workgroup of NB complex values per lane, fixed order.
+// Result is valid in lds_out[0..NB) for every lane after the call.
+template <int NB>
+__device__ inline void block_sum(cd64 (&acc)[NB], cd64* lds /*[16][NB]*/, cd64* lds_out /*[NB]*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double re = acc[b].re, im = acc[b].im;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) lds[wave * NB + b] = mkc(re, im);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    cd64 s = mkc(0.0, 0.0);
+    for (int w = 0; w < nw; ++w) s = cadd(s, lds[w * NB + threadIdx.x]);
+    lds_out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// coarse(c, b) = sum_{x in c} sum_{k in chi(b)} conj(P_{b mod nv}(x)_k) fine(x)_k
+// grid (Vc, nrhs), block 256.
+template <typename R, int NB>
+__global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fine, cplx<R>* __restrict__ coarse,
+                                                   const cplx<R>* __restrict__ P, FieldLayout lay,
+                                                   const int* __restrict__ agg_sites, int A, long Vc,
+                                                   const int* __restrict__ run) {
+  if (run && !*run) return;
+  constexpr int nv = NB / 2;
+  __shared__ cd64 lds[16 * NB];
+  __shared__ cd64 res[NB];
+  const long c = blockIdx.x;
+  const long r = blockIdx.y;
+  fine += r * lay.size();
+  coarse += r * Vc * NB;
+  const int h = lay.ns / 2;
+  const long pstride = lay.size();
+  cd64 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = mkc(0.0, 0.0);
+  for (int o = threadIdx.x; o < A; o += blockDim.x) {
+    const long s = agg_sites[c * A + o];
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      cplx<R> pa[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) pa[i] = mkc((R)0, (R)0);
+      for (int k = 0; k < h; ++k) {
+        const long e = lay.at(s, chi * h + k);
+        const cplx<R> v = fine[e];
+#pragma unroll
+        for (int i = 0; i < nv; ++i) cfmac(pa[i], P[i * pstride + e], v);
+      }
+#pragma unroll
+      for (int i = 0; i < nv; ++i) acc[chi * nv + i] = cadd(acc[chi * nv + i], ccast<double>(pa[i]));
+    }
+  }
+  block_sum<NB>(acc, lds, res);
+  if (threadIdx.x < NB) coarse[c * NB + threadIdx.x] = ccast<R>(res[threadIdx.x]);
+}
+
+// fine(x)_k (+)= sum_{i} P_i(x)_k coarse(c(x), chi(k) * nv + i); thread per site.
+template <typename R, int NB>
+__global__ void __launch_bounds__(256) k_prolong(const cplx<R>* __restrict__ coarse, cplx<R>* __restrict__ fine,
+                                                  const cplx<R>* __restrict__ P, FieldLayout lay,
+                                                  const int* __restrict__ coarse_of, long Vc, int accumulate,
+                                                  const int* __restrict__ run) {
+  if (run && !*run) return;
+  constexpr int nv = NB / 2;
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= lay.V) return;
+  const long r = blockIdx.y;
+  fine += r * lay.size();
+  coarse += r * Vc * NB;
+  const long c = coarse_of[s];
+  const int h = lay.ns / 2;
+  const long pstride = lay.size();
+  cplx<R> phi[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) phi[b] = coarse[c * NB + b];
+#pragma unroll
+  for (int chi = 0; chi < 2; ++chi)
+    for (int k = 0; k < h; ++k) {
+      const long e = lay.at(s, chi * h + k);
+      cplx<R> t = mkc((R)0, (R)0);
+#pragma unroll
+      for (int i = 0; i < nv; ++i) cfma(t, P[i * pstride + e], phi[chi * nv + i]);
+      if (accumulate) t = cadd(t, fine[e]);
+      fine[e] = t;
+    }
+}
+
+// Per aggregate and chirality: modified Gram-Schmidt of the nv vectors in
+// index order, each vector projected twice against the earlier ones, then
+// normalised (FP64).  Breakdown when the projected norm falls below 1e-10 of
+// the norm before projection.  grid (Vc, 2), block 256.
+__device__ inline double block_sum1(double v, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += lds[w];
+  return s;
+}
+
+__global__ void __launch_bounds__(256) k_block_orthonormalise(cd64* __restrict__ vecs, FieldLayout lay,
+                                                               const int* __restrict__ agg_sites, int A, int nv,
+                                                               int* __restrict__ breakdown) {
+  __shared__ double lds[16];
+  const long c = blockIdx.x;
+  const int chi = blockIdx.y;
+  const int h = lay.ns / 2;
+  const int nel = A * h;
+  const long vstride = lay.size();
+  auto elem = [&](int e) -> long {
+    const int o = e % A, k = e / A;
+    return lay.at(agg_sites[c * A + o], chi * h + k);
+  };
+  for (int i = 0; i < nv; ++i) {
+    cd64* vi = vecs + i * vstride;
+    double pre = 0.0;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+      cd64 v = vi[elem(e)];
+      pre += v.re * v.re + v.im * v.im;
+    }
+    pre = sqrt(block_sum1(pre, lds));
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < i; ++j) {
+        const cd64* vj = vecs + j * vstride;
+        double pr = 0.0, pi = 0.0;
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+          const long q = elem(e);
+          cd64 a = vj[q], b = vi[q];
+          pr += a.re * b.re + a.im * b.im;
+          pi += a.re * b.im - a.im * b.re;
+        }
+        pr = block_sum1(pr, lds);
+        pi = block_sum1(pi, lds);
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+          const long q = elem(e);
+          cd64 a = vj[q], b = vi[q];
+          b.re -= pr * a.re - pi * a.im;
+          b.im -= pr * a.im + pi * a.re;
+          vi[q] = b;
+        }
+        __syncthreads();
+      }
+    double post = 0.0;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+      cd64 v = vi[elem(e)];
+      post += v.re * v.re + v.im * v.im;
+    }
+    post = sqrt(block_sum1(post, lds));
+    if (!(post > 1e-10 * pre) || pre == 0.0) {
+      if (threadIdx.x == 0) atomicOr(breakdown, 1);
+      post = post > 0.0 ? post : 1.0;
+    }
+    const double inv = 1.0 / post;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+      const long q = elem(e);
+      cd64 v = vi[q];
+      vi[q] = mkc(v.re * inv, v.im * inv);
+    }
+    __syncthreads();
+  }
+}
+
+// Column fields of P: col_b(x)_k = P_{b mod nv}(x)_k on chirality half b / nv,
+// zero on the other half.  out [NB][layout].  grid (sites, NB).
+__global__ void k_prolongator_columns(const cd64* __restrict__ P, FieldLayout lay, int nv, cd64* __restrict__ out) {
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= lay.V) return;
+  const int b = blockIdx.y;
+  const int i = b % nv, chi = b / nv;
+  const int h = lay.ns / 2;
+  for (int k = 0; k < lay.ns; ++k) {
+    const long e = lay.at(s, k);
+    out[b * lay.size() + e] = (k / h == chi) ? P[i * lay.size() + e] : mkc(0.0, 0.0);
+  }
+}
+
+// Galerkin projection of one term of the level operator (Sec. 2.1 CoarsenOperator):
+// W_b = Mdir_d(column b of P) (or Mdiag for d = 0) is projected on the rows of
+// P aggregate by aggregate; contributions of sites whose d-neighbour lies in
+// the same aggregate go to block 0, the rest to block d.
+// grid (Vc, NB columns, 2 targets), block 256.  FP64.
+template <int NB>
+__global__ void __launch_bounds__(256) k_galerkin_project(const cd64* __restrict__ W, const cd64* __restrict__ P,
+                                                           FieldLayout lay, const int* __restrict__ agg_sites,
+                                                           const int* __restrict__ coarse_of,
+                                                           const int* __restrict__ nbr_d, int A, long Vc, int d,
+                                                           cd64* __restrict__ M) {
+  constexpr int nv = NB / 2;
+  __shared__ cd64 lds[16 * NB];
+  __shared__ cd64 res[NB];
+  const long c = blockIdx.x;
+  const int b = blockIdx.y;
+  const int target = blockIdx.z;  // 0: block 0 (interior), 1: block d (exterior)
+  if (d == 0 && target == 1) return;
+  const int h = lay.ns / 2;
+  const long vs = lay.size();
+  const cd64* Wb = W + b * vs;
+  cd64 acc[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) acc[a] = mkc(0.0, 0.0);
+  for (int o = threadIdx.x; o < A; o += blockDim.x) {
+    const long s = agg_sites[c * A + o];
+    bool interior = (d == 0) || (coarse_of[nbr_d[s]] == c);
+    if (interior != (target == 0)) continue;
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi)
+      for (int k = 0; k < h; ++k) {
+        const long e = lay.at(s, chi * h + k);
+        const cd64 w = Wb[e];
+#pragma unroll
+        for (int i = 0; i < nv; ++i) cfmac(acc[chi * nv + i], P[i * vs + e], w);
+      }
+  }
+  block_sum<NB>(acc, lds, res);
+  if (threadIdx.x < NB) {
+    const int dd = target == 0 ? 0 : d;
+    cd64* m = M + ((c * 9 + dd) * NB + threadIdx.x) * NB + b;
+    *m = cadd(*m, res[threadIdx.x]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+#define NB_SWITCH(nb, ...)                                     \
+  switch (nb) {                                                 \
+    case 8: { constexpr int NBc = 8; __VA_ARGS__; } break;            \
+    case 12: { constexpr int NBc = 12; __VA_ARGS__; } break;          \
+    case 16: { constexpr int NBc = 16; __VA_ARGS__; } break;          \
+    case 24: { constexpr int NBc = 24; __VA_ARGS__; } break;          \
+    case 32: { constexpr int NBc = 32; __VA_ARGS__; } break;          \
+    case 40: { constexpr int NBc = 40; __VA_ARGS__; } break;          \
+    case 4: { constexpr int NBc = 4; __VA_ARGS__; } break;            \
+    case 6: { constexpr int NBc = 6; __VA_ARGS__; } break;            \
+    case 20: { constexpr int NBc = 20; __VA_ARGS__; } break;          \
+    default: throw Error(WCMG_ERR_ARG, "unsupported coarse block size Nb = " + std::to_string(nb)); \
+  }
+
+bool supported_nb(int nb) {
+  return nb == 4 || nb == 6 || nb == 8 || nb == 12 || nb == 16 || nb == 20 || nb == 24 || nb == 32 || nb == 40;
+}
+
+template <typename R>
+void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
+                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st) {
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_restrict<R, NBc>), dim3(Vc, nrhs), dim3(kBlock), 0, st, fine, coarse, P, lay,
+                                    agg_sites, A, Vc, run));
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st) {
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_prolong<R, NBc>), dim3(nblocks(lay.V), nrhs), dim3(kBlock), 0, st, coarse,
+                                    fine, P, lay, coarse_of, Vc, accumulate, run));
+  WCMG_CHECK_LAUNCH();
+}
+#define INST_TR(R)                                                                                                 \
+  template void launch_restrict<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, int, long, int, \
+                                   int, const int*, hipStream_t);                                                  \
+  template void launch_prolong<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, long, int, int, \
+                                  int, const int*, hipStream_t);
+INST_TR(double)
+INST_TR(float)
+
+void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
+                                 int* breakdown, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_orthonormalise, dim3(Vc, 2), dim3(kBlock), 0, st, vecs, lay, agg_sites, A, nv, breakdown);
+  WCMG_CHECK_LAUNCH();
+}
+
+void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolongator_columns, dim3(nblocks(lay.V), 2 * nv), dim3(kBlock), 0, st, P, lay, nv, out);
+  WCMG_CHECK_LAUNCH();
+}
+
+void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
+                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
+                             hipStream_t st) {
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_project<NBc>), dim3(Vc, NBc, 2), dim3(kBlock), 0, st, W, P, lay,
+                                    agg_sites, coarse_of, nbr_d, A, Vc, d, M));
+  WCMG_CHECK_LAUNCH();
+}
+
+}  // namespace wcmg

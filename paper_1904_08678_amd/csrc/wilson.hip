@@ -1,0 +1,418 @@
+// Fine level: clover term, field packing and the Wilson-clover operator.
+//
+// Device layout of level 0 (aggregate-major, Sec. 3 of the paper: the fine
+// lattice is linearised aggregate by aggregate so restriction reads contiguous
+// memory):  device site s = c * A + o, with c the aggregate and o the offset
+// inside it.  Fields are structure-of-arrays over sites:
+//   spinor   [12][V]      complex (component k = 3*spin + colour)
+//   links    [4][9][V]    complex, U_mu(s) row-major; the antiperiodic sign of
+//                         the t boundary is folded into U_t on the last slice
+//   clover   [2][36][V]   real: per chirality a packed Hermitian 6x6 block of
+//                         (4 + m0) + C: 6 diagonal reals, then the 15 entries
+//                         below the diagonal (row i > col j, row-major) as re, im
+//   nbr      [8][V]       int32 neighbour site in direction d = 1..8
+#include "kernels.h"
+
+namespace wcmg {
+
+// ---------------------------------------------------------------- clover build
+// Q_{mu nu}(x): sum of the four plaquette leaves in the mu-nu plane through x.
+// Computed on the lexicographic lattice directly from the caller's links.
+struct Su3 {
+  cd64 m[9];
+};
+__device__ inline Su3 su3_load(const cd64* U, long site, int mu) {
+  Su3 r;
+  const cd64* p = U + (site * 4 + mu) * 9;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r.m[i] = p[i];
+  return r;
+}
+__device__ inline Su3 su3_mm(const Su3& a, const Su3& b) {
+  Su3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cd64 s = mkc(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(s, a.m[i * 3 + k], b.m[k * 3 + j]);
+      c.m[i * 3 + j] = s;
+    }
+  return c;
+}
+// a * b^dag
+__device__ inline Su3 su3_mmd(const Su3& a, const Su3& b) {
+  Su3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cd64 s = mkc(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(s, a.m[i * 3 + k], cconj(b.m[j * 3 + k]));
+      c.m[i * 3 + j] = s;
+    }
+  return c;
+}
+// a^dag * b
+__device__ inline Su3 su3_mdm(const Su3& a, const Su3& b) {
+  Su3 c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cd64 s = mkc(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfmac(s, a.m[k * 3 + i], b.m[k * 3 + j]);
+      c.m[i * 3 + j] = s;
+    }
+  return c;
+}
+
+struct Lex {
+  int L[4];
+  __device__ long shift(long i, int mu, int step) const {
+    int x[4];
+    long r = i;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      x[m] = (int)(r % L[m]);
+      r /= L[m];
+    }
+    x[mu] = (x[mu] + step + L[mu]) % L[mu];
+    return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3]));
+  }
+};
+
+// F_{mu nu}(x) = (Q - Q^dag) / 8
+__device__ Su3 field_strength(const cd64* U, const Lex& lx, long x, int mu, int nu) {
+  long xpm = lx.shift(x, mu, 1), xpn = lx.shift(x, nu, 1);
+  long xmm = lx.shift(x, mu, -1), xmn = lx.shift(x, nu, -1);
+  long xmm_pn = lx.shift(xmm, nu, 1), xmm_mn = lx.shift(xmm, nu, -1), xmn_pm = lx.shift(xmn, mu, 1);
+  Su3 Q, t;
+  // x -> x+mu -> x+mu+nu -> x+nu -> x
+  t = su3_mm(su3_load(U, x, mu), su3_load(U, xpm, nu));
+  t = su3_mmd(t, su3_load(U, xpn, mu));
+  Q = su3_mmd(t, su3_load(U, x, nu));
+  // x -> x+nu -> x+nu-mu -> x-mu -> x
+  t = su3_mmd(su3_load(U, x, nu), su3_load(U, xmm_pn, mu));
+  t = su3_mmd(t, su3_load(U, xmm, nu));
+  t = su3_mm(t, su3_load(U, xmm, mu));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Q.m[i] = cadd(Q.m[i], t.m[i]);
+  // x -> x-mu -> x-mu-nu -> x-nu -> x
+  {
+    Su3 a = su3_load(U, xmm, mu), b = su3_load(U, xmm_mn, nu);
+    // a^dag b^dag = (b a)^dag
+    Su3 ba = su3_mm(b, a);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t.m[i * 3 + j] = cconj(ba.m[j * 3 + i]);
+  }
+  t = su3_mm(t, su3_load(U, xmm_mn, mu));
+  t = su3_mm(t, su3_load(U, xmn, nu));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Q.m[i] = cadd(Q.m[i], t.m[i]);
+  // x -> x-nu -> x-nu+mu -> x+mu -> x
+  t = su3_mdm(su3_load(U, xmn, nu), su3_load(U, xmn, mu));
+  t = su3_mm(t, su3_load(U, xmn_pm, nu));
+  t = su3_mmd(t, su3_load(U, x, mu));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Q.m[i] = cadd(Q.m[i], t.m[i]);
+  Su3 F;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F.m[i * 3 + j] = cscale(0.125, csub(Q.m[i * 3 + j], cconj(Q.m[j * 3 + i])));
+  return F;
+}
+
+// Clover term per chirality in the chiral basis.  With X_l the colour matrices
+//   chirality +: X1 = F_xt - F_yz, X2 = F_yt + F_xz, X3 = F_zt - F_xy
+//   chirality -: X1 = -F_xt - F_yz, X2 = F_xz - F_yt, X3 = -F_zt - F_xy
+// the 6x6 block is c_sw (i/2) sum_l sigma_l (x) X_l, i.e. spin blocks
+//   (0,0) = X3, (0,1) = X1 - i X2, (1,0) = X1 + i X2, (1,1) = -X3, times c_sw i/2.
+// Output: [V][2][6][6] complex128, lexicographic.
+__global__ void k_clover_build(const cd64* __restrict__ U, Lex lx, long V, double csw, cd64* __restrict__ out) {
+  long x = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  Su3 Fxy = field_strength(U, lx, x, 0, 1), Fxz = field_strength(U, lx, x, 0, 2), Fxt = field_strength(U, lx, x, 0, 3);
+  Su3 Fyz = field_strength(U, lx, x, 1, 2), Fyt = field_strength(U, lx, x, 1, 3), Fzt = field_strength(U, lx, x, 2, 3);
+  for (int chi = 0; chi < 2; ++chi) {
+    double s = chi == 0 ? 1.0 : -1.0;
+    cd64* blk = out + (x * 2 + chi) * 36;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        int e = a * 3 + b;
+        cd64 X1 = csub(cscale(s, Fxt.m[e]), Fyz.m[e]);
+        cd64 X2 = cadd(Fxz.m[e], cscale(s, Fyt.m[e]));
+        cd64 X3 = csub(cscale(s, Fzt.m[e]), Fxy.m[e]);
+        cd64 b00 = X3, b11 = cneg(X3);
+        cd64 b01 = csub(X1, ci(X2)), b10 = cadd(X1, ci(X2));
+        // times c_sw * i / 2
+        blk[(0 * 3 + a) * 6 + 0 * 3 + b] = cscale(0.5 * csw, ci(b00));
+        blk[(0 * 3 + a) * 6 + 1 * 3 + b] = cscale(0.5 * csw, ci(b01));
+        blk[(1 * 3 + a) * 6 + 0 * 3 + b] = cscale(0.5 * csw, ci(b10));
+        blk[(1 * 3 + a) * 6 + 1 * 3 + b] = cscale(0.5 * csw, ci(b11));
+      }
+  }
+}
+
+// Pack (4 + m0) + C into the device clover layout, in device site order.
+template <typename R>
+__global__ void k_pack_clover(const cd64* __restrict__ blocks, const int* __restrict__ perm, long V, double m0,
+                              R* __restrict__ out) {
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  long x = perm[s];
+  for (int chi = 0; chi < 2; ++chi) {
+    const cd64* b = blocks + (x * 2 + chi) * 36;
+    R* o = out + (long)chi * 36 * V;
+    for (int i = 0; i < 6; ++i) o[(long)i * V + s] = (R)(4.0 + m0 + b[i * 6 + i].re);
+    int idx = 0;
+    for (int i = 1; i < 6; ++i)
+      for (int j = 0; j < i; ++j, ++idx) {
+        o[(long)(6 + 2 * idx) * V + s] = (R)b[i * 6 + j].re;
+        o[(long)(7 + 2 * idx) * V + s] = (R)b[i * 6 + j].im;
+      }
+  }
+}
+
+template <typename R>
+__global__ void k_pack_links(const cd64* __restrict__ U, const int* __restrict__ perm, long V, int Lt, long Vs,
+                             int antiperiodic, cplx<R>* __restrict__ out) {
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  long x = perm[s];
+  bool last_t = (x / Vs) == Lt - 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    double sg = (mu == 3 && antiperiodic && last_t) ? -1.0 : 1.0;
+    for (int e = 0; e < 9; ++e) {
+      cd64 u = U[(x * 4 + mu) * 9 + e];
+      out[(long)(mu * 9 + e) * V + s] = mkc((R)(sg * u.re), (R)(sg * u.im));
+    }
+  }
+}
+
+// canonical [V][12] (lexicographic) <-> device [12][V] (aggregate-major)
+template <typename Ti, typename To>
+__global__ void k_pack_fermion(const cplx<Ti>* __restrict__ in, const int* __restrict__ perm, long V,
+                               cplx<To>* __restrict__ out) {
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  long x = perm[s];
+  long r = blockIdx.y;
+  in += r * V * 12;
+  out += r * V * 12;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[(long)k * V + s] = ccast<To>(in[x * 12 + k]);
+}
+template <typename Ti, typename To>
+__global__ void k_unpack_fermion(const cplx<Ti>* __restrict__ in, const int* __restrict__ perm, long V,
+                                 cplx<To>* __restrict__ out) {
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  long x = perm[s];
+  long r = blockIdx.y;
+  in += r * V * 12;
+  out += r * V * 12;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[x * 12 + k] = ccast<To>(in[(long)k * V + s]);
+}
+
+// ---------------------------------------------------------------- Wilson-clover operator
+// Spin projection in the chiral basis.  For a hop in direction +mu the spinor
+// (1 - gamma_mu) psi has upper half h and lower half fixed by h; for -mu,
+// (1 + gamma_mu) psi.  Only h (2 spins x 3 colours) is transported by U.
+template <typename R, int MU, bool FWD>
+__device__ inline void project(const cplx<R> (&p)[12], cplx<R> (&h)[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cplx<R> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    if (MU == 0) {  // x: i sigma_1
+      h[c] = FWD ? cadd(p0, ci(p3)) : csub(p0, ci(p3));
+      h[3 + c] = FWD ? cadd(p1, ci(p2)) : csub(p1, ci(p2));
+    } else if (MU == 1) {  // y: i sigma_2 = [[0,1],[-1,0]]
+      h[c] = FWD ? cadd(p0, p3) : csub(p0, p3);
+      h[3 + c] = FWD ? csub(p1, p2) : cadd(p1, p2);
+    } else if (MU == 2) {  // z: i sigma_3
+      h[c] = FWD ? cadd(p0, ci(p2)) : csub(p0, ci(p2));
+      h[3 + c] = FWD ? csub(p1, ci(p3)) : cadd(p1, ci(p3));
+    } else {  // t
+      h[c] = FWD ? csub(p0, p2) : cadd(p0, p2);
+      h[3 + c] = FWD ? csub(p1, p3) : cadd(p1, p3);
+    }
+  }
+}
+
+// acc += -1/2 * reconstruct(h)
+template <typename R, int MU, bool FWD>
+__device__ inline void reconstruct_add(cplx<R> (&acc)[12], const cplx<R> (&h)[6]) {
+  const R m = (R)-0.5;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cplx<R> h0 = h[c], h1 = h[3 + c], l2, l3;
+    if (MU == 0) {
+      l2 = FWD ? cneg(ci(h1)) : ci(h1);
+      l3 = FWD ? cneg(ci(h0)) : ci(h0);
+    } else if (MU == 1) {
+      l2 = FWD ? cneg(h1) : h1;
+      l3 = FWD ? h0 : cneg(h0);
+    } else if (MU == 2) {
+      l2 = FWD ? cneg(ci(h0)) : ci(h0);
+      l3 = FWD ? ci(h1) : cneg(ci(h1));
+    } else {
+      l2 = FWD ? cneg(h0) : h0;
+      l3 = FWD ? cneg(h1) : h1;
+    }
+    acc[c] = cadd(acc[c], cscale(m, h0));
+    acc[3 + c] = cadd(acc[3 + c], cscale(m, h1));
+    acc[6 + c] = cadd(acc[6 + c], cscale(m, l2));
+    acc[9 + c] = cadd(acc[9 + c], cscale(m, l3));
+  }
+}
+
+template <typename R, int MU, bool FWD>
+__device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                           const int* __restrict__ nbr, long V, long s) {
+  const long y = nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s];
+  cplx<R> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = in[(long)k * V + y];
+  cplx<R> h[6];
+  project<R, MU, FWD>(p, h);
+  const long ls = FWD ? s : y;
+  cplx<R> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[(long)(MU * 9 + e) * V + ls];
+  cplx<R> g[6];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<R> t = mkc((R)0, (R)0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (FWD) cfma(t, u[a * 3 + b], h[sp * 3 + b]);
+        else cfmac(t, u[b * 3 + a], h[sp * 3 + b]);  // (U^dag)_{ab} = conj(U_{ba})
+      }
+      g[sp * 3 + a] = t;
+    }
+  reconstruct_add<R, MU, FWD>(acc, g);
+}
+
+// out = sum of the selected terms of D applied to in.
+// terms: bit 0 = Mdiag ((4+m0) + C), bit d (1..8) = Mdir_d.
+template <typename R>
+__global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                 const cplx<R>* __restrict__ U, const R* __restrict__ clov,
+                                                 const int* __restrict__ nbr, long V, int terms,
+                                                 const int* __restrict__ run) {
+  if (run && !*run) return;
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  const long r = blockIdx.y;
+  in += r * 12 * V;
+  out += r * 12 * V;
+  cplx<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mkc((R)0, (R)0);
+  if (terms & 1) {
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      const R* cb = clov + (long)chi * 36 * V + s;
+      cplx<R> p[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) p[k] = in[(long)(chi * 6 + k) * V + s];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        R d = cb[(long)i * V];
+        acc[chi * 6 + i] = cadd(acc[chi * 6 + i], cscale(d, p[i]));
+      }
+      int idx = 0;
+#pragma unroll
+      for (int i = 1; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j, ++idx) {
+          cplx<R> a = mkc(cb[(long)(6 + 2 * idx) * V], cb[(long)(7 + 2 * idx) * V]);
+          cfma(acc[chi * 6 + i], a, p[j]);
+          cfmac(acc[chi * 6 + j], a, p[i]);
+        }
+    }
+  }
+  if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
+  if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[(long)k * V + s] = acc[k];
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_clover_build(const cd64* U, const int L[4], double csw, cd64* out, hipStream_t st) {
+  Lex lx;
+  long V = 1;
+  for (int m = 0; m < 4; ++m) {
+    lx.L[m] = L[m];
+    V *= L[m];
+  }
+  hipLaunchKernelGGL(k_clover_build, dim3(nblocks(V, 128)), dim3(128), 0, st, U, lx, V, csw, out);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
+void launch_pack_clover(const cd64* blocks, const int* perm, long V, double m0, R* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_clover<R>, dim3(nblocks(V)), dim3(kBlock), 0, st, blocks, perm, V, m0, out);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_pack_clover<double>(const cd64*, const int*, long, double, double*, hipStream_t);
+template void launch_pack_clover<float>(const cd64*, const int*, long, double, float*, hipStream_t);
+
+template <typename R>
+void launch_pack_links(const cd64* U, const int* perm, const int L[4], int antiperiodic, cplx<R>* out,
+                       hipStream_t st) {
+  long V = (long)L[0] * L[1] * L[2] * L[3];
+  long Vs = (long)L[0] * L[1] * L[2];
+  hipLaunchKernelGGL(k_pack_links<R>, dim3(nblocks(V)), dim3(kBlock), 0, st, U, perm, V, L[3], Vs, antiperiodic,
+                     out);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_pack_links<double>(const cd64*, const int*, const int*, int, cd64*, hipStream_t);
+template void launch_pack_links<float>(const cd64*, const int*, const int*, int, cf32*, hipStream_t);
+
+template <typename Ti, typename To>
+void launch_pack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_pack_fermion<Ti, To>), dim3(nblocks(V), nrhs), dim3(kBlock), 0, st, in, perm, V, out);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename Ti, typename To>
+void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_unpack_fermion<Ti, To>), dim3(nblocks(V), nrhs), dim3(kBlock), 0, st, in, perm, V, out);
+  WCMG_CHECK_LAUNCH();
+}
+#define INST_PACK(Ti, To)                                                                                  \
+  template void launch_pack_fermion<Ti, To>(const cplx<Ti>*, const int*, long, int, cplx<To>*, hipStream_t); \
+  template void launch_unpack_fermion<Ti, To>(const cplx<Ti>*, const int*, long, int, cplx<To>*, hipStream_t);
+INST_PACK(double, double)
+INST_PACK(double, float)
+INST_PACK(float, float)
+INST_PACK(float, double)
+
+template <typename R>
+void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
+                   int terms, int nrhs, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_wilson<R>, dim3(nblocks(V), nrhs), dim3(kBlock), 0, st, in, out, U, clov, nbr, V, terms, run);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
+                                    const int*, hipStream_t);
+template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
+                                   const int*, hipStream_t);
+
+}  // namespace wcmg

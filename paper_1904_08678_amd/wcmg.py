@@ -1,0 +1,303 @@
+"""ctypes binding of the wcmg C ABI (include/wcmg.h).
+
+Torch supplies device memory and the stream; every operation runs in the HIP
+kernels of libwcmg.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+F64, F32, BF16 = 0, 1, 2
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libwcmg.so")
+_lib = None
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DIMS", 3: "ERR_STATE", 4: "ERR_HIP", 5: "ERR_NOMEM", 6: "ERR_BREAKDOWN",
+          7: "ERR_NOCONV", 8: "ERR_NAN"}
+
+
+class WcmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("dims", C.c_int32 * 4), ("m0", C.c_double), ("c_sw", C.c_double), ("antiperiodic_t", C.c_int32),
+        ("n_levels", C.c_int32), ("block", (C.c_int32 * 4) * 3), ("n_vec", C.c_int32 * 3),
+        ("relax_sweeps", C.c_int32), ("refine_iters", C.c_int32), ("post_smooth", C.c_int32),
+        ("coarse_restart", C.c_int32), ("coarse_maxit", C.c_int32), ("coarse_fixed_iters", C.c_int32),
+        ("coarse_tol", C.c_double), ("kcycle", C.c_int32), ("kcycle_maxit", C.c_int32), ("kcycle_tol", C.c_double),
+        ("outer_restart", C.c_int32), ("outer_maxit", C.c_int32), ("outer_tol", C.c_double),
+        ("cycle_prec", C.c_int32), ("coarse_store_prec", C.c_int32), ("setup_prec", C.c_int32),
+        ("reserved", C.c_int32 * 5),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("converged", C.c_int32), ("true_rel_res", C.c_double),
+                ("t_solve_s", C.c_double), ("coarse_iters", C.c_int64), ("cycles", C.c_int64)]
+
+
+def lib():
+    """Load libwcmg.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError("libwcmg.so is not built; run `python -m paper_1904_08678_amd.build`")
+        l = C.CDLL(library_path)
+        vp, ip = C.c_void_p, C.c_int
+        l.wcmg_default_params.argtypes = [C.POINTER(Params)]
+        l.wcmg_create.argtypes = [C.POINTER(Params), vp, C.POINTER(vp)]
+        l.wcmg_destroy.argtypes = [vp]
+        l.wcmg_last_error.argtypes = [vp]
+        l.wcmg_last_error.restype = C.c_char_p
+        for name in ("wcmg_set_gauge", "wcmg_set_clover", "wcmg_get_clover"):
+            getattr(l, name).argtypes = [vp, vp]
+        l.wcmg_set_null_vectors.argtypes = [vp, ip, vp, ip]
+        for name in ("wcmg_get_null_vectors", "wcmg_get_prolongator", "wcmg_rebuild_from_vectors",
+                     "wcmg_get_coarse_op", "wcmg_set_coarse_op"):
+            getattr(l, name).argtypes = [vp, ip, vp]
+        l.wcmg_setup.argtypes = [vp]
+        l.wcmg_refine.argtypes = [vp, ip]
+        l.wcmg_get_aggregate_map.argtypes = [vp, ip, vp, vp]
+        for name in ("wcmg_apply_D", "wcmg_restrict", "wcmg_prolong"):
+            getattr(l, name).argtypes = [vp, ip, vp, vp, ip, ip]
+        l.wcmg_cycle.argtypes = [vp, vp, vp]
+        l.wcmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(SolveInfo)]
+        l.wcmg_timers.argtypes = [vp, C.POINTER(C.c_double), ip]
+        l.wcmg_profile_enable.argtypes = [vp, C.c_char_p, ip]
+        l.wcmg_profile_stats.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        l.wcmg_coarse_create.argtypes = [C.POINTER(C.c_int32), ip, ip, vp, C.POINTER(vp)]
+        l.wcmg_coarse_destroy.argtypes = [vp]
+        l.wcmg_coarse_set.argtypes = [vp, vp, ip]
+        l.wcmg_coarse_apply.argtypes = [vp, vp, vp, ip]
+        l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
+        l.wcmg_coarse_last_error.argtypes = [vp]
+        l.wcmg_coarse_last_error.restype = C.c_char_p
+        _lib = l
+    return _lib
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().wcmg_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "dims":
+            for m in range(4):
+                p.dims[m] = int(v[m])
+        elif k == "block":
+            for l, b in enumerate(v):
+                for m in range(4):
+                    p.block[l][m] = int(b[m])
+        elif k == "n_vec":
+            for l, n in enumerate(v):
+                p.n_vec[l] = int(n)
+        elif k == "reserved":
+            for i, n in enumerate(v):
+                p.reserved[i] = int(n)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("wcmg takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("wcmg takes contiguous tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _cdtype(prec):
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+class Context:
+    """Multigrid context for one fine lattice (wcmg_ctx)."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        self.p = params if params is not None else default_params(**kw)
+        h = C.c_void_p()
+        st = lib().wcmg_create(C.byref(self.p), _stream(), C.byref(h))
+        if st:
+            raise WcmgError(st, lib().wcmg_last_error(None).decode())
+        self.h = h
+        self.dims = tuple(self.p.dims)
+        self.V = int(self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3])
+        self.nlev = self.p.n_levels
+        self.level_dims = [self.dims]
+        for l in range(self.nlev - 1):
+            self.level_dims.append(tuple(self.level_dims[-1][m] // self.p.block[l][m] for m in range(4)))
+        self.ns = [12] + [2 * self.p.n_vec[l] for l in range(self.nlev - 1)]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.wcmg_destroy(self.h)
+            self.h = None
+
+    def _chk(self, st):
+        if st:
+            raise WcmgError(st, lib().wcmg_last_error(self.h).decode())
+
+    def sites(self, level):
+        d = self.level_dims[level]
+        return int(d[0] * d[1] * d[2] * d[3])
+
+    # ---- fields
+    def set_gauge(self, U: torch.Tensor):
+        assert U.dtype == torch.complex128 and U.numel() == self.V * 36
+        self._chk(lib().wcmg_set_gauge(self.h, _ptr(U)))
+
+    def set_clover(self, blocks: torch.Tensor | None):
+        self._chk(lib().wcmg_set_clover(self.h, None if blocks is None else _ptr(blocks)))
+
+    def get_clover(self) -> torch.Tensor:
+        out = torch.empty((self.V, 2, 6, 6), dtype=torch.complex128, device="cuda")
+        self._chk(lib().wcmg_get_clover(self.h, _ptr(out)))
+        return out
+
+    def set_null_vectors(self, level, v: torch.Tensor):
+        nv = self.p.n_vec[level]
+        assert v.dtype == torch.complex128 and v.numel() == nv * self.sites(level) * self.ns[level]
+        self._chk(lib().wcmg_set_null_vectors(self.h, level, _ptr(v), nv))
+
+    def _level_vectors(self, fn, level):
+        out = torch.empty((self.p.n_vec[level], self.sites(level) * self.ns[level]), dtype=torch.complex128,
+                          device="cuda")
+        self._chk(fn(self.h, level, _ptr(out)))
+        return out
+
+    def null_vectors(self, level):
+        return self._level_vectors(lib().wcmg_get_null_vectors, level)
+
+    def prolongator(self, level):
+        return self._level_vectors(lib().wcmg_get_prolongator, level)
+
+    def rebuild_from_vectors(self, level, v: torch.Tensor):
+        self._chk(lib().wcmg_rebuild_from_vectors(self.h, level, _ptr(v.contiguous())))
+
+    def setup(self):
+        self._chk(lib().wcmg_setup(self.h))
+
+    def refine(self, iters):
+        self._chk(lib().wcmg_refine(self.h, int(iters)))
+
+    def aggregate_map(self, level):
+        import numpy as np
+        n = self.sites(level)
+        c = np.zeros(n, np.int32)
+        o = np.zeros(n, np.int32)
+        self._chk(lib().wcmg_get_aggregate_map(self.h, level, c.ctypes.data_as(C.c_void_p),
+                                               o.ctypes.data_as(C.c_void_p)))
+        return c, o
+
+    def coarse_op(self, level) -> torch.Tensor:
+        nb = self.ns[level]
+        out = torch.empty((self.sites(level), 9, nb, nb), dtype=torch.complex128, device="cuda")
+        self._chk(lib().wcmg_get_coarse_op(self.h, level, _ptr(out)))
+        return out
+
+    def set_coarse_op(self, level, blocks: torch.Tensor):
+        assert blocks.dtype == torch.complex128
+        self._chk(lib().wcmg_set_coarse_op(self.h, level, _ptr(blocks.contiguous())))
+
+    # ---- operators
+    def apply_D(self, level, x: torch.Tensor, prec=F64) -> torch.Tensor:
+        nrhs = x.numel() // (self.sites(level) * self.ns[level])
+        assert x.dtype == _cdtype(prec)
+        out = torch.empty_like(x)
+        self._chk(lib().wcmg_apply_D(self.h, level, _ptr(x), _ptr(out), nrhs, prec))
+        return out
+
+    def restrict(self, level, fine: torch.Tensor, prec=F64) -> torch.Tensor:
+        nrhs = fine.numel() // (self.sites(level) * self.ns[level])
+        out = torch.empty((nrhs, self.sites(level + 1), self.ns[level + 1]), dtype=fine.dtype, device="cuda")
+        self._chk(lib().wcmg_restrict(self.h, level, _ptr(fine), _ptr(out), nrhs, prec))
+        return out
+
+    def prolong(self, level, coarse: torch.Tensor, prec=F64) -> torch.Tensor:
+        nrhs = coarse.numel() // (self.sites(level + 1) * self.ns[level + 1])
+        out = torch.empty((nrhs, self.sites(level), self.ns[level]), dtype=coarse.dtype, device="cuda")
+        self._chk(lib().wcmg_prolong(self.h, level, _ptr(coarse), _ptr(out), nrhs, prec))
+        return out
+
+    def cycle(self, r: torch.Tensor) -> torch.Tensor:
+        out = torch.empty_like(r)
+        self._chk(lib().wcmg_cycle(self.h, _ptr(r), _ptr(out)))
+        return out
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, check=True):
+        nrhs = b.numel() // (self.V * 12)
+        if x is None:
+            x = torch.zeros_like(b)
+        info = (SolveInfo * nrhs)()
+        st = lib().wcmg_solve(self.h, _ptr(b), _ptr(x), nrhs, info)
+        if check and st not in (0,):
+            self._chk(st)
+        infos = [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
+                      t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters, cycles=i.cycles) for i in info]
+        return x, infos, st
+
+    def timers(self):
+        out = (C.c_double * 6)()
+        self._chk(lib().wcmg_timers(self.h, out, 6))
+        return dict(zip(["setup", "relax", "gram_schmidt", "coarsen", "refine", "solve"], list(out)))
+
+    def profile(self, family, enable=True):
+        self._chk(lib().wcmg_profile_enable(self.h, family.encode(), int(enable)))
+
+    def profile_stats(self, family):
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        self._chk(lib().wcmg_profile_stats(self.h, family.encode(), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+
+class CoarseOperator:
+    """Standalone coarse operator (wcmg_coarse): nine Nb x Nb blocks per site."""
+
+    def __init__(self, dims, nb, store_prec=F32):
+        d = (C.c_int32 * 4)(*[int(x) for x in dims])
+        h = C.c_void_p()
+        st = lib().wcmg_coarse_create(d, int(nb), int(store_prec), _stream(), C.byref(h))
+        if st:
+            raise WcmgError(st, "wcmg_coarse_create failed")
+        self.h = h
+        self.dims = tuple(dims)
+        self.nb = nb
+        self.store = store_prec
+        self.Vc = int(dims[0] * dims[1] * dims[2] * dims[3])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.wcmg_coarse_destroy(self.h)
+            self.h = None
+
+    def _chk(self, st):
+        if st:
+            raise WcmgError(st, lib().wcmg_coarse_last_error(self.h).decode())
+
+    def set(self, blocks: torch.Tensor):
+        prec = F64 if blocks.dtype == torch.complex128 else F32
+        self._chk(lib().wcmg_coarse_set(self.h, _ptr(blocks), prec))
+
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        nrhs = x.numel() // (self.Vc * self.nb)
+        out = torch.empty_like(x) if out is None else out
+        self._chk(lib().wcmg_coarse_apply(self.h, _ptr(x), _ptr(out), nrhs))
+        return out
+
+    def time(self, x: torch.Tensor, out: torch.Tensor, reps=20) -> float:
+        nrhs = x.numel() // (self.Vc * self.nb)
+        ms = C.c_double(0.0)
+        self._chk(lib().wcmg_coarse_time(self.h, _ptr(x), _ptr(out), nrhs, int(reps), C.byref(ms)))
+        return ms.value

@@ -1,0 +1,320 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: integer maps bit-exact; FP64 results within 1e-12 normwise relative;
+FP32 arithmetic within 1e-5; BF16-stored coarse blocks compared with the
+oracle applied to the same BF16-rounded blocks, within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as syn
+from tests import brute_force as bf
+
+pytestmark = pytest.mark.gpu
+
+
+def wc():
+    import paper_1904_08678_amd as w
+    return w
+
+
+def rel(a, b):
+    a = np.asarray(a).reshape(-1)
+    b = np.asarray(b).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def bf16_round(x):
+    """FP64 -> FP32 -> BF16 (round to nearest even), returned as FP64."""
+    def r(a):
+        f = np.ascontiguousarray(a, dtype=np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return r(x.real) + 1j * r(x.imag)
+
+
+def make_pair(L, eps, seed, m0=-0.05, csw=1.0, blocks=((2, 2, 2, 2),), nv=(4,), n_levels=2, **kw):
+    """GPU context and oracle hierarchy built from the same parameters and inputs."""
+    w = wc()
+    U = syn.gauge_field(L, eps, seed)
+    gkw = dict(dims=L, m0=m0, c_sw=csw, n_levels=n_levels, block=blocks, n_vec=nv)
+    okw = dict(m0=m0, csw=csw, n_levels=n_levels, blocks=blocks, nv=nv)
+    for k, v in kw.items():
+        gkw[k] = v
+        if k in oracle.DEFAULTS:
+            okw[k] = v
+    ctx = w.Context(**gkw)
+    ctx.set_gauge(dev(U))
+    H = oracle.Hierarchy(L, U, **okw)
+    return ctx, H, U
+
+
+# ---------------------------------------------------------------- a1 aggregation
+@pytest.mark.parametrize("L,block", [((8, 4, 4, 8), (4, 2, 2, 4)), ((4, 6, 4, 8), (2, 3, 2, 2))])
+def test_aggregation_map_bit_exact(L, block):
+    w = wc()
+    ctx = w.Context(dims=L, n_levels=2, block=(block,), n_vec=(4,))
+    c, o = ctx.aggregate_map(0)
+    oc, oo, _ = oracle.agg_map(L, block)
+    assert np.array_equal(c, oc) and np.array_equal(o, oo)
+
+
+def test_aggregation_map_second_level_bit_exact():
+    w = wc()
+    L = (8, 8, 8, 16)
+    ctx = w.Context(dims=L, n_levels=3, block=((2, 2, 2, 2), (2, 2, 2, 4)), n_vec=(4, 4))
+    c, o = ctx.aggregate_map(1)
+    oc, oo, _ = oracle.agg_map((4, 4, 4, 8), (2, 2, 2, 4))
+    assert np.array_equal(c, oc) and np.array_equal(o, oo)
+
+
+def test_dims_errors():
+    w = wc()
+    with pytest.raises(w.WcmgError) as e:
+        w.Context(dims=(6, 4, 4, 4), n_levels=2, block=((4, 2, 2, 2),), n_vec=(4,))
+    assert e.value.code == 2
+    with pytest.raises(w.WcmgError) as e:
+        w.Context(dims=(4, 4, 4, 4), n_levels=2, block=((4, 2, 2, 2),), n_vec=(4,))  # coarse extent 1
+    assert e.value.code == 2
+
+
+# ---------------------------------------------------------------- a2 clover and D
+def test_clover_fp64_parity():
+    L = (4, 4, 4, 8)
+    ctx, H, U = make_pair(L, 0.3, 201)
+    C = oracle.clover(L, U, 1.0)
+    ref = np.stack([C[:, :6, :6], C[:, 6:, 6:]], axis=1)
+    got = host(ctx.get_clover())
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("L,block", [((4, 4, 4, 8), (2, 2, 2, 2)), ((4, 6, 4, 8), (2, 3, 2, 4))])
+def test_dslash_parity(L, block):
+    w = wc()
+    ctx, H, U = make_pair(L, 0.3, 202, m0=-0.08, blocks=(block,))
+    V = int(np.prod(L))
+    psi = syn.complex_gaussian((3, V, 4, 3), 203)
+    ref = np.stack([H.apply(0, psi[r]).reshape(V, 4, 3) for r in range(3)])
+    got64 = host(ctx.apply_D(0, dev(psi), w.F64))
+    assert rel(got64, ref) < 1e-13
+    got32 = host(ctx.apply_D(0, dev(psi.astype(np.complex64)), w.F32))
+    assert rel(got32, ref) < 1e-5
+
+
+def test_dslash_single_point_source_response():
+    """A point source picks out one column of D: diagonal block plus 8 hops."""
+    w = wc()
+    L = (4, 4, 4, 4)
+    ctx, H, U = make_pair(L, 0.3, 204)
+    e = np.zeros((256, 4, 3), np.complex128)
+    e[37, 2, 1] = 1.0
+    got = host(ctx.apply_D(0, dev(e), w.F64))
+    ref = H.apply(0, e).reshape(256, 4, 3)
+    assert rel(got, ref) < 1e-14
+    assert np.count_nonzero(np.abs(got).sum(axis=(1, 2)) > 1e-15) == 9
+
+
+# ---------------------------------------------------------------- a5 coarse apply
+@pytest.mark.parametrize("Lc,nb", [((3, 2, 4, 3), 8), ((2, 2, 2, 2), 16), ((4, 4, 4, 8), 24), ((3, 3, 2, 2), 32),
+                                    ((2, 3, 2, 2), 6)])
+def test_coarse_apply_parity_all_precisions(Lc, nb):
+    w = wc()
+    Vc = int(np.prod(Lc))
+    blocks = syn.complex_gaussian((Vc, 9, nb, nb), 301)
+    phi = syn.complex_gaussian((2, Vc, nb), 302)
+    ref = oracle.coarse_apply(Lc, blocks, phi)
+    for store in (w.F64, w.F32, w.BF16):
+        if store == w.BF16 and nb % 4:
+            with pytest.raises(w.WcmgError):
+                w.CoarseOperator(Lc, nb, store)
+            continue
+        op = w.CoarseOperator(Lc, nb, store)
+        op.set(dev(blocks))
+        if store == w.F64:
+            got = host(op.apply(dev(phi)))
+            assert rel(got, ref) < 1e-14
+        elif store == w.F32:
+            got = host(op.apply(dev(phi.astype(np.complex64))))
+            assert rel(got, ref) < 1e-5
+        else:
+            ref_b = oracle.coarse_apply(Lc, bf16_round(blocks), phi)
+            got = host(op.apply(dev(phi.astype(np.complex64))))
+            assert rel(got, ref_b) < 1e-5
+            assert rel(got, ref) < 2e-2  # storage error of BF16 alone
+
+
+# ---------------------------------------------------------------- a3/a7 setup parity
+@pytest.mark.parametrize("L,block,nv,m0", [((4, 4, 4, 4), (2, 2, 2, 2), 8, -0.05), ((8, 8, 8, 8), (4, 4, 4, 4), 12, -0.08)])
+def test_setup_fp64_parity(L, block, nv, m0):
+    """Relaxation (MR on D x = 0), chirality-split Gram-Schmidt and Galerkin
+    coarsening from identical start vectors: vectors, P and D_c to 1e-12."""
+    ctx, H, U = make_pair(L, 0.3, 401, m0=m0, blocks=(block,), nv=(nv,))
+    V = int(np.prod(L))
+    start = syn.complex_gaussian((nv, V, 12), 402)
+    ctx.set_null_vectors(0, dev(start))
+    H.set_start(0, start)
+    ctx.setup()
+    H.setup()
+    assert rel(host(ctx.null_vectors(0)), H.vectors(0)) < 1e-12
+    assert rel(host(ctx.prolongator(0)), H.P(0)) < 1e-12
+    assert rel(host(ctx.coarse_op(1)), H.coarse(1)) < 1e-12
+
+
+def test_galerkin_from_given_vectors_parity():
+    """Coarsening alone: the same near-null vectors in, D_c out (1e-12)."""
+    L, block, nv = (4, 4, 4, 8), (2, 2, 2, 4), 6
+    ctx, H, U = make_pair(L, 0.3, 403, blocks=(block,), nv=(nv,))
+    V = int(np.prod(L))
+    vecs = syn.complex_gaussian((nv, V, 12), 404)
+    ctx.set_null_vectors(0, dev(vecs))
+    ctx.rebuild_from_vectors(0, dev(vecs))
+    H.set_start(0, vecs)
+    H.setup()
+    H.set_vectors(0, vecs)
+    assert rel(host(ctx.prolongator(0)), H.P(0)) < 1e-12
+    got = host(ctx.coarse_op(1))
+    assert rel(got, H.coarse(1)) < 1e-12
+    Dc = bf.dense_from_blocks((2, 2, 2, 2), got)
+    s3 = np.kron(np.eye(16), np.diag([1.0] * nv + [-1.0] * nv))
+    assert np.max(np.abs(s3 @ Dc @ s3 - Dc.conj().T)) < 1e-12 * np.max(np.abs(Dc))
+
+
+def test_breakdown_reported():
+    w = wc()
+    L, block, nv = (4, 4, 4, 4), (2, 2, 2, 2), 4
+    ctx, H, U = make_pair(L, 0.3, 405, blocks=(block,), nv=(nv,))
+    vecs = syn.complex_gaussian((nv, 256, 12), 406)
+    vecs[2] = 3.0 * vecs[0]
+    with pytest.raises(w.WcmgError) as e:
+        ctx.rebuild_from_vectors(0, dev(vecs))
+    assert e.value.code == 6
+
+
+# ---------------------------------------------------------------- a4 restrict / prolong
+def test_restrict_prolong_parity():
+    w = wc()
+    L, block, nv = (8, 4, 4, 8), (4, 2, 2, 4), 6
+    ctx, H, U = make_pair(L, 0.3, 501, blocks=(block,), nv=(nv,))
+    V = int(np.prod(L))
+    ctx.set_null_vectors(0, dev(syn.complex_gaussian((nv, V, 12), 502)))
+    ctx.setup()
+    Pv = host(ctx.prolongator(0))
+    v = syn.complex_gaussian((2, V, 12), 503)
+    ref = oracle.restrict(L, block, 12, Pv, v)
+    assert rel(host(ctx.restrict(0, dev(v), w.F64)), ref) < 1e-13
+    assert rel(host(ctx.restrict(0, dev(v.astype(np.complex64)), w.F32)), ref) < 1e-5
+    Vc = V // 64
+    phi = syn.complex_gaussian((2, Vc, 2 * nv), 504)
+    ref = oracle.prolong(L, block, 12, Pv, phi)
+    assert rel(host(ctx.prolong(0, dev(phi), w.F64)), ref) < 1e-13
+    assert rel(host(ctx.prolong(0, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
+    # R P = 1
+    rp = host(ctx.restrict(0, ctx.prolong(0, dev(phi), w.F64), w.F64))
+    assert rel(rp, phi) < 1e-13
+
+
+def test_coarse_level_apply_parity():
+    w = wc()
+    L, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 8
+    ctx, H, U = make_pair(L, 0.3, 505, blocks=(block,), nv=(nv,))
+    ctx.set_null_vectors(0, dev(syn.complex_gaussian((nv, 512, 12), 506)))
+    ctx.setup()
+    blocks = host(ctx.coarse_op(1))
+    Lc = (2, 2, 2, 4)
+    phi = syn.complex_gaussian((2, 32, 16), 507)
+    ref = oracle.coarse_apply(Lc, blocks, phi)
+    assert rel(host(ctx.apply_D(1, dev(phi), w.F64)), ref) < 1e-14
+    assert rel(host(ctx.apply_D(1, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
+    refb = oracle.coarse_apply(Lc, bf16_round(blocks), phi)
+    assert rel(host(ctx.apply_D(1, dev(phi.astype(np.complex64)), w.BF16)), refb) < 1e-5
+
+
+# ---------------------------------------------------------------- a8 cycle and solve
+def test_cycle_fp64_parity_fixed_coarse_iterations():
+    L, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 8
+    ctx, H, U = make_pair(L, 0.3, 601, blocks=(block,), nv=(nv,), coarse_fixed_iters=12)
+    V = 512
+    start = syn.complex_gaussian((nv, V, 12), 602)
+    ctx.set_null_vectors(0, dev(start))
+    H.set_start(0, start)
+    ctx.setup()
+    H.setup()
+    r = syn.complex_gaussian((V, 4, 3), 603)
+    got = host(ctx.cycle(dev(r)))
+    ref = H.cycle(0, r).reshape(V, 4, 3)
+    assert rel(got, ref) < 1e-11
+
+
+def test_solve_fp64_config1():
+    """Config 1: 4^4, 2^4 aggregates, Nv 8, MR(4), FGMRES(16) to 1e-10."""
+    L = (4, 4, 4, 4)
+    ctx, H, U = make_pair(L, 0.3, 101, m0=-0.05, blocks=((2, 2, 2, 2),), nv=(8,), outer_restart=16)
+    start = syn.complex_gaussian((8, 256, 12), 102)
+    ctx.set_null_vectors(0, dev(start))
+    H.set_start(0, start)
+    ctx.setup()
+    H.setup()
+    b = syn.complex_gaussian((256, 4, 3), 103)
+    x, info, st = ctx.solve(dev(b))
+    xo, ito, rro, sto = H.solve(b)
+    assert st == 0 and info[0]["converged"] and info[0]["true_rel_res"] <= 1e-10
+    assert abs(info[0]["outer_iters"] - ito) <= 1
+    xg = host(x).reshape(-1)
+    # both are solutions to 1e-10; their difference is bounded by the conditioning
+    assert rel(xg, xo) < 1e-8
+    r = b.reshape(-1) - H.apply(0, xg)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_solve_mixed_precision_bf16_blocks():
+    """FP32 cycle with BF16-stored coarse blocks under the FP64 outer FGMRES:
+    the true residual still reaches 1e-10 (the outer solver refines)."""
+    w = wc()
+    L = (8, 8, 8, 8)
+    ctx, H, U = make_pair(L, 0.25, 701, m0=-0.05, blocks=((4, 4, 4, 4),), nv=(12,), cycle_prec=w.F32,
+                          coarse_store_prec=w.BF16, setup_prec=w.F32)
+    ctx.set_null_vectors(0, dev(syn.complex_gaussian((12, 4096, 12), 702)))
+    ctx.setup()
+    b = syn.complex_gaussian((4096, 4, 3), 703)
+    x, info, st = ctx.solve(dev(b))
+    assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+    r = b.reshape(-1) - H.apply(0, host(x).reshape(-1))
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_three_level_kcycle_solve():
+    w = wc()
+    L = (8, 8, 8, 8)
+    ctx, H, U = make_pair(L, 0.25, 111, m0=-0.05, n_levels=3, blocks=((2, 2, 2, 2), (2, 2, 2, 2)), nv=(6, 6),
+                          kcycle=1, outer_restart=20)
+    ctx.set_null_vectors(0, dev(syn.complex_gaussian((6, 4096, 12), 112)))
+    ctx.set_null_vectors(1, dev(syn.complex_gaussian((6, 256, 12), 114)))
+    ctx.setup()
+    ctx.refine(1)
+    b = syn.complex_gaussian((4096, 4, 3), 113)
+    x, info, st = ctx.solve(dev(b))
+    assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+
+
+def test_state_errors():
+    w = wc()
+    ctx = w.Context(dims=(4, 4, 4, 4), n_levels=2, block=((2, 2, 2, 2),), n_vec=(4,))
+    with pytest.raises(w.WcmgError) as e:
+        ctx.setup()  # no gauge field
+    assert e.value.code == 3
+    ctx.set_gauge(dev(syn.gauge_field((4, 4, 4, 4), 0.3, 1)))
+    with pytest.raises(w.WcmgError) as e:
+        ctx.solve(dev(np.ones((256, 4, 3), np.complex128)))
+    assert e.value.code == 3
