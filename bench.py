@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the Wilson-clover multigrid hot path on one MI355X.
+
+Workload (two-level MG on a 16^3 x 32 lattice): SU(3) links U = exp(i 0.25 H)
+with H Gaussian traceless Hermitian (seeded), c_sw = 1, m0 = -0.08,
+antiperiodic t, 4^4 aggregates (coarse lattice 4^3 x 8), 12 near-null vectors
+split by chirality to Nb = 24, 20 MR relaxation sweeps plus one iteration of the
+iterative setup, MR(4) post-smoothing, coarse GMRES(20) to 0.05, outer FP64
+FGMRES(20) to a true relative residual of 1e-10, Gaussian right-hand side.
+
+One step = the whole path on that input: setup (relaxation, chirality-split
+Gram-Schmidt, Galerkin coarsening, refinement) and the mixed-precision solve
+(FP32 smoother, restriction, prolongation and coarse arithmetic with FP32
+coarse blocks; FP64 outer solver).  `value` is the solve time of the mixed
+solve (seconds to 1e-10); the plain FP64 solve, the coarse-apply bandwidth on a
+large synthetic coarse lattice, the roofline of the dominant solve kernel and
+the CPU oracle are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MG solve s to 1e-10 rel. residual (mixed/batched vs FP64); coarse-apply GB/s"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD = dict(
+    name="two-level MG, 16^3x32, Nb=24 (4^4 aggregates, 12 vectors), 1 refinement iteration, FGMRES(20) to 1e-10",
+    L=(16, 16, 16, 32), eps=0.25, m0=-0.08, csw=1.0, block=(4, 4, 4, 4), nv=12, relax=20, refine=1, seed=102,
+)
+
+
+def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int) -> float:
+    """Bytes a launch must move at minimum (each operand read once, output written once)."""
+    if family == "dslash_f64":
+        return 1536.0 * V          # links 576 + clover 576 + in 192 + out 192 (FP64)
+    if family == "dslash_f32":
+        return 768.0 * V           # links 288 + clover 288 + in 96 + out 96 (FP32)
+    if family.startswith("coarse_apply"):
+        sb = {"coarse_apply_f64": 16, "coarse_apply_f32": 8, "coarse_apply_bf16": 4}[family]
+        sv = 16 if family.endswith("f64") else 8
+        return (9.0 * nb * nb * sb + 2.0 * nb * sv) * Vc
+    if family in ("restrict_f32", "prolong_f32"):
+        return (nv * 12 * 8.0 + 12 * 8.0) * V
+    if family in ("restrict_f64", "prolong_f64"):
+        return (nv * 12 * 16.0 + 12 * 16.0) * V
+    return float("nan")
+
+
+def make_inputs(wl):
+    import numpy as np
+    import synthetic as syn
+    L = wl["L"]
+    V = int(np.prod(L))
+    s = syn.config_seeds(wl["seed"])
+    U = syn.gauge_field(L, wl["eps"], s["gauge"])
+    start = syn.start_vectors(wl["nv"], V, 12, s["start"])
+    b = syn.complex_gaussian((V, 4, 3), s["rhs"])
+    return U, start, b
+
+
+def make_context(w, wl, mixed: bool):
+    kw = dict(dims=wl["L"], m0=wl["m0"], c_sw=wl["csw"], n_levels=2, block=(wl["block"],), n_vec=(wl["nv"],),
+              relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000)
+    if mixed:
+        kw.update(cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32)
+    return w.Context(**kw)
+
+
+def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20):
+    """Coarse apply on a coarse lattice far larger than the 256 MB last-level cache."""
+    out = {}
+    Vc = dims[0] * dims[1] * dims[2] * dims[3]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    blocks = torch.randn((Vc, 9, nb, nb), dtype=torch.complex64, device="cuda", generator=g)
+    for store in stores or (w.F32, w.BF16, w.F64):
+        name = {w.F64: "f64", w.F32: "f32", w.BF16: "bf16"}[store]
+        op = w.CoarseOperator(dims, nb, store)
+        op.set(blocks)
+        vdt = torch.complex128 if store == w.F64 else torch.complex64
+        x = torch.randn((Vc, nb), dtype=vdt, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        op.time(x, y, reps=3)
+        ms = op.time(x, y, reps=reps)
+        sb = {"f64": 16, "f32": 8, "bf16": 4}[name]
+        sv = 16 if name == "f64" else 8
+        byts = (9.0 * nb * nb * sb + 2.0 * nb * sv) * Vc
+        out[name] = {"ms": ms, "GB_s": byts / ms / 1e6, "frac": byts / ms / 1e6 / HBM_PEAK_GBS,
+                     "bytes_per_launch": byts}
+        del op, x, y
+        torch.cuda.synchronize()
+    del blocks
+    torch.cuda.empty_cache()
+    return {"coarse_dims": list(dims), "Vc": Vc, "nb": nb, "per_store": out}
+
+
+def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
+    """Oracle (plain FP64 C++) on the host cores: seconds per outer FGMRES
+    iteration at the same lattice and parameters, scaled to the GPU's outer
+    iteration count.  The oracle's own setup (20 relaxation sweeps, no
+    refinement) runs untimed first."""
+    import numpy as np
+    import oracle
+    H = oracle.Hierarchy(wl["L"], U, m0=wl["m0"], csw=wl["csw"], blocks=(wl["block"],), nv=(wl["nv"],),
+                         relax_sweeps=wl["relax"], outer_restart=20, outer_maxit=sample_iters)
+    H.set_start(0, start)
+    H.setup()
+    t0 = time.perf_counter()
+    x, it, rel, st = H.solve(b)
+    dt = time.perf_counter() - t0
+    per_iter = dt / max(it, 1)
+    return {"value": per_iter * gpu_outer_iters, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d outer FGMRES iterations of the oracle FP64 two-level solve on the same 16^3x32 input "
+                      "(%.2f s, %.3f s/iteration), scaled to the GPU's %d outer iterations; oracle setup "
+                      "(20 MR sweeps, no refinement) untimed" % (it, dt, per_iter, gpu_outer_iters),
+            "host_cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-mk", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; N=%d is not supported (the path would shard by 4D domain "
+              "decomposition, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1904_08678_amd as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = WORKLOAD
+    L = wl["L"]
+    V = int(np.prod(L))
+    Vc = V // int(np.prod(wl["block"]))
+    nb = 2 * wl["nv"]
+    print("[bench] generating inputs", file=sys.stderr, flush=True)
+    U, start, b = make_inputs(wl)
+    Ud, startd, bd = torch.from_numpy(U).cuda(), torch.from_numpy(start).cuda(), torch.from_numpy(b).cuda()
+
+    ctx = make_context(w, wl, mixed=True)
+    ctx.set_gauge(Ud)
+    ctx.set_null_vectors(0, startd)
+    families = ["dslash_f64", "dslash_f32", "coarse_apply_f32", "restrict_f32", "prolong_f32"]
+
+    def step(profile=False):
+        ctx.setup()
+        setup_s = ctx.timers()["setup"]
+        for f in families:
+            ctx.profile(f, profile)
+        x, info, st = ctx.solve(bd)
+        for f in families:
+            ctx.profile(f, False)
+        return setup_s, info[0], st
+
+    for i in range(args.warmup):
+        s, inf, st = step()
+        print("[bench] warmup %d: setup %.3f s solve %.4f s iters %d res %.2e" % (
+            i, s, inf["t_solve_s"], inf["outer_iters"], inf["true_rel_res"]), file=sys.stderr, flush=True)
+    # per-family kernel statistics gathered inside the timed region
+    stats = {f: [0, 0.0] for f in families}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setups, solves, infos = [], [], []
+    for i in range(args.steps):
+        s, inf, st = step(profile=True)
+        for f in families:
+            n, ms = ctx.profile_stats(f)
+            stats[f][0] += n
+            stats[f][1] += ms
+        setups.append(s)
+        solves.append(inf["t_solve_s"])
+        infos.append(inf)
+        print("[bench] step %d: setup %.3f s solve %.4f s iters %d res %.2e" % (
+            i, s, inf["t_solve_s"], inf["outer_iters"], inf["true_rel_res"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    solve_s = float(np.mean(solves))
+    ok = all(i["converged"] and i["true_rel_res"] <= 1e-10 for i in infos)
+
+    # dominant kernel of the timed solve, by total time
+    dom = max(families, key=lambda f: stats[f][1])
+    n, ms = stats[dom]
+    avg_ms = ms / max(n, 1)
+    bpl = algorithmic_bytes(dom, V, Vc, nb, wl["nv"])
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": n, "avg_launch_ms": avg_ms,
+                "bytes_per_launch": bpl}
+    kernel_table = {f: {"launches": stats[f][0], "total_ms": stats[f][1],
+                        "avg_ms": stats[f][1] / max(stats[f][0], 1),
+                        "GB_s": algorithmic_bytes(f, V, Vc, nb, wl["nv"]) / (stats[f][1] / max(stats[f][0], 1)) / 1e6
+                        if stats[f][0] else None} for f in families}
+
+    extra = {}
+    if not args.no_fp64:
+        print("[bench] plain FP64 solve", file=sys.stderr, flush=True)
+        c64 = make_context(w, wl, mixed=False)
+        c64.set_gauge(Ud)
+        c64.set_null_vectors(0, startd)
+        c64.setup()
+        x64, inf64, st64 = c64.solve(bd)
+        x64b, inf64b, _ = c64.solve(bd)
+        extra["fp64"] = {"solve_s": min(inf64[0]["t_solve_s"], inf64b[0]["t_solve_s"]),
+                         "setup_s": c64.timers()["setup"], "outer_iters": inf64[0]["outer_iters"],
+                         "true_rel_res": inf64[0]["true_rel_res"]}
+        extra["speedup_mixed_vs_fp64"] = extra["fp64"]["solve_s"] / solve_s
+        del c64
+    if not args.no_mk:
+        print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
+        extra["coarse_apply_large"] = coarse_apply_mk(w, torch)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, U, start, b, infos[-1]["outer_iters"])
+
+    line = {
+        "metric": METRIC, "value": solve_s, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "lattice": list(L), "aggregates": list(wl["block"]), "Nb": nb,
+                   "m0": wl["m0"], "c_sw": wl["csw"], "eps": wl["eps"], "tol": 1e-10, "precision":
+                   "FP32 cycle and coarse blocks, FP64 outer FGMRES"},
+        "converged": ok, "setup_s": float(np.mean(setups)), "outer_iters": infos[-1]["outer_iters"],
+        "coarse_iters": infos[-1]["coarse_iters"], "true_rel_res": infos[-1]["true_rel_res"],
+        "roofline": roofline, "kernels": kernel_table, "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -174,9 +174,12 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
 
 /* Kernel timing: when enabled, launches of the named kernel family are
- * bracketed by HIP events on the context stream.  Families: "dslash",
- * "coarse_apply", "restrict", "prolong".  Stats return the number of timed
- * launches and their total duration in milliseconds, then reset. */
+ * bracketed by HIP events on the context stream.  Families:
+ * "dslash_f64", "dslash_f32" (full fine operator), "wilson_term" (single
+ * terms, coarsening), "coarse_apply_f64", "coarse_apply_f32",
+ * "coarse_apply_bf16", "coarse_term", "restrict_f64", "restrict_f32",
+ * "prolong_f64", "prolong_f32".  Stats return the number of timed launches
+ * and their total duration in milliseconds, then reset. */
 int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable);
 int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms);
 

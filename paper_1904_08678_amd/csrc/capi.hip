@@ -246,9 +246,7 @@ int wcmg_apply_D(wcmg_ctx* ctx, int level, const void* in, void* out, int nrhs, 
       CoarseOp& C = *c.cop[level - 1];
       require(C.fresh[WCMG_F64], WCMG_ERR_STATE, "coarse operator not built");
       if (prec != WCMG_F64) C.refresh(prec, c.stream);
-      c.prof.begin("coarse_apply", c.stream);
       C.apply(prec, in, out, 0x1ff, 0, nrhs, nullptr, c.stream);
-      c.prof.end("coarse_apply", c.stream);
     }
     WCMG_HIP(hipStreamSynchronize(c.stream));
   });
@@ -451,6 +449,7 @@ int wcmg_coarse_set(wcmg_coarse* h, const void* blocks, int src_prec) {
   return guarded_c(h, [&](wcmg_coarse& o) {
     require(blocks && (src_prec == WCMG_F64 || src_prec == WCMG_F32), WCMG_ERR_ARG, "bad blocks");
     const long n = o.op.V * 9L * o.op.nb * o.op.nb;
+    o.op.M64.alloc(n * sizeof(cd64));
     if (src_prec == WCMG_F64)
       WCMG_HIP(hipMemcpyAsync(o.op.M64.p, blocks, n * sizeof(cd64), hipMemcpyDeviceToDevice, o.stream));
     else

@@ -270,19 +270,22 @@ template <typename R>
 void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms) {
   const bool single = sizeof(R) == 4;
   if (l == 0) {
-    prof.begin("dslash", stream);
+    const char* fam = terms != 0x1ff ? "wilson_term" : single ? "dslash_f32" : "dslash_f64";
+    prof.begin(fam, stream);
     if (single)
       launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
                            geo[0].V, terms, nrhs, run, stream);
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
                             geo[0].V, terms, nrhs, run, stream);
-    prof.end("dslash", stream);
+    prof.end(fam, stream);
   } else {
     const int prec = store_prec_for(l, single);
-    prof.begin("coarse_apply", stream);
+    const char* fam = terms != 0x1ff ? "coarse_term" : prec == WCMG_F64 ? "coarse_apply_f64"
+                                                      : prec == WCMG_F32 ? "coarse_apply_f32" : "coarse_apply_bf16";
+    prof.begin(fam, stream);
     cop[l - 1]->apply(prec, in, out, terms, 0, nrhs, run, stream);
-    prof.end("coarse_apply", stream);
+    prof.end(fam, stream);
   }
 }
 
@@ -324,18 +327,20 @@ template <typename R>
 void Context::restrict_(int l, const cplx<R>* fine, cplx<R>* coarse, int nrhs, const int* run) {
   Transfer& T = tr[l];
   const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
-  prof.begin("restrict", stream);
+  const char* fam = sizeof(R) == 8 ? "restrict_f64" : "restrict_f32";
+  prof.begin(fam, stream);
   launch_restrict<R>(fine, coarse, P, geo[l].lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nb, nrhs, run, stream);
-  prof.end("restrict", stream);
+  prof.end(fam, stream);
 }
 
 template <typename R>
 void Context::prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumulate, int nrhs, const int* run) {
   Transfer& T = tr[l];
   const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
-  prof.begin("prolong", stream);
+  const char* fam = sizeof(R) == 8 ? "prolong_f64" : "prolong_f32";
+  prof.begin(fam, stream);
   launch_prolong<R>(coarse, fine, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, accumulate, nrhs, run, stream);
-  prof.end("prolong", stream);
+  prof.end(fam, stream);
 }
 
 // ---------------------------------------------------------------- smoother
