@@ -135,7 +135,7 @@ int wcmg_refine(wcmg_ctx* ctx, int iterations);
  * rebuild P_l, D_{l+1} and the Galerkin products below. */
 int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v);
 
-/* Aggregation map of level l -> l+1 (a1): per site of level l (lexicographic),
+/* Aggregation map of level l -> l+1: per site of level l (lexicographic),
  * the coarse site and the offset inside its aggregate.  Host int32 arrays of V_l. */
 int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host);
 

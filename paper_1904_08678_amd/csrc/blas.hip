@@ -56,19 +56,31 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cplx<R>* __restrict__
   }
 }
 
-// out[k * ostride] (op)= sum_g partial[g][k]; mode 0: store, 1: add, 2: subtract
-__global__ void k_dot_finish(const cd64* __restrict__ partial, int G, int m, const int* __restrict__ m_dev,
-                             int mstride, cd64* __restrict__ out, int ostride, int mode,
-                             const int* __restrict__ run) {
+// out[k * ostride] (op)= sum_g partial[g][k]; mode 0: store, 1: add, 2: subtract.
+// One workgroup per k; each lane sums a strided subset of the partials, then a
+// fixed-order wave and LDS reduction (deterministic).
+__global__ void __launch_bounds__(256) k_dot_finish(const cd64* __restrict__ partial, int G, int m,
+                                                     const int* __restrict__ m_dev, int mstride,
+                                                     cd64* __restrict__ out, int ostride, int mode,
+                                                     const int* __restrict__ run) {
   if (run && !*run) return;
   if (m_dev) m = *m_dev;
-  for (int k = threadIdx.x; k < m; k += blockDim.x) {
-    cd64 s = mkc(0.0, 0.0);
-    for (int g = 0; g < G; ++g) s = cadd(s, partial[(long)g * mstride + k]);
+  const int k = blockIdx.x;
+  if (k >= m) return;
+  __shared__ cd64 lds[4];
+  cd64 s = mkc(0.0, 0.0);
+  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, partial[(long)g * mstride + k]);
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cd64 t = mkc(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
     cd64* o = out + (long)k * ostride;
-    if (mode == 0) *o = s;
-    else if (mode == 1) *o = cadd(*o, s);
-    else *o = csub(*o, s);
+    if (mode == 0) *o = t;
+    else if (mode == 1) *o = cadd(*o, t);
+    else *o = csub(*o, t);
   }
 }
 
@@ -315,7 +327,7 @@ void launch_dot(const cplx<R>* a, long astride, int m, const int* m_dev, const c
   int G = red_blocks(n);
   hipLaunchKernelGGL(k_dot_partial<R>, dim3(G), dim3(kBlock), 0, st, a, astride, m, m_dev, b, n, partial, mstride, run);
   WCMG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, m, m_dev, mstride, out, ostride, mode, run);
+  hipLaunchKernelGGL(k_dot_finish, dim3(m), dim3(kBlock), 0, st, partial, G, m, m_dev, mstride, out, ostride, mode, run);
   WCMG_CHECK_LAUNCH();
 }
 
@@ -323,8 +335,8 @@ int reduction_blocks(long n) { return red_blocks(n); }
 
 void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out, int ostride, int mode,
                        const int* run, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, m, (const int*)nullptr, mstride, out, ostride,
-                     mode, run);
+  hipLaunchKernelGGL(k_dot_finish, dim3(m), dim3(kBlock), 0, st, partial, G, m, (const int*)nullptr, mstride, out,
+                     ostride, mode, run);
   WCMG_CHECK_LAUNCH();
 }
 
@@ -371,7 +383,7 @@ void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd6
   int G = red_blocks(n);
   hipLaunchKernelGGL(k_dot2_partial<R>, dim3(G), dim3(kBlock), 0, st, p, r, n, partial, run);
   WCMG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(64), 0, st, partial, G, 2, (const int*)nullptr, 2, dots, 1, 0, run);
+  hipLaunchKernelGGL(k_dot_finish, dim3(2), dim3(kBlock), 0, st, partial, G, 2, (const int*)nullptr, 2, dots, 1, 0, run);
   WCMG_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_mr_update<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, r, p, dots, n, run);
   WCMG_CHECK_LAUNCH();

@@ -61,7 +61,7 @@ def make_pair(L, eps, seed, m0=-0.05, csw=1.0, blocks=((2, 2, 2, 2),), nv=(4,), 
     return ctx, H, U
 
 
-# ---------------------------------------------------------------- a1 aggregation
+# ---------------------------------------------------------------- aggregation map
 @pytest.mark.parametrize("L,block", [((8, 4, 4, 8), (4, 2, 2, 4)), ((4, 6, 4, 8), (2, 3, 2, 2))])
 def test_aggregation_map_bit_exact(L, block):
     w = wc()
@@ -90,7 +90,7 @@ def test_dims_errors():
     assert e.value.code == 2
 
 
-# ---------------------------------------------------------------- a2 clover and D
+# ---------------------------------------------------------------- clover term and Wilson-clover operator
 def test_clover_fp64_parity():
     L = (4, 4, 4, 8)
     ctx, H, U = make_pair(L, 0.3, 201)
@@ -126,7 +126,7 @@ def test_dslash_single_point_source_response():
     assert np.count_nonzero(np.abs(got).sum(axis=(1, 2)) > 1e-15) == 9
 
 
-# ---------------------------------------------------------------- a5 coarse apply
+# ---------------------------------------------------------------- coarse operator apply
 @pytest.mark.parametrize("Lc,nb", [((3, 2, 4, 3), 8), ((2, 2, 2, 2), 16), ((4, 4, 4, 8), 24), ((3, 3, 2, 2), 32),
                                     ((2, 3, 2, 2), 6)])
 def test_coarse_apply_parity_all_precisions(Lc, nb):
@@ -155,7 +155,7 @@ def test_coarse_apply_parity_all_precisions(Lc, nb):
             assert rel(got, ref) < 2e-2  # storage error of BF16 alone
 
 
-# ---------------------------------------------------------------- a3/a7 setup parity
+# ---------------------------------------------------------------- setup
 @pytest.mark.parametrize("L,block,nv,m0", [((4, 4, 4, 4), (2, 2, 2, 2), 8, -0.05), ((8, 8, 8, 8), (4, 4, 4, 4), 12, -0.08)])
 def test_setup_fp64_parity(L, block, nv, m0):
     """Relaxation (MR on D x = 0), chirality-split Gram-Schmidt and Galerkin
@@ -202,23 +202,28 @@ def test_breakdown_reported():
     assert e.value.code == 6
 
 
-# ---------------------------------------------------------------- a4 restrict / prolong
+# ---------------------------------------------------------------- restriction and prolongation
 def test_restrict_prolong_parity():
+    """GPU and oracle build P from the same start vectors; each restricts and
+    prolongs with its own P."""
     w = wc()
     L, block, nv = (8, 4, 4, 8), (4, 2, 2, 4), 6
     ctx, H, U = make_pair(L, 0.3, 501, blocks=(block,), nv=(nv,))
     V = int(np.prod(L))
-    ctx.set_null_vectors(0, dev(syn.complex_gaussian((nv, V, 12), 502)))
+    start = syn.complex_gaussian((nv, V, 12), 502)
+    ctx.set_null_vectors(0, dev(start))
     ctx.setup()
-    Pv = host(ctx.prolongator(0))
+    H.set_start(0, start)
+    H.setup()
+    Pv = H.P(0)
     v = syn.complex_gaussian((2, V, 12), 503)
     ref = oracle.restrict(L, block, 12, Pv, v)
-    assert rel(host(ctx.restrict(0, dev(v), w.F64)), ref) < 1e-13
+    assert rel(host(ctx.restrict(0, dev(v), w.F64)), ref) < 1e-12
     assert rel(host(ctx.restrict(0, dev(v.astype(np.complex64)), w.F32)), ref) < 1e-5
     Vc = V // 64
     phi = syn.complex_gaussian((2, Vc, 2 * nv), 504)
     ref = oracle.prolong(L, block, 12, Pv, phi)
-    assert rel(host(ctx.prolong(0, dev(phi), w.F64)), ref) < 1e-13
+    assert rel(host(ctx.prolong(0, dev(phi), w.F64)), ref) < 1e-12
     assert rel(host(ctx.prolong(0, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
     # R P = 1
     rp = host(ctx.restrict(0, ctx.prolong(0, dev(phi), w.F64), w.F64))
@@ -226,22 +231,28 @@ def test_restrict_prolong_parity():
 
 
 def test_coarse_level_apply_parity():
+    """The level-1 operator: GPU-built D_c applied in FP64/FP32 against the
+    oracle's own D_c; BF16 storage with the oracle's blocks injected."""
     w = wc()
     L, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 8
     ctx, H, U = make_pair(L, 0.3, 505, blocks=(block,), nv=(nv,))
-    ctx.set_null_vectors(0, dev(syn.complex_gaussian((nv, 512, 12), 506)))
+    start = syn.complex_gaussian((nv, 512, 12), 506)
+    ctx.set_null_vectors(0, dev(start))
     ctx.setup()
-    blocks = host(ctx.coarse_op(1))
+    H.set_start(0, start)
+    H.setup()
+    blocks = H.coarse(1)
     Lc = (2, 2, 2, 4)
     phi = syn.complex_gaussian((2, 32, 16), 507)
     ref = oracle.coarse_apply(Lc, blocks, phi)
-    assert rel(host(ctx.apply_D(1, dev(phi), w.F64)), ref) < 1e-14
+    assert rel(host(ctx.apply_D(1, dev(phi), w.F64)), ref) < 1e-12
     assert rel(host(ctx.apply_D(1, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
+    ctx.set_coarse_op(1, dev(blocks))
     refb = oracle.coarse_apply(Lc, bf16_round(blocks), phi)
     assert rel(host(ctx.apply_D(1, dev(phi.astype(np.complex64)), w.BF16)), refb) < 1e-5
 
 
-# ---------------------------------------------------------------- a8 cycle and solve
+# ---------------------------------------------------------------- cycle and solve
 def test_cycle_fp64_parity_fixed_coarse_iterations():
     L, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 8
     ctx, H, U = make_pair(L, 0.3, 601, blocks=(block,), nv=(nv,), coarse_fixed_iters=12)
