@@ -103,6 +103,38 @@ __global__ void __launch_bounds__(256) k_multi_axpy(cplx<R>* __restrict__ y, con
   y[i] = acc;
 }
 
+// y[i] += sign * sum_{k<m} coef[k] V_k[i], then per-workgroup partials of |y|^2
+// (grid-stride over a fixed number of workgroups, so partials are deterministic).
+template <typename R>
+__global__ void __launch_bounds__(256) k_multi_axpy_norm(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ V,
+                                                          long vstride, int m, const cd64* __restrict__ coef,
+                                                          int cstride, double sign, long n,
+                                                          cd64* __restrict__ partial, const int* __restrict__ run) {
+  if (run && !*run) return;
+  __shared__ cd64 lds[4];
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double q = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    cplx<R> acc = y[i];
+    for (int k = 0; k < m; ++k) {
+      const cd64 c = coef[(long)k * cstride];
+      cfma(acc, mkc((R)(sign * c.re), (R)(sign * c.im)), V[k * vstride + i]);
+    }
+    y[i] = acc;
+    q += (double)acc.re * acc.re + (double)acc.im * acc.im;
+  }
+  cd64 s = wave_sum(mkc(q, 0.0));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cd64 t = mkc(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
+    partial[blockIdx.x] = t;
+  }
+}
+
 // y = a * x + b * y with real constants
 template <typename R>
 __global__ void k_axpby(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, R a, R b, long n,
@@ -333,6 +365,20 @@ void launch_dot(const cplx<R>* a, long astride, int m, const int* m_dev, const c
 
 int reduction_blocks(long n) { return red_blocks(n); }
 
+template <typename R>
+void launch_multi_axpy_norm(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, int cstride,
+                            double sign, long n, cd64* partial, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_axpy_norm<R>, dim3(red_blocks(n)), dim3(kBlock), 0, st, y, V, vstride, m, coef, cstride,
+                     sign, n, partial, run);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_multi_axpy_norm<double>(cd64*, const cd64*, long, int, const cd64*, int, double, long, cd64*,
+                                             const int*, hipStream_t);
+template void launch_multi_axpy_norm<float>(cf32*, const cf32*, long, int, const cd64*, int, double, long, cd64*,
+                                            const int*, hipStream_t);
+
+
+
 void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out, int ostride, int mode,
                        const int* run, hipStream_t st) {
   hipLaunchKernelGGL(k_dot_finish, dim3(m), dim3(kBlock), 0, st, partial, G, m, (const int*)nullptr, mstride, out,
@@ -378,6 +424,13 @@ void launch_convert(const cplx<Ti>* x, cplx<To>* y, long n, const int* run, hipS
 }
 
 template <typename R>
+void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots, long n, const int* run,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_mr_update<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, r, p, dots, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
 void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
                            const int* run, hipStream_t st) {
   int G = red_blocks(n);
@@ -398,6 +451,7 @@ void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd6
   template void launch_zero<R>(cplx<R>*, long, const int*, hipStream_t);                                             \
   template void launch_sub<R>(cplx<R>*, const cplx<R>*, const cplx<R>*, long, const int*, hipStream_t);              \
   template void launch_scale_inv_norm<R>(cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t);      \
+  template void launch_mr_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t); \
   template void launch_mr_dots_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, cd64*, cd64*, const int*,         \
                                          hipStream_t);
 INST_BLAS(double)

@@ -108,7 +108,8 @@ struct Context {
 
   // operators
   template <typename R>
-  void apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms = 0x1ff);
+  void apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms = 0x1ff,
+                cd64* dots = nullptr);
   int store_prec_for(int l, bool single) const;
 
   // building blocks
@@ -127,6 +128,8 @@ struct Context {
   template <typename R>
   void cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run);
   void precondition64(int l, const cd64* r, cd64* x, const int* run);
+  template <typename R>
+  int coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* parent, int check_every);
   template <typename R>
   int gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<R>*, const int*)>& A,
             const std::function<void(const cplx<R>*, cplx<R>*, const int*)>* M, const cplx<R>* b, cplx<R>* x,

@@ -267,17 +267,17 @@ int Context::store_prec_for(int l, bool single) const {
 }
 
 template <typename R>
-void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms) {
+void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms, cd64* dots) {
   const bool single = sizeof(R) == 4;
   if (l == 0) {
     const char* fam = terms != 0x1ff ? "wilson_term" : single ? "dslash_f32" : "dslash_f64";
     prof.begin(fam, stream);
     if (single)
       launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
-                           geo[0].V, terms, nrhs, run, stream);
+                           geo[0].V, terms, nrhs, run, stream, dots);
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                            geo[0].V, terms, nrhs, run, stream);
+                            geo[0].V, terms, nrhs, run, stream, dots);
     prof.end(fam, stream);
   } else {
     const int prec = store_prec_for(l, single);
@@ -363,6 +363,17 @@ void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, c
     if (b) launch_sub<R>(r, b, pp, nn, run, stream);
     else launch_axpby<R>(r, pp, -1.0, 0.0, nn, run, stream);
   }
+  if (l == 0) {
+    // the inner products <p, r> and <p, p> come out of the operator's epilogue
+    const int G = wilson_blocks(geo[0].V);
+    cd64* part = buf<cd64>("mr_part" + t, 2L * G);
+    for (int k = 0; k < steps; ++k) {
+      apply_op<R>(l, r, pp, 1, run, 0x1ff, part);
+      launch_dot_finish(part, G, 2, 2, dots, 1, 0, run, stream);
+      launch_mr_update<R>(x, r, pp, dots, nn, run, stream);
+    }
+    return;
+  }
   for (int k = 0; k < steps; ++k) {
     apply_op<R>(l, r, pp, 1, run);
     launch_mr_dots_update<R>(x, r, pp, nn, partial.as<cd64>(), dots, run, stream);
@@ -419,12 +430,13 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
       cplx<R>* zj = M ? Z + (long)j * nn : vj;
       if (M) (*M)(vj, zj, run);
       A(zj, w, run);
+      // classical Gram-Schmidt applied twice; |w|^2 comes out of the last update
       launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, H + j, m, 0, run, stream);
       launch_multi_axpy<R>(w, V, nn, j + 1, nullptr, H + j, m, -1.0, nn, run, stream);
       launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, tmp, 1, 0, run, stream);
       launch_dot_finish(part, Gb, j + 1, j + 1, H + j, m, 1, run, stream);
-      launch_multi_axpy<R>(w, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, run, stream);
-      launch_dot<R>(w, 0, 1, nullptr, w, nn, part, 1, misc + 3, 1, 0, run, stream);
+      launch_multi_axpy_norm<R>(w, V, nn, j + 1, tmp, 1, -1.0, nn, part, run, stream);
+      launch_dot_finish(part, Gb, 1, 1, misc + 3, 1, 0, run, stream);
       launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
       if (j + 1 < m) launch_scale_inv_norm<R>(V + (long)(j + 1) * nn, w, misc + 3, nn, run, stream);
       if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
@@ -434,6 +446,85 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
     }
     launch_gmres_solve_y(st, S, m, stream);
     launch_multi_axpy<R>(x, M ? Z : V, nn, m, st + 2, y, 1, 1.0, nn, nullptr, stream);
+    launch_gmres_cycle_end(st, stream);
+    if (check_every > 0) {
+      read_state();
+      if (!pinned[1]) break;
+    }
+  }
+  if (check_every > 0) {
+    read_state();
+    return pinned[3];
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------- fused coarsest GMRES
+// Same semantics as gmres() with restart = coarse_restart, x0 = 0 and the
+// estimate ending the solve, but each Arnoldi step is four kernels
+// (coarse_gmres.hip).
+template <typename R>
+int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* parent, int check_every) {
+  CoarseOp& C = *cop[lc - 1];
+  const bool single = sizeof(R) == 4;
+  const int prec = store_prec_for(lc, single);
+  const int nb = C.nb;
+  const long nn = C.V * nb;
+  const int m = p.coarse_restart, m1 = m + 1;
+  const std::string t = std::to_string(lc) + (single ? "f" : "d");
+  GmresState& G = gmres_state("cgf" + t, m, nn, single ? 1 : 0, false);
+  cplx<R>* V = G.V.as<cplx<R>>();
+  cplx<R>* wb[2] = {G.w.as<cplx<R>>(), buf<cplx<R>>("cgf_w1" + t, nn)};
+  cplx<R>* r = buf<cplx<R>>("cgf_r" + t, nn);
+  const long G1max = (long)nblocks(nn * 8), G2 = nblocks(nn);
+  cd64* partA = buf<cd64>("cgf_pa" + t, G1max * m1);
+  cd64* partB = buf<cd64>("cgf_pb" + t, G2 * m1);
+  cd64* partC = buf<cd64>("cgf_pc" + t, G2 * m1);
+  cd64* S = G.S.as<cd64>();
+  cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+  cd64* y = misc - m;
+  int* st = G.st.as<int>();
+  int* run = st;
+  int* live = st + 1;
+  const void* blk = C.dev[prec].p;
+  require(C.fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  const int fixed = p.coarse_fixed_iters;
+  const int limit = fixed > 0 ? fixed : p.coarse_maxit;
+  const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
+  auto read_state = [&]() {
+    WCMG_HIP(hipMemcpyAsync(pinned, st, 5 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    sync();
+  };
+  const char* fam = prec == WCMG_F64 ? "coarse_gmres_step_f64" : prec == WCMG_F32 ? "coarse_gmres_step_f32"
+                                                                                     : "coarse_gmres_step_bf16";
+  launch_gmres_init(st, parent, stream);
+  launch_zero<R>(x, nn, live, stream);
+  for (int cyc = 0; cyc < max_cycles; ++cyc) {
+    const cplx<R>* u0 = b;
+    if (cyc > 0) {
+      C.apply(prec, x, wb[0], 0x1ff, 0, 1, live, stream);
+      launch_sub<R>(r, b, wb[0], nn, live, stream);
+      u0 = r;
+    }
+    launch_cg_norm_partial<R>(u0, nn, partC, m1, live, stream);
+    launch_cg_cycle_start(st, S, m, partC, (int)G2, cyc == 0 ? 1 : 0, p.coarse_tol, limit, fixed, stream);
+    for (int j = 0; j < m; ++j) {
+      const cplx<R>* u = j == 0 ? u0 : wb[j & 1];
+      const cd64* unrm2 = j == 0 ? misc + 1 : misc + 3;
+      cplx<R>* w = wb[(j + 1) & 1];
+      prof.begin(fam, stream);
+      const int G1 = launch_cg_apply(prec, nb, blk, C.nbr.as<int>(), C.V, u, unrm2, V, j, w, partA, m1, run, stream);
+      prof.end(fam, stream);
+      launch_cg_orth<R>(V, j, w, nn, partA, G1, S, m, 0, partB, run, stream);
+      launch_cg_orth<R>(V, j, w, nn, partB, (int)G2, S, m, 1, partC, run, stream);
+      launch_cg_givens(st, S, m, j, partC, (int)G2, p.coarse_tol, limit, fixed, stream);
+      if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
+        read_state();
+        if (!pinned[0]) break;
+      }
+    }
+    launch_gmres_solve_y(st, S, m, stream);
+    launch_multi_axpy<R>(x, V, nn, m, st + 2, y, 1, 1.0, nn, nullptr, stream);
     launch_gmres_cycle_end(st, stream);
     if (check_every > 0) {
       read_state();
@@ -464,7 +555,10 @@ void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
     apply_op<R>(lc, i, o, 1, rn);
   };
   const int check = (p.reserved[0] & 1) ? 0 : 4;  // reserved[0] bit 0: no host checks inside cycles
-  if (lc + 1 >= nlev) {
+  if (lc + 1 >= nlev && cg_fused_supported(geo[lc].ns) && !(p.reserved[0] & 2)) {
+    int it = coarse_gmres<R>(lc, rc, ec, run, check);
+    if (it > 0) coarse_iters += it;
+  } else if (lc + 1 >= nlev) {
     GmresState& G = gmres_state("cg" + t, p.coarse_restart, nc, sizeof(R) == 8 ? 0 : 1, false);
     int it = gmres<R>(G, A, nullptr, rc, ec, true, p.coarse_restart, p.coarse_maxit, p.coarse_tol,
                       p.coarse_fixed_iters, true, run, check);
@@ -607,8 +701,8 @@ void Context::setup_all() {
 }
 
 // ---------------------------------------------------------------- instantiations
-template void Context::apply_op<double>(int, const cd64*, cd64*, int, const int*, int);
-template void Context::apply_op<float>(int, const cf32*, cf32*, int, const int*, int);
+template void Context::apply_op<double>(int, const cd64*, cd64*, int, const int*, int, cd64*);
+template void Context::apply_op<float>(int, const cf32*, cf32*, int, const int*, int, cd64*);
 template void Context::restrict_<double>(int, const cd64*, cd64*, int, const int*);
 template void Context::restrict_<float>(int, const cf32*, cf32*, int, const int*);
 template void Context::prolong_<double>(int, const cd64*, cd64*, int, int, const int*);
@@ -616,6 +710,8 @@ template void Context::prolong_<float>(int, const cf32*, cf32*, int, int, const 
 template void Context::mr<double>(int, const cd64*, cd64*, bool, int, const int*);
 template void Context::mr<float>(int, const cf32*, cf32*, bool, int, const int*);
 template void Context::cycle<double>(int, const cd64*, cd64*, const int*);
+template int Context::coarse_gmres<double>(int, const cd64*, cd64*, const int*, int);
+template int Context::coarse_gmres<float>(int, const cf32*, cf32*, const int*, int);
 template void Context::cycle<float>(int, const cf32*, cf32*, const int*);
 template int Context::gmres<double>(GmresState&, const std::function<void(const cd64*, cd64*, const int*)>&,
                                     const std::function<void(const cd64*, cd64*, const int*)>*, const cd64*, cd64*,

@@ -20,7 +20,8 @@ template <typename Ti, typename To>
 void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st);
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr);
+int wilson_blocks(long V);
 
 // ---- coarse operator (coarse.hip)
 size_t device_block_bytes(long Vc, int nb, int prec);
@@ -49,6 +50,10 @@ template <typename R>
 void launch_dot(const cplx<R>* a, long astride, int m, const int* m_dev, const cplx<R>* b, long n, cd64* partial,
                 int mstride, cd64* out, int ostride, int mode, const int* run, hipStream_t st);
 int reduction_blocks(long n);
+template <typename R>
+void launch_multi_axpy_norm(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, int cstride,
+                            double sign, long n, cd64* partial, const int* run, hipStream_t st);
+
 void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out, int ostride, int mode,
                        const int* run, hipStream_t st);
 template <typename R>
@@ -65,6 +70,9 @@ void launch_sub(cplx<R>* y, const cplx<R>* a, const cplx<R>* b, long n, const in
 template <typename Ti, typename To>
 void launch_convert(const cplx<Ti>* x, cplx<To>* y, long n, const int* run, hipStream_t st);
 template <typename R>
+void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots, long n, const int* run,
+                      hipStream_t st);
+template <typename R>
 void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
                            const int* run, hipStream_t st);
 void launch_gmres_init(int* st_, const int* parent, hipStream_t st);
@@ -73,6 +81,20 @@ void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit,
                          hipStream_t st);
 void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
 void launch_gmres_cycle_end(int* st_, hipStream_t st);
+
+// ---- fused coarse GMRES (coarse_gmres.hip)
+bool cg_fused_supported(int nb);
+template <typename R>
+void launch_cg_norm_partial(const cplx<R>* r, long n, cd64* part, int m1, const int* run, hipStream_t st);
+void launch_cg_cycle_start(int* stw, cd64* S, int m, const cd64* part, int G, int first, double tol, int limit,
+                           int fixed, hipStream_t st);
+int launch_cg_apply(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
+                    void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st);
+template <typename R>
+void launch_cg_orth(cplx<R>* V, int j, cplx<R>* w, long n, const cd64* part_in, int G_in, cd64* S, int m, int pass,
+                    cd64* part_out, const int* run, hipStream_t st);
+void launch_cg_givens(int* stw, cd64* S, int m, int j, const cd64* part, int G, double tol, int limit, int fixed,
+                      hipStream_t st);
 
 constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
 

@@ -7,10 +7,13 @@
 //   spinor   [12][V]      complex (component k = 3*spin + colour)
 //   links    [4][9][V]    complex, U_mu(s) row-major; the antiperiodic sign of
 //                         the t boundary is folded into U_t on the last slice
-//   clover   [2][36][V]   real: per chirality a packed Hermitian 6x6 block of
-//                         (4 + m0) + C: 6 diagonal reals, then the 15 entries
-//                         below the diagonal (row i > col j, row-major) as re, im
+//   clover   [2][36/RC][V][RC] real: per chirality a packed Hermitian 6x6 block
+//                         of (4 + m0) + C: 6 diagonal reals, then the 15
+//                         entries below the diagonal (row i > col j, row-major)
+//                         as re, im, in 16-byte chunks of RC reals
 //   nbr      [8][V]       int32 neighbour site in direction d = 1..8
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace wcmg {
@@ -160,23 +163,29 @@ __global__ void k_clover_build(const cd64* __restrict__ U, Lex lx, long V, doubl
   }
 }
 
-// Pack (4 + m0) + C into the device clover layout, in device site order.
+// Pack (4 + m0) + C into the device clover layout, in device site order:
+// per chirality the 36 reals (6 diagonal, then the 15 lower-triangle entries
+// as re, im) in 16-byte chunks of RC = 16 / sizeof(R) reals: [chi][36/RC][V][RC].
 template <typename R>
 __global__ void k_pack_clover(const cd64* __restrict__ blocks, const int* __restrict__ perm, long V, double m0,
                               R* __restrict__ out) {
+  constexpr int RC = 16 / sizeof(R);
   long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (s >= V) return;
   long x = perm[s];
   for (int chi = 0; chi < 2; ++chi) {
     const cd64* b = blocks + (x * 2 + chi) * 36;
-    R* o = out + (long)chi * 36 * V;
-    for (int i = 0; i < 6; ++i) o[(long)i * V + s] = (R)(4.0 + m0 + b[i * 6 + i].re);
+    R e[36];
+    for (int i = 0; i < 6; ++i) e[i] = (R)(4.0 + m0 + b[i * 6 + i].re);
     int idx = 0;
     for (int i = 1; i < 6; ++i)
       for (int j = 0; j < i; ++j, ++idx) {
-        o[(long)(6 + 2 * idx) * V + s] = (R)b[i * 6 + j].re;
-        o[(long)(7 + 2 * idx) * V + s] = (R)b[i * 6 + j].im;
+        e[6 + 2 * idx] = (R)b[i * 6 + j].re;
+        e[7 + 2 * idx] = (R)b[i * 6 + j].im;
       }
+    R* o = out + (long)chi * 36 * V;
+    for (int q = 0; q < 36 / RC; ++q)
+      for (int r = 0; r < RC; ++r) o[((long)q * V + s) * RC + r] = e[q * RC + r];
   }
 }
 
@@ -305,53 +314,132 @@ __device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, c
 
 // out = sum of the selected terms of D applied to in.
 // terms: bit 0 = Mdiag ((4+m0) + C), bit d (1..8) = Mdir_d.
+//
+// A workgroup of 4 waves owns 64 consecutive sites; wave mu computes the two
+// hops along direction mu for all 64 sites (waves 0 and 1 also the clover
+// block of chirality 0 and 1), so every branch is wave-uniform and four times
+// as many loads are in flight as with one lane per site.  The four partial
+// spinors are combined in LDS in a fixed order.
+// dots != nullptr: per-workgroup partials of <out, in> and <out, out> (the
+// inner products of an MR step, where in = r and out = D r) go to
+// dots[2*blk], dots[2*blk+1].
+template <typename R, int chi>
+__device__ inline void clover_chirality(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in,
+                                        const R* __restrict__ clov, long V, long s) {
+  constexpr int RC = 16 / sizeof(R);
+  typedef typename std::conditional<sizeof(R) == 4, float4, double2>::type V16;
+  R e[36];
+  const V16* cb = (const V16*)(clov + (long)chi * 36 * V);
+#pragma unroll
+  for (int q = 0; q < 36 / RC; ++q) {
+    V16 c = cb[(long)q * V + s];
+    if constexpr (RC == 4) {
+      e[q * 4 + 0] = c.x;
+      e[q * 4 + 1] = c.y;
+      e[q * 4 + 2] = c.z;
+      e[q * 4 + 3] = c.w;
+    } else {
+      e[q * 2 + 0] = c.x;
+      e[q * 2 + 1] = c.y;
+    }
+  }
+  cplx<R> p[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = in[(long)(chi * 6 + k) * V + s];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[chi * 6 + i] = cadd(acc[chi * 6 + i], cscale(e[i], p[i]));
+  int idx = 0;
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j, ++idx) {
+      const cplx<R> a = mkc(e[6 + 2 * idx], e[7 + 2 * idx]);
+      cfma(acc[chi * 6 + i], a, p[j]);
+      cfmac(acc[chi * 6 + j], a, p[i]);
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                                  const int* __restrict__ nbr, long V, int terms,
-                                                 const int* __restrict__ run) {
+                                                 cd64* __restrict__ dots, const int* __restrict__ run) {
   if (run && !*run) return;
-  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (s >= V) return;
+  __shared__ cplx<R> part[4][12][64];
+  __shared__ cd64 red[8];
+  const int lane = threadIdx.x & 63;
+  const int mu = threadIdx.x >> 6;  // wave-uniform
+  const long blk = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
+  const long s = blk * 64 + lane;
+  const bool valid = s < V;
   const long r = blockIdx.y;
   in += r * 12 * V;
   out += r * 12 * V;
   cplx<R> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mkc((R)0, (R)0);
-  if (terms & 1) {
-#pragma unroll
-    for (int chi = 0; chi < 2; ++chi) {
-      const R* cb = clov + (long)chi * 36 * V + s;
-      cplx<R> p[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) p[k] = in[(long)(chi * 6 + k) * V + s];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        R d = cb[(long)i * V];
-        acc[chi * 6 + i] = cadd(acc[chi * 6 + i], cscale(d, p[i]));
-      }
-      int idx = 0;
-#pragma unroll
-      for (int i = 1; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < i; ++j, ++idx) {
-          cplx<R> a = mkc(cb[(long)(6 + 2 * idx) * V], cb[(long)(7 + 2 * idx) * V]);
-          cfma(acc[chi * 6 + i], a, p[j]);
-          cfmac(acc[chi * 6 + j], a, p[i]);
-        }
+  if (valid) {
+    if ((terms & 1) && mu == 0) clover_chirality<R, 0>(acc, in, clov, V, s);
+    if ((terms & 1) && mu == 1) clover_chirality<R, 1>(acc, in, clov, V, s);
+    if (mu == 0) {
+      if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
+      if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
+    } else if (mu == 1) {
+      if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
+      if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
+    } else if (mu == 2) {
+      if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
+      if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
+    } else {
+      if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
+      if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
     }
   }
-  if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
-  if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) out[(long)k * V + s] = acc[k];
+  for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
+  __syncthreads();
+  // wave mu writes components 3 mu .. 3 mu + 2 (spin mu), summed over the 4 waves in order
+  double pr = 0.0, pi = 0.0, pp = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int k = 3 * mu + c;
+    cplx<R> v = part[0][k][lane];
+    v = cadd(v, part[1][k][lane]);
+    v = cadd(v, part[2][k][lane]);
+    v = cadd(v, part[3][k][lane]);
+    if (valid) {
+      out[(long)k * V + s] = v;
+      if (dots) {
+        const cplx<R> x = in[(long)k * V + s];
+        pr += (double)v.re * x.re + (double)v.im * x.im;
+        pi += (double)v.re * x.im - (double)v.im * x.re;
+        pp += (double)v.re * v.re + (double)v.im * v.im;
+      }
+    }
+  }
+  if (dots) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pr += __shfl_xor(pr, off, 64);
+      pi += __shfl_xor(pi, off, 64);
+      pp += __shfl_xor(pp, off, 64);
+    }
+    if (lane == 0) {
+      red[2 * mu] = mkc(pr, pi);
+      red[2 * mu + 1] = mkc(pp, 0.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      cd64 a = mkc(0.0, 0.0), b = mkc(0.0, 0.0);
+      for (int w = 0; w < 4; ++w) {
+        a = cadd(a, red[2 * w]);
+        b = cadd(b, red[2 * w + 1]);
+      }
+      const long bi = blockIdx.y * gridDim.x + blockIdx.x;
+      dots[2 * bi] = a;
+      dots[2 * bi + 1] = b;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -406,13 +494,16 @@ INST_PACK(float, double)
 
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st) {
-  hipLaunchKernelGGL(k_wilson<R>, dim3(nblocks(V), nrhs), dim3(kBlock), 0, st, in, out, U, clov, nbr, V, terms, run);
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots) {
+  hipLaunchKernelGGL(k_wilson<R>, dim3(nblocks(V, 64), nrhs), dim3(kBlock), 0, st, in, out, U, clov, nbr, V, terms,
+                     dots, run);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
-                                    const int*, hipStream_t);
+                                    const int*, hipStream_t, cd64*);
 template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
-                                   const int*, hipStream_t);
+                                   const int*, hipStream_t, cd64*);
+
+int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 
 }  // namespace wcmg

@@ -329,3 +329,28 @@ def test_state_errors():
     with pytest.raises(w.WcmgError) as e:
         ctx.solve(dev(np.ones((256, 4, 3), np.complex128)))
     assert e.value.code == 3
+
+
+@pytest.mark.parametrize("fixed", [0, 9])
+def test_fused_coarse_gmres_matches_generic_path(fixed):
+    """The four-kernel Arnoldi step of the coarsest GMRES and the generic
+    multi-kernel path give the same cycle output (FP64) and solve."""
+    w = wc()
+    L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    U = syn.gauge_field(L, 0.25, 801)
+    start = syn.complex_gaussian((nv, 4096, 12), 802)
+    r = syn.complex_gaussian((4096, 4, 3), 803)
+    outs, infos = [], []
+    for flags in (0, 2):
+        ctx = w.Context(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), coarse_fixed_iters=fixed,
+                        reserved=(flags,))
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        outs.append(host(ctx.cycle(dev(r))))
+        x, info, st = ctx.solve(dev(r))
+        assert st == 0
+        infos.append(info[0])
+    assert rel(outs[0], outs[1]) < 1e-11
+    assert abs(infos[0]["outer_iters"] - infos[1]["outer_iters"]) <= 1
+    assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
