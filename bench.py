@@ -55,6 +55,31 @@ def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int) -> float:
     return float("nan")
 
 
+TRAFFIC_SOURCES = {
+    "dslash_f32": ("paper_1904_08678_amd/csrc/wilson.hip",),
+    "coarse_apply_f32_large": ("paper_1904_08678_amd/csrc/coarse.hip", "paper_1904_08678_amd/csrc/coarse_common.h"),
+}
+
+
+def counter_traffic(key: str):
+    """Calibrated HBM traffic per launch from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_counters.md")
+    try:
+        text = open(path).read()
+        data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        rec = data[key]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[key]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def make_inputs(wl):
     import numpy as np
     import synthetic as syn
@@ -125,6 +150,57 @@ def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
             "host_cpu": platform.processor() or platform.machine()}
 
 
+def kernel_mode(args):
+    """Launch one kernel family back to back (for rocprofv3 counter runs) and
+    print its mean launch duration from HIP events."""
+    import numpy as np
+    import torch
+    import paper_1904_08678_amd as w
+    torch.cuda.set_device(0)
+    fam = args.family
+    if fam == "copy":
+        n = args.mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.reps):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"family": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "reps": args.reps}))
+        return
+    if fam.startswith("coarse_mk"):
+        store = {"f64": w.F64, "f32": w.F32, "bf16": w.BF16}[fam.split("_")[-1]]
+        res = coarse_apply_mk(w, torch, stores=(store,), reps=args.reps)
+        print(json.dumps({"family": fam, **res}))
+        return
+    wl = WORKLOAD
+    L = wl["L"]
+    V = int(np.prod(L))
+    U, start, b = make_inputs(wl)
+    ctx = make_context(w, wl, mixed=True)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    if fam in ("dslash_f32", "dslash_f64"):
+        prec = w.F32 if fam.endswith("f32") else w.F64
+        x = torch.from_numpy(b).cuda().to(torch.complex64 if prec == w.F32 else torch.complex128)
+        ctx.profile(fam, True)
+        for _ in range(args.reps):
+            ctx.apply_D(0, x, prec)
+        n, ms = ctx.profile_stats(fam)
+    else:
+        ctx.set_null_vectors(0, torch.from_numpy(start).cuda())
+        ctx.setup()
+        x = torch.from_numpy(b).cuda().to(torch.complex64)
+        ctx.profile(fam, True)
+        for _ in range(args.reps):
+            if fam == "restrict_f32":
+                ctx.restrict(0, x, w.F32)
+            else:
+                ctx.prolong(0, torch.zeros((V // 256, 24), dtype=torch.complex64, device="cuda"), w.F32)
+        n, ms = ctx.profile_stats(fam)
+    bpl = algorithmic_bytes(fam, V, V // 256, 24, 12)
+    print(json.dumps({"family": fam, "launches": n, "avg_ms": ms / max(n, 1), "bytes_per_launch": bpl,
+                      "GB_s": bpl / (ms / max(n, 1)) / 1e6}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,11 +209,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mk", action="store_true")
+    ap.add_argument("--kernel", dest="family", default=None,
+                    help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
+                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy")
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; N=%d is not supported (the path would shard by 4D domain "
               "decomposition, see DESIGN.md)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.family:
+        kernel_mode(args)
+        return
 
     import numpy as np
     import torch
@@ -202,8 +286,9 @@ def main():
     bpl = algorithmic_bytes(dom, V, Vc, nb, wl["nv"])
     achieved = bpl / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": n, "avg_launch_ms": avg_ms,
-                "bytes_per_launch": bpl}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": counter_traffic(dom) if dom in TRAFFIC_SOURCES else None,
+                "launches": n, "avg_launch_ms": avg_ms, "bytes_per_launch": bpl}
     kernel_table = {f: {"launches": stats[f][0], "total_ms": stats[f][1],
                         "avg_ms": stats[f][1] / max(stats[f][0], 1),
                         "GB_s": algorithmic_bytes(f, V, Vc, nb, wl["nv"]) / (stats[f][1] / max(stats[f][0], 1)) / 1e6
@@ -226,6 +311,7 @@ def main():
     if not args.no_mk:
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)
+        extra["coarse_apply_large"]["per_store"]["f32"]["traffic"] = counter_traffic("coarse_apply_f32_large")
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
