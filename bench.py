@@ -100,7 +100,7 @@ def make_context(w, wl, mixed: bool):
     return w.Context(**kw)
 
 
-def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20):
+def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20, nrhs_batch=12):
     """Coarse apply on a coarse lattice far larger than the 256 MB last-level cache."""
     out = {}
     Vc = dims[0] * dims[1] * dims[2] * dims[3]
@@ -123,9 +123,34 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
                      "bytes_per_launch": byts}
         del op, x, y
         torch.cuda.synchronize()
+    # twelve right-hand sides in one launch: matrix-core kernel against the per-row kernel
+    batched = {}
+    if nrhs_batch:
+        for store in (w.F32, w.BF16):
+            name = {w.F32: "f32", w.BF16: "bf16"}[store]
+            op = w.CoarseOperator(dims, nb, store)
+            op.set(blocks)
+            x = torch.randn((nrhs_batch, Vc, nb), dtype=torch.complex64, device="cuda", generator=g)
+            y = torch.empty_like(x)
+            sb = {"f32": 8, "bf16": 4}[name]
+            byts = (9.0 * nb * nb * sb + 2.0 * nb * nrhs_batch * 8) * Vc
+            flops = 8.0 * 9 * nb * nb * nrhs_batch * Vc
+            rec = {}
+            for kern, kname in ((2, "matrix_cores"), (1, "vector")):
+                op.set_kernel(kern)
+                op.time(x, y, reps=2)
+                ms = op.time(x, y, reps=max(3, reps // 2))
+                rec[kname] = {"ms": ms, "GB_s": byts / ms / 1e6, "frac_hbm": byts / ms / 1e6 / HBM_PEAK_GBS,
+                              "TFLOP_s": flops / ms / 1e9}
+            rec["bytes_per_launch"] = byts
+            rec["flops_per_launch"] = flops
+            batched[name] = rec
+            del op, x, y
+            torch.cuda.synchronize()
     del blocks
     torch.cuda.empty_cache()
-    return {"coarse_dims": list(dims), "Vc": Vc, "nb": nb, "per_store": out}
+    return {"coarse_dims": list(dims), "Vc": Vc, "nb": nb, "per_store": out, "nrhs": nrhs_batch,
+            "batched": batched}
 
 
 def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
@@ -169,7 +194,7 @@ def kernel_mode(args):
         return
     if fam.startswith("coarse_mk"):
         store = {"f64": w.F64, "f32": w.F32, "bf16": w.BF16}[fam.split("_")[-1]]
-        res = coarse_apply_mk(w, torch, stores=(store,), reps=args.reps)
+        res = coarse_apply_mk(w, torch, stores=(store,), reps=args.reps, nrhs_batch=args.nrhs)
         print(json.dumps({"family": fam, **res}))
         return
     wl = WORKLOAD
@@ -214,6 +239,7 @@ def main():
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides for the batched coarse-apply kernel mode")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; N=%d is not supported (the path would shard by 4D domain "

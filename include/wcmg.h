@@ -194,8 +194,14 @@ int wcmg_coarse_destroy(wcmg_coarse* op);
  * (BF16: round to nearest even). */
 int wcmg_coarse_set(wcmg_coarse* op, const void* blocks, int src_prec);
 /* out = D_c in for nrhs fields [nrhs][Vc][Nb]: complex128 for F64 storage,
- * complex64 otherwise (FP32 accumulation). */
+ * complex64 otherwise (FP32 accumulation).  With FP32/BF16 storage and several
+ * right-hand sides the product runs on the matrix cores (each site and
+ * direction is a complex [Nb x Nb] x [Nb x nrhs] GEMM), up to 16 per launch. */
 int wcmg_coarse_apply(wcmg_coarse* op, const void* in, void* out, int nrhs);
+/* Kernel choice for wcmg_coarse_apply: 0 automatic (matrix cores from 4
+ * right-hand sides on), 1 per-row vector kernel, 2 matrix cores (FP32/BF16
+ * storage, Nb in {8, 16, 24, 32, 40}).  WCMG_ERR_ARG when unsupported. */
+int wcmg_coarse_set_kernel(wcmg_coarse* op, int kernel);
 /* Time `reps` back-to-back applies between HIP events on the op's stream;
  * *avg_ms receives the mean launch duration. */
 int wcmg_coarse_time(wcmg_coarse* op, const void* in, void* out, int nrhs, int reps, double* avg_ms);

@@ -213,7 +213,7 @@ int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks) {
     require(level >= 1 && level < c.nlev && blocks, WCMG_ERR_ARG, "level must name a coarse level");
     CoarseOp& C = *c.cop[level - 1];
     WCMG_HIP(hipMemcpyAsync(C.M64.p, blocks, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
-    for (int q = 0; q < 3; ++q) C.fresh[q] = false;
+    C.invalidate();
     C.refresh(WCMG_F64, c.stream);
     C.refresh(WCMG_F32, c.stream);
     if (C.nb % 4 == 0) C.refresh(WCMG_BF16, c.stream);
@@ -398,6 +398,7 @@ int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, dou
 struct wcmg_coarse {
   CoarseOp op;
   int store = WCMG_F32;
+  int kernel = 0;
   hipStream_t stream = nullptr;
   std::string err;
 };
@@ -454,8 +455,9 @@ int wcmg_coarse_set(wcmg_coarse* h, const void* blocks, int src_prec) {
       WCMG_HIP(hipMemcpyAsync(o.op.M64.p, blocks, n * sizeof(cd64), hipMemcpyDeviceToDevice, o.stream));
     else
       launch_c64_to_c128((const cf32*)blocks, o.op.M64.as<cd64>(), n, o.stream);
-    for (int q = 0; q < 3; ++q) o.op.fresh[q] = false;
+    o.op.invalidate();
     o.op.refresh(o.store, o.stream);
+    if (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb)) o.op.refresh_mfma(o.store, o.stream);
     WCMG_HIP(hipStreamSynchronize(o.stream));
     // the canonical master is only needed to build the device layout
     o.op.M64.release();
@@ -466,7 +468,16 @@ int wcmg_coarse_set(wcmg_coarse* h, const void* blocks, int src_prec) {
 int wcmg_coarse_apply(wcmg_coarse* h, const void* in, void* out, int nrhs) {
   return guarded_c(h, [&](wcmg_coarse& o) {
     require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
-    o.op.apply(o.store, in, out, 0x1ff, 0, nrhs, nullptr, o.stream);
+    o.op.apply_batch(o.store, in, out, nrhs, o.kernel, nullptr, 0, o.stream);
+  });
+}
+
+int wcmg_coarse_set_kernel(wcmg_coarse* h, int kernel) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(kernel >= 0 && kernel <= 2, WCMG_ERR_ARG, "kernel must be 0 (auto), 1 (vector) or 2 (matrix cores)");
+    require(kernel != 2 || (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb)), WCMG_ERR_ARG,
+            "matrix-core kernel needs FP32/BF16 storage and Nb in {8,16,24,32,40}");
+    o.kernel = kernel;
   });
 }
 
@@ -477,7 +488,7 @@ int wcmg_coarse_time(wcmg_coarse* h, const void* in, void* out, int nrhs, int re
     WCMG_HIP(hipEventCreate(&a));
     WCMG_HIP(hipEventCreate(&b));
     WCMG_HIP(hipEventRecord(a, o.stream));
-    for (int i = 0; i < reps; ++i) o.op.apply(o.store, in, out, 0x1ff, 0, nrhs, nullptr, o.stream);
+    for (int i = 0; i < reps; ++i) o.op.apply_batch(o.store, in, out, nrhs, o.kernel, nullptr, 0, o.stream);
     WCMG_HIP(hipEventRecord(b, o.stream));
     WCMG_HIP(hipEventSynchronize(b));
     float ms = 0.f;

@@ -30,6 +30,19 @@ struct BlkTraits<WCMG_BF16> {
 struct alignas(16) Chunk16 {
   uint32_t w[4];
 };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A chunk of the block stream, read once per apply: non-temporal, so the
+// stream does not evict from L2 the neighbour vectors that nine sites share.
+__device__ inline Chunk16 load_stream(const Chunk16* p) {
+  const u32x4 raw = __builtin_nontemporal_load((const u32x4*)p);
+  Chunk16 c;
+  c.w[0] = raw.x;
+  c.w[1] = raw.y;
+  c.w[2] = raw.z;
+  c.w[3] = raw.w;
+  return c;
+}
 
 template <int P>
 __device__ inline void decode(const Chunk16& c, cplx<typename BlkTraits<P>::R> (&m)[BlkTraits<P>::K]) {
@@ -85,7 +98,7 @@ __device__ inline cplx<typename BlkTraits<P>::R> coarse_row(const Chunk16* __res
         if (q < nq) {
           const int d = q / (nq / 9), jc = q - d * (nq / 9);
           if ((dmask >> d) & 1) {
-            Chunk16 c = blk[(long)q * rows + t];
+            const Chunk16 c = load_stream(blk + (long)q * rows + t);
             cplx<R> m[K];
             decode<P>(c, m);
             const cplx<R>* phi = in + src[d] * nb + jc * K;
@@ -102,7 +115,7 @@ __device__ inline cplx<typename BlkTraits<P>::R> coarse_row(const Chunk16* __res
       for (int q = sub; q < nq; q += S) {
         const int d = q / nchunk, jc = q - d * nchunk;
         if (!((dmask >> d) & 1)) continue;
-        Chunk16 c = blk[(long)q * rows + t];
+        const Chunk16 c = load_stream(blk + (long)q * rows + t);
         cplx<R> m[K];
         decode<P>(c, m);
         const cplx<R>* phi = in + src[d] * nb + jc * K;

@@ -62,8 +62,17 @@ struct CoarseOp {
   DevBuf M64;   // canonical [V][9][nb][nb]
   DevBuf dev[3];
   bool fresh[3] = {false, false, false};
+  DevBuf mfma[3];  // fragment-ordered blocks for the matrix-core kernel (F32, BF16)
+  bool mfma_fresh[3] = {false, false, false};
   void init_geometry(const int Lc[4], int nb_, hipStream_t st);
   void refresh(int prec, hipStream_t st);  // canonical -> device layout of prec
+  void refresh_mfma(int prec, hipStream_t st);
+  void invalidate() {
+    for (int q = 0; q < 3; ++q) fresh[q] = mfma_fresh[q] = false;
+  }
+  // nrhs right-hand sides (RHS-major); kernel: 0 auto, 1 per-row vector kernel, 2 matrix cores
+  void apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,
+                   hipStream_t st);
   void apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
 };
 

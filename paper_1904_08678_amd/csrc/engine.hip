@@ -93,6 +93,32 @@ void CoarseOp::refresh(int prec, hipStream_t st) {
   fresh[prec] = true;
 }
 
+void CoarseOp::refresh_mfma(int prec, hipStream_t st) {
+  if (mfma_fresh[prec]) return;
+  mfma[prec].alloc(mfma_block_bytes(V, nb, prec));
+  launch_blocks_to_mfma(M64.as<cd64>(), V, nb, prec, mfma[prec].p, st);
+  mfma_fresh[prec] = true;
+}
+
+void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,
+                           hipStream_t st) {
+  const bool can_mfma = prec != WCMG_F64 && mfma_supported_nb(nb);
+  const bool use_mfma = can_mfma && (kernel == 2 || (kernel == 0 && nrhs >= 4));
+  require(kernel != 2 || can_mfma, WCMG_ERR_ARG, "matrix-core kernel needs FP32/BF16 storage and Nb in {8,16,24,32,40}");
+  if (use_mfma) {
+    require(mfma_fresh[prec], WCMG_ERR_STATE, "matrix-core block layout not built");
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      const int k = std::min(16, nrhs - r0);
+      const long off = (long)r0 * V * nb;
+      launch_coarse_apply_mfma(prec, nb, mfma[prec].p, (const cf32*)in + off, (cf32*)out + off, nbr.as<int>(), V, k,
+                               run ? run + (long)r0 * run_stride : nullptr, run_stride, st);
+    }
+  } else {
+    require(run == nullptr || run_stride == 0, WCMG_ERR_ARG, "per-RHS flags need the matrix-core kernel");
+    apply(prec, in, out, 0x1ff, 0, nrhs, run, st);
+  }
+}
+
 void CoarseOp::apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run,
                      hipStream_t st) {
   require(fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
@@ -628,7 +654,7 @@ void Context::galerkin(int l) {
     launch_galerkin_project(W, T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.coarse_of.as<int>(), nbr_d, T.A,
                             T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
   }
-  for (int q = 0; q < 3; ++q) C.fresh[q] = false;
+  C.invalidate();
   C.refresh(WCMG_F64, stream);
   if (p.cycle_prec == WCMG_F32 || p.setup_prec == WCMG_F32) C.refresh(store_prec_for(l + 1, true), stream);
   sync();

@@ -30,6 +30,13 @@ void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st);
 void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
                          int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
 
+// ---- batched coarse apply on the matrix cores (coarse_mfma.hip)
+bool mfma_supported_nb(int nb);
+size_t mfma_block_bytes(long Vc, int nb, int prec);
+void launch_blocks_to_mfma(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
+void launch_coarse_apply_mfma(int prec, int nb, const void* blk, const cf32* in, cf32* out, const int* nbr, long Vc,
+                              int nrhs, const int* run, int run_stride, hipStream_t st);
+
 // ---- transfer and coarsening (transfer.hip)
 bool supported_nb(int nb);
 template <typename R>

@@ -76,6 +76,7 @@ def lib():
         l.wcmg_coarse_destroy.argtypes = [vp]
         l.wcmg_coarse_set.argtypes = [vp, vp, ip]
         l.wcmg_coarse_apply.argtypes = [vp, vp, vp, ip]
+        l.wcmg_coarse_set_kernel.argtypes = [vp, ip]
         l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
         l.wcmg_coarse_last_error.argtypes = [vp]
         l.wcmg_coarse_last_error.restype = C.c_char_p
@@ -289,6 +290,10 @@ class CoarseOperator:
     def set(self, blocks: torch.Tensor):
         prec = F64 if blocks.dtype == torch.complex128 else F32
         self._chk(lib().wcmg_coarse_set(self.h, _ptr(blocks), prec))
+
+    def set_kernel(self, kernel: int):
+        """0 automatic, 1 per-row vector kernel, 2 matrix cores."""
+        self._chk(lib().wcmg_coarse_set_kernel(self.h, int(kernel)))
 
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         nrhs = x.numel() // (self.Vc * self.nb)

@@ -354,3 +354,26 @@ def test_fused_coarse_gmres_matches_generic_path(fixed):
     assert rel(outs[0], outs[1]) < 1e-11
     assert abs(infos[0]["outer_iters"] - infos[1]["outer_iters"]) <= 1
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
+
+
+@pytest.mark.parametrize("Lc,nb,nrhs", [((2, 2, 2, 2), 8, 12), ((3, 2, 2, 4), 16, 5), ((4, 4, 4, 8), 24, 12),
+                                         ((2, 3, 2, 2), 24, 16), ((3, 3, 2, 2), 32, 12), ((2, 2, 2, 2), 40, 17)])
+def test_coarse_apply_matrix_cores_parity(Lc, nb, nrhs):
+    """Batched coarse apply on the matrix cores (complex GEMM per site and
+    direction) against the oracle, FP32 and BF16 storage; also equal to the
+    per-row vector kernel on the same inputs."""
+    w = wc()
+    Vc = int(np.prod(Lc))
+    blocks = syn.complex_gaussian((Vc, 9, nb, nb), 311)
+    phi = syn.complex_gaussian((nrhs, Vc, nb), 312)
+    for store in (w.F32, w.BF16):
+        op = w.CoarseOperator(Lc, nb, store)
+        op.set(dev(blocks))
+        ref = oracle.coarse_apply(Lc, blocks if store == w.F32 else bf16_round(blocks), phi)
+        x = dev(phi.astype(np.complex64))
+        op.set_kernel(2)
+        got = host(op.apply(x))
+        assert rel(got, ref) < 1e-5
+        op.set_kernel(1)
+        got1 = host(op.apply(x))
+        assert rel(got, got1) < 1e-5
