@@ -169,6 +169,28 @@ typedef struct {
  * info: host array of nrhs entries (may be NULL). */
 int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info* info);
 
+/* Batched form of wcmg_solve: the right-hand sides are taken in groups of up
+ * to 16, and each group is solved together, one FP64 FGMRES per right-hand
+ * side advancing through shared launches (every Dslash, restrict, prolong and
+ * coarse apply covers the group; with FP32/BF16 coarse storage and Nb in
+ * {8,16,24,32,40} the coarse apply of a group of >= 4 runs on the matrix
+ * cores).  A converged right-hand side is masked out of the group's launches.
+ * Each solve is the method of wcmg_solve; results differ from it only by
+ * rounding order.  b, x as in wcmg_solve (x holds the initial guesses).
+ * flags: bit 0 (WCMG_BATCH_GRAPH) captures the preconditioner application in a
+ *          HIP graph on its second use and replays it (the cycle then runs
+ *          without host checks: inner solves run their iteration limits,
+ *          predicated off once converged; the cycle must be FP32);
+ *        bits 1-2: coarse apply kernel, 0 auto, 1 per-row vector kernel,
+ *          2 matrix cores (WCMG_BATCH_VECTOR, WCMG_BATCH_MFMA).
+ * info: host array of nrhs entries (may be NULL); t_solve_s, coarse_iters and
+ * cycles are those of the whole group.  Errors: WCMG_ERR_ARG for bad flags or
+ * fields; WCMG_ERR_NOCONV / WCMG_ERR_NAN as wcmg_solve (x is written). */
+#define WCMG_BATCH_GRAPH 1
+#define WCMG_BATCH_VECTOR 2
+#define WCMG_BATCH_MFMA 4
+int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flags, wcmg_solve_info* info);
+
 /* Per-phase timers in seconds: [0] setup total, [1] relaxation, [2] Gram-Schmidt,
  * [3] coarsening, [4] refinement, [5] last solve.  n entries are written. */
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);

@@ -371,6 +371,73 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
   return status;
 }
 
+int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flags, wcmg_solve_info* info) {
+  int status = WCMG_OK;
+  int rc = guarded(ctx, [&](Context& c) {
+    require(c.gauge_set, WCMG_ERR_STATE, "gauge field not set");
+    require(c.nlev == 1 || c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
+    require(b && x && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    require((flags & ~7) == 0 && ((flags >> 1) & 3) != 3, WCMG_ERR_ARG, "bad flags");
+    const bool graph = flags & WCMG_BATCH_GRAPH;
+    require(!graph || c.p.cycle_prec == WCMG_F32, WCMG_ERR_ARG, "graph capture needs an FP32 cycle");
+    const long V = c.geo[0].V, nn = c.n(0);
+    c.coarse_kernel = (flags >> 1) & 3;
+    c.use_graph = graph;
+    struct Reset {
+      Context& c;
+      ~Reset() {
+        c.coarse_kernel = 0;
+        c.use_graph = false;
+        c.drop_graph();
+      }
+    } reset{c};
+    for (int k0 = 0; k0 < nrhs; k0 += 16) {
+      const int B = std::min(16, nrhs - k0);
+      auto t0 = std::chrono::steady_clock::now();
+      c.coarse_iters = 0;
+      c.cycles = 0;
+      cd64* b64 = c.buf<cd64>("bsolve_b", B * nn);
+      cd64* x64 = c.buf<cd64>("bsolve_x", B * nn);
+      cd64* r64 = c.buf<cd64>("bsolve_r", B * nn);
+      cd64* nrm = c.buf<cd64>("bsolve_n", 2L * B);
+      launch_pack_fermion<double, double>((const cd64*)b + k0 * nn, c.perm0.as<int>(), V, B, b64, c.stream);
+      launch_pack_fermion<double, double>((const cd64*)x + k0 * nn, c.perm0.as<int>(), V, B, x64, c.stream);
+      int its[16] = {0};
+      c.solve_batched(b64, x64, B, its);
+      // true residuals in FP64
+      c.apply_opB<double>(0, x64, r64, B, nullptr, 0);
+      launch_belem<cd64, cd64>(r64, nn, b64, nn, r64, nn, nullptr, 0, nn, B, 2, nullptr, 0, c.stream);
+      launch_bdot<double>(r64, 0, nn, 1, r64, nn, nn, B, c.bpart.as<cd64>(), nrm, 1, 2, 0, nullptr, 0, c.stream);
+      launch_bdot<double>(b64, 0, nn, 1, b64, nn, nn, B, c.bpart.as<cd64>(), nrm + 1, 1, 2, 0, nullptr, 0, c.stream);
+      cd64 hn[32];
+      WCMG_HIP(hipMemcpyAsync(hn, nrm, 2 * B * sizeof(cd64), hipMemcpyDeviceToHost, c.stream));
+      launch_unpack_fermion<double, double>(x64, c.perm0.as<int>(), V, B, (cd64*)x + k0 * nn, c.stream);
+      c.sync();
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      c.timers[5] = dt;
+      for (int r = 0; r < B; ++r) {
+        const double rr = hn[2 * r].re, bb = hn[2 * r + 1].re;
+        const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        const bool conv = rel <= c.p.outer_tol;
+        if (!(rel == rel)) status = WCMG_ERR_NAN;
+        else if (!conv && status == WCMG_OK) status = WCMG_ERR_NOCONV;
+        if (info) {
+          wcmg_solve_info& I = info[k0 + r];
+          I.outer_iters = its[r];
+          I.converged = conv ? 1 : 0;
+          I.true_rel_res = rel;
+          I.t_solve_s = dt;
+          I.coarse_iters = c.coarse_iters;
+          I.cycles = c.cycles;
+        }
+      }
+    }
+  });
+  if (rc != WCMG_OK) return rc;
+  if (status != WCMG_OK) ctx->err = status == WCMG_ERR_NAN ? "NaN in residual" : "solver did not converge";
+  return status;
+}
+
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n) {
   return guarded(ctx, [&](Context& c) {
     require(out_host != nullptr && n >= 0, WCMG_ERR_ARG, "bad output");

@@ -16,9 +16,9 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const Chunk16* __restrict_
                                                        const cplx<typename BlkTraits<P>::R>* __restrict__ in,
                                                        cplx<typename BlkTraits<P>::R>* __restrict__ out,
                                                        const int* __restrict__ nbr, long Vc, int nb_rt, int dmask,
-                                                       int accumulate, const int* __restrict__ run) {
+                                                       int accumulate, const int* __restrict__ run, int rs) {
   typedef typename BlkTraits<P>::R R;
-  if (run && !*run) return;
+  if (run && !run[(long)blockIdx.y * rs]) return;
   const int nb = NB > 0 ? NB : nb_rt;
   const long rows = Vc * nb;
   const long g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -102,43 +102,43 @@ void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st) {
 
 template <int P, int NB, int S>
 static void launch_ca(const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb, int dmask,
-                      int accumulate, int nrhs, const int* run, hipStream_t st) {
+                      int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
   typedef typename BlkTraits<P>::R R;
   long rows = Vc * nb;
   hipLaunchKernelGGL((k_coarse_apply<P, NB, S>), dim3(nblocks(rows * S), nrhs), dim3(kBlock), 0, st,
-                     (const Chunk16*)blk, (const cplx<R>*)in, (cplx<R>*)out, nbr, Vc, nb, dmask, accumulate, run);
+                     (const Chunk16*)blk, (const cplx<R>*)in, (cplx<R>*)out, nbr, Vc, nb, dmask, accumulate, run, rs);
 }
 
 template <int P, int NB>
 static void dispatch_s(const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb, int dmask,
-                       int accumulate, int nrhs, const int* run, hipStream_t st) {
+                       int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
   switch (coarse_split(Vc * nb * nrhs)) {
-    case 1: launch_ca<P, NB, 1>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 2: launch_ca<P, NB, 2>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 4: launch_ca<P, NB, 4>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    default: launch_ca<P, NB, 8>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
+    case 1: launch_ca<P, NB, 1>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 2: launch_ca<P, NB, 2>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 4: launch_ca<P, NB, 4>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    default: launch_ca<P, NB, 8>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
   }
 }
 
 template <int P>
 static void dispatch_nb(const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb, int dmask,
-                        int accumulate, int nrhs, const int* run, hipStream_t st) {
+                        int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
   switch (nb) {
-    case 8: dispatch_s<P, 8>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 12: dispatch_s<P, 12>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 16: dispatch_s<P, 16>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 24: dispatch_s<P, 24>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 32: dispatch_s<P, 32>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    case 40: dispatch_s<P, 40>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
-    default: dispatch_s<P, 0>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st); break;
+    case 8: dispatch_s<P, 8>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 12: dispatch_s<P, 12>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 16: dispatch_s<P, 16>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 24: dispatch_s<P, 24>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 32: dispatch_s<P, 32>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    case 40: dispatch_s<P, 40>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
+    default: dispatch_s<P, 0>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs); break;
   }
 }
 
 void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
-                         int dmask, int accumulate, int nrhs, const int* run, hipStream_t st) {
-  if (prec == WCMG_F64) dispatch_nb<WCMG_F64>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st);
-  else if (prec == WCMG_F32) dispatch_nb<WCMG_F32>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st);
-  else dispatch_nb<WCMG_BF16>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st);
+                         int dmask, int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
+  if (prec == WCMG_F64) dispatch_nb<WCMG_F64>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs);
+  else if (prec == WCMG_F32) dispatch_nb<WCMG_F32>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs);
+  else dispatch_nb<WCMG_BF16>(blk, in, out, nbr, Vc, nb, dmask, accumulate, nrhs, run, st, rs);
   WCMG_CHECK_LAUNCH();
 }
 

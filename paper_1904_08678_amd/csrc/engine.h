@@ -73,7 +73,34 @@ struct CoarseOp {
   // nrhs right-hand sides (RHS-major); kernel: 0 auto, 1 per-row vector kernel, 2 matrix cores
   void apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,
                    hipStream_t st);
-  void apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
+  void apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run, hipStream_t st,
+             int run_stride = 0);
+};
+
+// B independent (F)GMRES solves advancing through shared launches.  Basis
+// vectors are stored [k][r][n] so that v_k of all right-hand sides is one
+// RHS-major batch; scalars and state words are per right-hand side.
+struct BatchGmres {
+  int m = 0, B = 0, prec = 0;
+  long n = 0;
+  bool flex = false;
+  long ss = 0;  // cd64 scalars per right-hand side
+  DevBuf V, Z, w, S, st;
+};
+
+// Operator or preconditioner on a batch: (in, out, run flags, flag stride).
+template <typename R>
+using BatchOp = std::function<void(const cplx<R>*, cplx<R>*, const int*, int)>;
+
+// A captured preconditioner application (one batched cycle) and the buffers
+// and flags it was captured with.
+struct CycleGraph {
+  hipGraphExec_t exec = nullptr;
+  int l = -1, B = 0, rs = 0;
+  const void* in = nullptr;
+  void* out = nullptr;
+  const int* run = nullptr;
+  bool warm = false;
 };
 
 struct GmresState {
@@ -101,6 +128,15 @@ struct Context {
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::map<std::string, std::unique_ptr<GmresState>> gm;
   DevBuf partial, scratch64;
+  // batched solves
+  std::map<std::string, std::unique_ptr<BatchGmres>> bgm;
+  DevBuf bpart;               // reduction partials [B][blocks][m]
+  int coarse_kernel = 0;      // 0 auto, 1 per-row vector kernel, 2 matrix cores
+  bool use_graph = false;     // capture the batched cycle in a HIP graph
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  CycleGraph cgraph;
+  int64_t graph_launches = 0;
   int* pinned = nullptr;  // host-pinned status words
   double timers[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t coarse_iters = 0, cycles = 0;
@@ -151,6 +187,23 @@ struct Context {
   template <typename R>
   double norm2_host(const cplx<R>* v, long n);
   void sync();
+
+  // batched path (engine_batch.hip): B right-hand sides, RHS-major fields
+  BatchGmres& bgmres_state(const std::string& tag, int m, long n, int B, int prec, bool flex);
+  template <typename R>
+  void apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int* run, int rs);
+  template <typename R>
+  void mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const int* run, int rs);
+  template <typename R>
+  void cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run, int rs);
+  void precondition64B(int l, const cd64* r, cd64* x, int B, const int* run, int rs);
+  template <typename R>
+  void gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, const cplx<R>* b, cplx<R>* x, bool x0_zero,
+              int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent, int prs,
+              int check_every, int* iters);
+  void drop_graph();
+  // solve D x_r = b_r, r < B (device-order FP64 fields); per-RHS outer iterations
+  void solve_batched(const cd64* b, cd64* x, int B, int* iters);
 };
 
 }  // namespace wcmg

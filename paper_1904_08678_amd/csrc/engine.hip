@@ -114,15 +114,15 @@ void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int ke
                                run ? run + (long)r0 * run_stride : nullptr, run_stride, st);
     }
   } else {
-    require(run == nullptr || run_stride == 0, WCMG_ERR_ARG, "per-RHS flags need the matrix-core kernel");
-    apply(prec, in, out, 0x1ff, 0, nrhs, run, st);
+    apply(prec, in, out, 0x1ff, 0, nrhs, run, st, run_stride);
   }
 }
 
 void CoarseOp::apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run,
-                     hipStream_t st) {
+                     hipStream_t st, int run_stride) {
   require(fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
-  launch_coarse_apply(prec, dev[prec].p, in, out, nbr.as<int>(), V, nb, dmask, accumulate, nrhs, run, st);
+  launch_coarse_apply(prec, dev[prec].p, in, out, nbr.as<int>(), V, nb, dmask, accumulate, nrhs, run, st,
+                      run_stride);
 }
 
 // ---------------------------------------------------------------- context
@@ -242,7 +242,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   }
   partial.alloc(kPartialSlots * sizeof(cd64));
   scratch64.alloc(64 * sizeof(cd64));
-  WCMG_HIP(hipHostMalloc((void**)&pinned, 64 * sizeof(int), hipHostMallocDefault));
+  WCMG_HIP(hipHostMalloc((void**)&pinned, 256 * sizeof(int), hipHostMallocDefault));
   const long V0 = geo[0].V;
   U_lex.alloc(V0 * 36 * sizeof(cd64));
   clover_lex.alloc(V0 * 72 * sizeof(cd64));
@@ -253,6 +253,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
 }
 
 Context::~Context() {
+  drop_graph();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
 }
 

@@ -20,7 +20,7 @@ template <typename Ti, typename To>
 void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr);
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0);
 int wilson_blocks(long V);
 
 // ---- coarse operator (coarse.hip)
@@ -28,7 +28,7 @@ size_t device_block_bytes(long Vc, int nb, int prec);
 void launch_blocks_to_device(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
 void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st);
 void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
-                         int dmask, int accumulate, int nrhs, const int* run, hipStream_t st);
+                         int dmask, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
 
 // ---- batched coarse apply on the matrix cores (coarse_mfma.hip)
 bool mfma_supported_nb(int nb);
@@ -41,10 +41,10 @@ void launch_coarse_apply_mfma(int prec, int nb, const void* blk, const cf32* in,
 bool supported_nb(int nb);
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
-                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st);
+                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs = 0);
 template <typename R>
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
-                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st);
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
 void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
                                  int* breakdown, hipStream_t st);
 void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st);
@@ -102,6 +102,31 @@ void launch_cg_orth(cplx<R>* V, int j, cplx<R>* w, long n, const cd64* part_in, 
                     cd64* part_out, const int* run, hipStream_t st);
 void launch_cg_givens(int* stw, cd64* S, int m, int j, const cd64* part, int G, double tol, int limit, int fixed,
                       hipStream_t st);
+
+// ---- batched vector kernels (blas_batch.hip)
+int bred_blocks(long n);
+template <typename R>
+void launch_bdot(const cplx<R>* a, long avs, long ars, int m, const cplx<R>* b, long brs, long n, int B,
+                 cd64* partial, cd64* out, int ostride, long ors, int mode, const int* run, int rs, hipStream_t st);
+void launch_bdot_finish(const cd64* partial, int G, int m, int mstride, int B, cd64* out, int ostride, long ors,
+                        int mode, const int* run, int rs, hipStream_t st);
+template <typename R>
+void launch_bmulti_axpy(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const int* m_dev, int ms,
+                        const cd64* coef, int cks, long crs, double sign, long n, int B, cd64* norm_part,
+                        const int* run, int rs, hipStream_t st);
+template <typename Ti, typename To>
+void launch_belem(To* y, long yrs, const Ti* x, long xrs, const Ti* z, long zrs, const cd64* nrm2, long nrs, long n,
+                  int B, int op, const int* run, int rs, hipStream_t st);
+template <typename R>
+void launch_bmr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long rsf, const cd64* dots, long n, int B,
+                       const int* run, int rs, hipStream_t st);
+void launch_bgmres_init(int* st_, int B, const int* parent, int prs, hipStream_t st);
+void launch_bgmres_cycle_start(int* st_, cd64* S, long ss, int B, int m, double tol, int limit, int fixed,
+                               hipStream_t st);
+void launch_bgmres_givens(int* st_, cd64* S, long ss, int B, int m, int j, double tol, int limit, int fixed,
+                          int stop_on_est, hipStream_t st);
+void launch_bgmres_solve_y(const int* st_, cd64* S, long ss, int B, int m, hipStream_t st);
+void launch_bgmres_cycle_end(int* st_, int B, hipStream_t st);
 
 constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
 

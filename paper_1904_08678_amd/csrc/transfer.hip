@@ -45,8 +45,8 @@ template <typename R, int NB>
 __global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fine, cplx<R>* __restrict__ coarse,
                                                    const cplx<R>* __restrict__ P, FieldLayout lay,
                                                    const int* __restrict__ agg_sites, int A, long Vc,
-                                                   const int* __restrict__ run) {
-  if (run && !*run) return;
+                                                   const int* __restrict__ run, int rs) {
+  if (run && !run[(long)blockIdx.y * rs]) return;
   constexpr int nv = NB / 2;
   __shared__ cd64 lds[16 * NB];
   __shared__ cd64 res[NB];
@@ -85,8 +85,8 @@ template <typename R, int NB>
 __global__ void __launch_bounds__(256) k_prolong(const cplx<R>* __restrict__ coarse, cplx<R>* __restrict__ fine,
                                                   const cplx<R>* __restrict__ P, FieldLayout lay,
                                                   const int* __restrict__ coarse_of, long Vc, int accumulate,
-                                                  const int* __restrict__ run) {
-  if (run && !*run) return;
+                                                  const int* __restrict__ run, int rs) {
+  if (run && !run[(long)blockIdx.y * rs]) return;
   constexpr int nv = NB / 2;
   const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (s >= lay.V) return;
@@ -269,23 +269,23 @@ bool supported_nb(int nb) {
 
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
-                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st) {
+                     int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
   NB_SWITCH(nb, hipLaunchKernelGGL((k_restrict<R, NBc>), dim3(Vc, nrhs), dim3(kBlock), 0, st, fine, coarse, P, lay,
-                                    agg_sites, A, Vc, run));
+                                    agg_sites, A, Vc, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 template <typename R>
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
-                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st) {
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
   NB_SWITCH(nb, hipLaunchKernelGGL((k_prolong<R, NBc>), dim3(nblocks(lay.V), nrhs), dim3(kBlock), 0, st, coarse,
-                                    fine, P, lay, coarse_of, Vc, accumulate, run));
+                                    fine, P, lay, coarse_of, Vc, accumulate, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 #define INST_TR(R)                                                                                                 \
   template void launch_restrict<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, int, long, int, \
-                                   int, const int*, hipStream_t);                                                  \
+                                   int, const int*, hipStream_t, int);                                             \
   template void launch_prolong<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, long, int, int, \
-                                  int, const int*, hipStream_t);
+                                  int, const int*, hipStream_t, int);
 INST_TR(double)
 INST_TR(float)
 

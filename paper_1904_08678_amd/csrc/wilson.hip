@@ -363,8 +363,8 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                                  const int* __restrict__ nbr, long V, int terms,
-                                                 cd64* __restrict__ dots, const int* __restrict__ run) {
-  if (run && !*run) return;
+                                                 cd64* __restrict__ dots, const int* __restrict__ run, int rs) {
+  if (run && !run[(long)blockIdx.y * rs]) return;
   __shared__ cplx<R> part[4][12][64];
   __shared__ cd64 red[8];
   const int lane = threadIdx.x & 63;
@@ -494,15 +494,15 @@ INST_PACK(float, double)
 
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots) {
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs) {
   hipLaunchKernelGGL(k_wilson<R>, dim3(nblocks(V, 64), nrhs), dim3(kBlock), 0, st, in, out, U, clov, nbr, V, terms,
-                     dots, run);
+                     dots, run, rs);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
-                                    const int*, hipStream_t, cd64*);
+                                    const int*, hipStream_t, cd64*, int);
 template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
-                                   const int*, hipStream_t, cd64*);
+                                   const int*, hipStream_t, cd64*, int);
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 

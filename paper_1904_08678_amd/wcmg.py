@@ -11,6 +11,7 @@ import os
 import torch
 
 F64, F32, BF16 = 0, 1, 2
+BATCH_GRAPH, BATCH_VECTOR, BATCH_MFMA = 1, 2, 4
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libwcmg.so")
 _lib = None
@@ -69,6 +70,7 @@ def lib():
             getattr(l, name).argtypes = [vp, ip, vp, vp, ip, ip]
         l.wcmg_cycle.argtypes = [vp, vp, vp]
         l.wcmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(SolveInfo)]
+        l.wcmg_solve_batched.argtypes = [vp, vp, vp, ip, ip, C.POINTER(SolveInfo)]
         l.wcmg_timers.argtypes = [vp, C.POINTER(C.c_double), ip]
         l.wcmg_profile_enable.argtypes = [vp, C.c_char_p, ip]
         l.wcmg_profile_stats.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -242,6 +244,21 @@ class Context:
             x = torch.zeros_like(b)
         info = (SolveInfo * nrhs)()
         st = lib().wcmg_solve(self.h, _ptr(b), _ptr(x), nrhs, info)
+        if check and st not in (0,):
+            self._chk(st)
+        infos = [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
+                      t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters, cycles=i.cycles) for i in info]
+        return x, infos, st
+
+    def solve_batched(self, b: torch.Tensor, x: torch.Tensor | None = None, graph=False, kernel="auto",
+                      check=True):
+        """wcmg_solve_batched: groups of up to 16 right-hand sides solved together."""
+        nrhs = b.numel() // (self.V * 12)
+        if x is None:
+            x = torch.zeros_like(b)
+        flags = (BATCH_GRAPH if graph else 0) | {"auto": 0, "vector": BATCH_VECTOR, "mfma": BATCH_MFMA}[kernel]
+        info = (SolveInfo * nrhs)()
+        st = lib().wcmg_solve_batched(self.h, _ptr(b), _ptr(x), nrhs, flags, info)
         if check and st not in (0,):
             self._chk(st)
         infos = [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
