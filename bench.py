@@ -38,20 +38,28 @@ WORKLOAD = dict(
 )
 
 
-def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int) -> float:
-    """Bytes a launch must move at minimum (each operand read once, output written once)."""
+WORKLOAD_BATCH = dict(
+    name="two-level MG, 24^3x48, Nb=24 (4^4 aggregates, 12 vectors), 1 refinement iteration, 12 point sources "
+         "(one per spin-colour) solved together, FGMRES(20) to 1e-10",
+    L=(24, 24, 24, 48), eps=0.25, m0=-0.08, csw=1.0, block=(4, 4, 4, 4), nv=12, relax=20, refine=1, seed=104,
+)
+
+
+def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int = 1) -> float:
+    """Bytes a launch must move at minimum (each operand read once, output written
+    once); with nrhs fields per launch the gauge data and P are read once."""
     if family == "dslash_f64":
-        return 1536.0 * V          # links 576 + clover 576 + in 192 + out 192 (FP64)
+        return (1152.0 + 384.0 * nrhs) * V   # links 576 + clover 576, in 192 + out 192 per field (FP64)
     if family == "dslash_f32":
-        return 768.0 * V           # links 288 + clover 288 + in 96 + out 96 (FP32)
+        return (576.0 + 192.0 * nrhs) * V    # links 288 + clover 288, in 96 + out 96 per field (FP32)
     if family.startswith("coarse_apply"):
         sb = {"coarse_apply_f64": 16, "coarse_apply_f32": 8, "coarse_apply_bf16": 4}[family]
         sv = 16 if family.endswith("f64") else 8
         return (9.0 * nb * nb * sb + 2.0 * nb * sv) * Vc
     if family in ("restrict_f32", "prolong_f32"):
-        return (nv * 12 * 8.0 + 12 * 8.0) * V
+        return (nv * 12 * 8.0 + 12 * 8.0 * nrhs) * V
     if family in ("restrict_f64", "prolong_f64"):
-        return (nv * 12 * 16.0 + 12 * 16.0) * V
+        return (nv * 12 * 16.0 + 12 * 16.0 * nrhs) * V
     return float("nan")
 
 
@@ -153,6 +161,89 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
             "batched": batched}
 
 
+def batched_point_sources(w, torch, wl, fp64=True):
+    """Twelve point sources on the 24^3 x 48 lattice: one batched solve (matrix-core
+    coarse apply; with and without the HIP-graph cycle; per-row coarse kernel for
+    comparison) against the same twelve solves one after another, mixed and FP64."""
+    import numpy as np
+    import synthetic as syn
+    L = wl["L"]
+    V = int(np.prod(L))
+    s = syn.config_seeds(wl["seed"])
+    Ud = torch.from_numpy(syn.gauge_field(L, wl["eps"], s["gauge"])).cuda()
+    startd = torch.from_numpy(syn.start_vectors(wl["nv"], V, 12, s["start"])).cuda()
+    bd = torch.from_numpy(syn.point_sources(V, site=0)).cuda()
+    out = {"workload": wl["name"], "nrhs": 12}
+    ctx = make_context(w, wl, mixed=True)
+    ctx.set_gauge(Ud)
+    ctx.set_null_vectors(0, startd)
+    ctx.setup()
+    out["setup_s"] = ctx.timers()["setup"]
+    fams = ["dslash_f32", "coarse_mfma_f32", "restrict_f32", "prolong_f32"]
+
+    def run(label, profile=False, **kw):
+        ctx.solve_batched(bd, **kw)  # first call allocates the batch's Krylov space
+        for f in fams:
+            ctx.profile(f, profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, st = ctx.solve_batched(bd, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"solve_s": dt, "outer_iters": [i["outer_iters"] for i in info],
+               "max_true_rel_res": max(i["true_rel_res"] for i in info),
+               "converged": all(i["converged"] for i in info) and st == 0,
+               "coarse_iters": info[0]["coarse_iters"]}
+        if profile:
+            rec["kernels"] = {}
+            for f in fams:
+                n, ms = ctx.profile_stats(f)
+                ctx.profile(f, False)
+                rec["kernels"][f] = {"launches": n, "total_ms": ms, "avg_ms": ms / max(n, 1)}
+        print("[bench] %s: %.3f s, iters %s, max res %.2e" % (label, dt, rec["outer_iters"],
+                                                              rec["max_true_rel_res"]), file=sys.stderr, flush=True)
+        del x
+        return rec
+
+    out["batched_mfma"] = run("batched (autotuned kernels)", profile=True)
+    out["tuner"] = ctx.tune_table()
+    out["batched_mfma_graph"] = run("batched + HIP graph", graph=True)
+    out["batched_vector"] = run("batched (per-row coarse kernel)", kernel="vector")
+    ctx.solve(bd[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info, st = ctx.solve(bd)
+    torch.cuda.synchronize()
+    out["sequential_mixed"] = {"solve_s": time.perf_counter() - t0, "outer_iters": [i["outer_iters"] for i in info],
+                               "max_true_rel_res": max(i["true_rel_res"] for i in info)}
+    print("[bench] 12 sequential mixed solves: %.3f s" % out["sequential_mixed"]["solve_s"], file=sys.stderr,
+          flush=True)
+    del ctx
+    torch.cuda.empty_cache()
+    if fp64:
+        c64 = make_context(w, wl, mixed=False)
+        c64.set_gauge(Ud)
+        c64.set_null_vectors(0, startd)
+        c64.setup()
+        c64.solve(bd[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, st = c64.solve(bd)
+        torch.cuda.synchronize()
+        out["sequential_fp64"] = {"solve_s": time.perf_counter() - t0,
+                                  "outer_iters": [i["outer_iters"] for i in info],
+                                  "max_true_rel_res": max(i["true_rel_res"] for i in info),
+                                  "setup_s": c64.timers()["setup"]}
+        print("[bench] 12 sequential FP64 solves: %.3f s" % out["sequential_fp64"]["solve_s"], file=sys.stderr,
+              flush=True)
+        best = min(out["batched_mfma"]["solve_s"], out["batched_mfma_graph"]["solve_s"])
+        out["speedup_batched_vs_fp64"] = out["sequential_fp64"]["solve_s"] / best
+        out["speedup_batched_vs_sequential_mixed"] = out["sequential_mixed"]["solve_s"] / best
+        del c64
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
     """Oracle (plain FP64 C++) on the host cores: seconds per outer FGMRES
     iteration at the same lattice and parameters, scaled to the GPU's outer
@@ -192,6 +283,24 @@ def kernel_mode(args):
         torch.cuda.synchronize()
         print(json.dumps({"family": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "reps": args.reps}))
         return
+    if fam == "batched_solve":
+        # setup plus one batched solve of the twelve point sources on 24^3 x 48
+        import synthetic as syn
+        wl = WORKLOAD_BATCH
+        L = wl["L"]
+        V = int(np.prod(L))
+        s = syn.config_seeds(wl["seed"])
+        ctx = make_context(w, wl, mixed=True)
+        ctx.set_gauge(torch.from_numpy(syn.gauge_field(L, wl["eps"], s["gauge"])).cuda())
+        ctx.set_null_vectors(0, torch.from_numpy(syn.start_vectors(wl["nv"], V, 12, s["start"])).cuda())
+        ctx.setup()
+        bd = torch.from_numpy(syn.point_sources(V, site=0)).cuda()
+        t0 = time.perf_counter()
+        x, info, st = ctx.solve_batched(bd, graph=args.graph)
+        torch.cuda.synchronize()
+        print(json.dumps({"family": fam, "solve_s": time.perf_counter() - t0, "status": st,
+                          "outer_iters": [i["outer_iters"] for i in info]}))
+        return
     if fam.startswith("coarse_mk"):
         store = {"f64": w.F64, "f32": w.F32, "bf16": w.BF16}[fam.split("_")[-1]]
         res = coarse_apply_mk(w, torch, stores=(store,), reps=args.reps, nrhs_batch=args.nrhs)
@@ -203,9 +312,11 @@ def kernel_mode(args):
     U, start, b = make_inputs(wl)
     ctx = make_context(w, wl, mixed=True)
     ctx.set_gauge(torch.from_numpy(U).cuda())
+    nr = max(1, args.nrhs)
     if fam in ("dslash_f32", "dslash_f64"):
         prec = w.F32 if fam.endswith("f32") else w.F64
         x = torch.from_numpy(b).cuda().to(torch.complex64 if prec == w.F32 else torch.complex128)
+        x = x.unsqueeze(0).repeat(nr, 1, 1, 1).contiguous()
         ctx.profile(fam, True)
         for _ in range(args.reps):
             ctx.apply_D(0, x, prec)
@@ -213,17 +324,18 @@ def kernel_mode(args):
     else:
         ctx.set_null_vectors(0, torch.from_numpy(start).cuda())
         ctx.setup()
-        x = torch.from_numpy(b).cuda().to(torch.complex64)
+        x = torch.from_numpy(b).cuda().to(torch.complex64).unsqueeze(0).repeat(nr, 1, 1, 1).contiguous()
+        xc = torch.zeros((nr, V // 256, 24), dtype=torch.complex64, device="cuda")
         ctx.profile(fam, True)
         for _ in range(args.reps):
             if fam == "restrict_f32":
                 ctx.restrict(0, x, w.F32)
             else:
-                ctx.prolong(0, torch.zeros((V // 256, 24), dtype=torch.complex64, device="cuda"), w.F32)
+                ctx.prolong(0, xc, w.F32)
         n, ms = ctx.profile_stats(fam)
-    bpl = algorithmic_bytes(fam, V, V // 256, 24, 12)
-    print(json.dumps({"family": fam, "launches": n, "avg_ms": ms / max(n, 1), "bytes_per_launch": bpl,
-                      "GB_s": bpl / (ms / max(n, 1)) / 1e6}))
+    bpl = algorithmic_bytes(fam, V, V // 256, 24, 12, nr)
+    print(json.dumps({"family": fam, "nrhs": nr, "launches": n, "avg_ms": ms / max(n, 1), "bytes_per_launch": bpl,
+                      "GB_s": bpl / (ms / max(n, 1)) / 1e6, "tuner": ctx.tune_table()}))
 
 
 def main():
@@ -234,10 +346,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mk", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
-                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy")
+                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
     ap.add_argument("--mib", type=int, default=1024)
     ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides for the batched coarse-apply kernel mode")
     args = ap.parse_args()
@@ -338,6 +452,9 @@ def main():
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)
         extra["coarse_apply_large"]["per_store"]["f32"]["traffic"] = counter_traffic("coarse_apply_f32_large")
+    if not args.no_batched:
+        print("[bench] batched point sources, 24^3x48", file=sys.stderr, flush=True)
+        extra["batched_24x48"] = batched_point_sources(w, torch, WORKLOAD_BATCH, fp64=not args.no_fp64)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)

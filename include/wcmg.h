@@ -180,16 +180,39 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
  * flags: bit 0 (WCMG_BATCH_GRAPH) captures the preconditioner application in a
  *          HIP graph on its second use and replays it (the cycle then runs
  *          without host checks: inner solves run their iteration limits,
- *          predicated off once converged; the cycle must be FP32);
+ *          predicated off once converged, and the coarsest GMRES is limited
+ *          to one restart cycle, min(coarse_maxit, coarse_restart)
+ *          iterations; the cycle must be FP32);
  *        bits 1-2: coarse apply kernel, 0 auto, 1 per-row vector kernel,
- *          2 matrix cores (WCMG_BATCH_VECTOR, WCMG_BATCH_MFMA).
+ *          2 matrix cores (WCMG_BATCH_VECTOR, WCMG_BATCH_MFMA);
+ *        bit 3 (WCMG_BATCH_DSLASH_PER_RHS): FP32 Dslash launched per
+ *          right-hand side instead of the shared-link multi-RHS kernel.
  * info: host array of nrhs entries (may be NULL); t_solve_s, coarse_iters and
  * cycles are those of the whole group.  Errors: WCMG_ERR_ARG for bad flags or
  * fields; WCMG_ERR_NOCONV / WCMG_ERR_NAN as wcmg_solve (x is written). */
 #define WCMG_BATCH_GRAPH 1
 #define WCMG_BATCH_VECTOR 2
 #define WCMG_BATCH_MFMA 4
+#define WCMG_BATCH_DSLASH_PER_RHS 8
 int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flags, wcmg_solve_info* info);
+
+/* Kernel autotuner of the batched path.  For each launch configuration met
+ * (operator, lattice or coarse-lattice size, block size, precision, number of
+ * right-hand sides) the library times every applicable kernel variant once on
+ * the live operands, keeps the fastest and reuses it; the result of a call
+ * never depends on whether it tuned.  Configurations decided so far form a
+ * table, exported as JSON text {"<configuration>": {"choice": v, "ms": [...]}}
+ * and accepted back (entries loaded are used as given, without timing).
+ *   wcmg_tune_enable: 0 = no timing (untuned configurations use the built-in
+ *     defaults), 1 = tune (default).
+ *   wcmg_tune_table: writes the JSON (NUL-terminated) to buf if it fits in len
+ *     bytes; *needed receives the length including the NUL.  WCMG_ERR_ARG if
+ *     it does not fit.
+ *   wcmg_tune_load: merges a table produced by wcmg_tune_table; WCMG_ERR_ARG
+ *     on malformed text. */
+int wcmg_tune_enable(wcmg_ctx* ctx, int enable);
+int wcmg_tune_table(wcmg_ctx* ctx, char* buf, int len, int* needed);
+int wcmg_tune_load(wcmg_ctx* ctx, const char* json);
 
 /* Per-phase timers in seconds: [0] setup total, [1] relaxation, [2] Gram-Schmidt,
  * [3] coarsening, [4] refinement, [5] last solve.  n entries are written. */

@@ -24,7 +24,9 @@ __device__ inline cd64 wave_sum(cd64 v) {
   return v;
 }
 
-// partial[blk][k] = sum over this block's range of conj(a_k[i]) b[i], k < m
+// partial[blk][k] = sum over this block's range of conj(a_k[i]) b[i], k < m.
+// The a_k are taken KT at a time, so b is read once per tile and KT
+// independent loads are in flight per element.
 template <typename R>
 __global__ void __launch_bounds__(256) k_dot_partial(const cplx<R>* __restrict__ a, long astride, int m,
                                                       const int* __restrict__ m_dev, const cplx<R>* __restrict__ b,
@@ -32,25 +34,35 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cplx<R>* __restrict__
                                                       const int* __restrict__ run) {
   if (run && !*run) return;
   if (m_dev) m = *m_dev;
-  __shared__ cd64 lds[4];
+  constexpr int KT = 8;
+  __shared__ cd64 lds[4][KT];
   const long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < m; ++k) {
-    const cplx<R>* ak = a + k * astride;
-    cd64 s = mkc(0.0, 0.0);
+  for (int k0 = 0; k0 < m; k0 += KT) {
+    cd64 s[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
     for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      cplx<R> x = ak[i], y = b[i];
-      s.re += (double)x.re * y.re + (double)x.im * y.im;
-      s.im += (double)x.re * y.im - (double)x.im * y.re;
+      const cplx<R> y = b[i];
+#pragma unroll
+      for (int q = 0; q < KT; ++q)
+        if (k0 + q < m) {
+          const cplx<R> x = a[(k0 + q) * astride + i];
+          s[q].re += (double)x.re * y.re + (double)x.im * y.im;
+          s[q].im += (double)x.re * y.im - (double)x.im * y.re;
+        }
     }
-    s = wave_sum(s);
-    if (lane == 0) lds[wave] = s;
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      s[q] = wave_sum(s[q]);
+      if (lane == 0) lds[wave][q] = s[q];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < KT && k0 + (int)threadIdx.x < m) {
       cd64 t = mkc(0.0, 0.0);
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
-      partial[(long)blockIdx.x * mstride + k] = t;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w][threadIdx.x]);
+      partial[(long)blockIdx.x * mstride + k0 + threadIdx.x] = t;
     }
     __syncthreads();
   }

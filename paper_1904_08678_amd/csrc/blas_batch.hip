@@ -23,7 +23,8 @@ __device__ inline cd64 wsum2(cd64 v) {
 __device__ inline bool live_r(const int* run, int rs, int r) { return !run || run[(long)r * rs]; }
 }  // namespace
 
-// partial[r][blk][k] = sum conj(a_{r,k}[i]) b_r[i] over this block's range, k < m
+// partial[r][blk][k] = sum conj(a_{r,k}[i]) b_r[i] over this block's range, k < m;
+// the a_k are taken KT at a time (b read once per tile, KT loads in flight).
 template <typename R>
 __global__ void __launch_bounds__(256) k_bdot_partial(const cplx<R>* __restrict__ a, long avs, long ars, int m,
                                                        const cplx<R>* __restrict__ b, long brs, long n,
@@ -31,30 +32,101 @@ __global__ void __launch_bounds__(256) k_bdot_partial(const cplx<R>* __restrict_
                                                        const int* __restrict__ run, int rs) {
   const int r = blockIdx.y;
   if (!live_r(run, rs, r)) return;
-  __shared__ cd64 lds[4];
+  constexpr int KT = 8;
+  __shared__ cd64 lds[4][KT];
   a += r * ars;
   b += r * brs;
   partial += (long)r * gridDim.x * mstride;
   const long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < m; ++k) {
-    const cplx<R>* ak = a + k * avs;
-    cd64 s = mkc(0.0, 0.0);
+  for (int k0 = 0; k0 < m; k0 += KT) {
+    cd64 s[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
     for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      cplx<R> x = ak[i], y = b[i];
-      s.re += (double)x.re * y.re + (double)x.im * y.im;
-      s.im += (double)x.re * y.im - (double)x.im * y.re;
+      const cplx<R> y = b[i];
+#pragma unroll
+      for (int q = 0; q < KT; ++q)
+        if (k0 + q < m) {
+          const cplx<R> x = a[(k0 + q) * avs + i];
+          s[q].re += (double)x.re * y.re + (double)x.im * y.im;
+          s[q].im += (double)x.re * y.im - (double)x.im * y.re;
+        }
     }
-    s = wsum2(s);
-    if (lane == 0) lds[wave] = s;
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      s[q] = wsum2(s[q]);
+      if (lane == 0) lds[wave][q] = s[q];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < KT && k0 + (int)threadIdx.x < m) {
       cd64 t = mkc(0.0, 0.0);
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
-      partial[(long)blockIdx.x * mstride + k] = t;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w][threadIdx.x]);
+      partial[(long)blockIdx.x * mstride + k0 + threadIdx.x] = t;
     }
     __syncthreads();
+  }
+}
+
+// Second half of a Gram-Schmidt pass in one sweep over the basis:
+//   y_r -= sum_{k<m} coef_r[k] V_{r,k}, then partial[r][blk][k] = <V_{r,k}, y_r> of
+// the updated y.  Each element's m basis entries stay in registers between the
+// update and the inner products (m <= kFusedMaxM).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bmulti_axpy_dot(cplx<R>* __restrict__ y, long yrs,
+                                                          const cplx<R>* __restrict__ V, long vvs, long vrs, int m,
+                                                          const cd64* __restrict__ coef, int cks, long crs, long n,
+                                                          cd64* __restrict__ partial, int mstride,
+                                                          const int* __restrict__ run, int rs) {
+  constexpr int MM = kFusedMaxM;
+  const int r = blockIdx.y;
+  if (!live_r(run, rs, r)) return;
+  __shared__ cd64 lds[4][MM];
+  y += r * yrs;
+  V += r * vrs;
+  coef += r * crs;
+  partial += (long)r * gridDim.x * mstride;
+  cplx<R> c[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    const cd64 v = k < m ? coef[(long)k * cks] : mkc(0.0, 0.0);
+    c[k] = mkc((R)-v.re, (R)-v.im);
+  }
+  cd64 s[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) s[k] = mkc(0.0, 0.0);
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    cplx<R> v[MM];
+#pragma unroll
+    for (int k = 0; k < MM; ++k)
+      if (k < m) v[k] = V[k * vvs + i];
+    cplx<R> acc = y[i];
+#pragma unroll
+    for (int k = 0; k < MM; ++k)
+      if (k < m) cfma(acc, c[k], v[k]);
+    y[i] = acc;
+#pragma unroll
+    for (int k = 0; k < MM; ++k)
+      if (k < m) {
+        s[k].re += (double)v[k].re * acc.re + (double)v[k].im * acc.im;
+        s[k].im += (double)v[k].re * acc.im - (double)v[k].im * acc.re;
+      }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < MM; ++k)
+    if (k < m) {
+      s[k] = wsum2(s[k]);
+      if (lane == 0) lds[wave][k] = s[k];
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    cd64 t = mkc(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w][threadIdx.x]);
+    partial[(long)blockIdx.x * mstride + threadIdx.x] = t;
   }
 }
 
@@ -313,6 +385,16 @@ void launch_bdot(const cplx<R>* a, long avs, long ars, int m, const cplx<R>* b, 
   WCMG_CHECK_LAUNCH();
 }
 
+template <typename R>
+void launch_bmulti_axpy_dot(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const cd64* coef,
+                            int cks, long crs, long n, int B, cd64* partial, const int* run, int rs, hipStream_t st) {
+  require(m >= 1 && m <= kFusedMaxM, WCMG_ERR_ARG, "fused Gram-Schmidt sweep takes at most 20 vectors");
+  const int G = red_b(n);
+  hipLaunchKernelGGL(k_bmulti_axpy_dot<R>, dim3(G, B), dim3(kBlock), 0, st, y, yrs, V, vvs, vrs, m, coef, cks, crs, n,
+                     partial, m, run, rs);
+  WCMG_CHECK_LAUNCH();
+}
+
 void launch_bdot_finish(const cd64* partial, int G, int m, int mstride, int B, cd64* out, int ostride, long ors,
                         int mode, const int* run, int rs, hipStream_t st) {
   hipLaunchKernelGGL(k_bdot_finish, dim3(m, B), dim3(kBlock), 0, st, partial, G, m, mstride, out, ostride, ors, mode,
@@ -374,7 +456,9 @@ void launch_bgmres_cycle_end(int* st_, int B, hipStream_t st) {
   template void launch_bmulti_axpy<R>(cplx<R>*, long, const cplx<R>*, long, long, int, const int*, int, const cd64*, \
                                       int, long, double, long, int, cd64*, const int*, int, hipStream_t);           \
   template void launch_bmr_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, const cd64*, long, int, const int*,    \
-                                     int, hipStream_t);
+                                     int, hipStream_t);                                                             \
+  template void launch_bmulti_axpy_dot<R>(cplx<R>*, long, const cplx<R>*, long, long, int, const cd64*, int, long,      \
+                                          long, int, cd64*, const int*, int, hipStream_t);
 INST_B(double)
 INST_B(float)
 template void launch_belem<cd64, cd64>(cd64*, long, const cd64*, long, const cd64*, long, const cd64*, long, long, int,

@@ -239,7 +239,8 @@ int wcmg_apply_D(wcmg_ctx* ctx, int level, const void* in, void* out, int nrhs, 
         cf32* a = c.buf<cf32>("abi_a32", nn * nrhs);
         cf32* b = c.buf<cf32>("abi_b32", nn * nrhs);
         launch_pack_fermion<float, float>((const cf32*)in, c.perm0.as<int>(), V, nrhs, a, c.stream);
-        c.apply_op<float>(0, a, b, nrhs, nullptr);
+        if (nrhs >= 2) c.apply_opB<float>(0, a, b, nrhs, nullptr, 0);  // links and clover shared by the batch
+        else c.apply_op<float>(0, a, b, nrhs, nullptr);
         launch_unpack_fermion<float, float>(b, c.perm0.as<int>(), V, nrhs, (cf32*)out, c.stream);
       }
     } else {
@@ -377,16 +378,18 @@ int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flag
     require(c.gauge_set, WCMG_ERR_STATE, "gauge field not set");
     require(c.nlev == 1 || c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
     require(b && x && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
-    require((flags & ~7) == 0 && ((flags >> 1) & 3) != 3, WCMG_ERR_ARG, "bad flags");
+    require((flags & ~15) == 0 && ((flags >> 1) & 3) != 3, WCMG_ERR_ARG, "bad flags");
     const bool graph = flags & WCMG_BATCH_GRAPH;
     require(!graph || c.p.cycle_prec == WCMG_F32, WCMG_ERR_ARG, "graph capture needs an FP32 cycle");
     const long V = c.geo[0].V, nn = c.n(0);
     c.coarse_kernel = (flags >> 1) & 3;
+    c.dslash_per_rhs = flags & WCMG_BATCH_DSLASH_PER_RHS;
     c.use_graph = graph;
     struct Reset {
       Context& c;
       ~Reset() {
         c.coarse_kernel = 0;
+        c.dslash_per_rhs = false;
         c.use_graph = false;
         c.drop_graph();
       }
@@ -436,6 +439,26 @@ int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flag
   if (rc != WCMG_OK) return rc;
   if (status != WCMG_OK) ctx->err = status == WCMG_ERR_NAN ? "NaN in residual" : "solver did not converge";
   return status;
+}
+
+int wcmg_tune_enable(wcmg_ctx* ctx, int enable) {
+  return guarded(ctx, [&](Context& c) { c.tuner.enabled = enable != 0; });
+}
+
+int wcmg_tune_table(wcmg_ctx* ctx, char* buf, int len, int* needed) {
+  return guarded(ctx, [&](Context& c) {
+    const std::string j = c.tuner.to_json();
+    if (needed) *needed = (int)j.size() + 1;
+    require(buf != nullptr && len >= (int)j.size() + 1, WCMG_ERR_ARG, "tuning table does not fit the buffer");
+    std::memcpy(buf, j.c_str(), j.size() + 1);
+  });
+}
+
+int wcmg_tune_load(wcmg_ctx* ctx, const char* json) {
+  return guarded(ctx, [&](Context& c) {
+    require(json != nullptr, WCMG_ERR_ARG, "null tuning table");
+    c.tuner.from_json(json);
+  });
 }
 
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n) {

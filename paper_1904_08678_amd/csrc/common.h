@@ -135,6 +135,24 @@ inline size_t cbytes(int prec) { return prec == WCMG_F64 ? 16 : 8; }
 constexpr int kBlock = 256;
 inline unsigned nblocks(long n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }
 
+// Workgroup -> (item, right-hand side) for launches over items x fields, with
+// the field varying fastest inside each XCD's contiguous share of the grid
+// (padded to a multiple of the 8 XCDs, which receive workgroups round-robin):
+// the workgroups that read the same item's operator data (links, clover, P)
+// run together on one XCD, so that data crosses HBM about once per launch and
+// is served from that XCD's L2 to the other fields.  Returns false for
+// padding workgroups.
+__device__ inline bool item_rhs(long n_items, int nrhs, long* item, long* rhs) {
+  const long G = gridDim.x;
+  const long h = blockIdx.x;
+  const long L = (h % 8) * (G / 8) + h / 8;
+  if (L >= n_items * nrhs) return false;
+  *item = L / nrhs;
+  *rhs = L % nrhs;
+  return true;
+}
+inline unsigned item_rhs_grid(long n_items, int nrhs) { return (unsigned)((n_items * nrhs + 7) / 8 * 8); }
+
 // Site geometry of one level as the kernels see it.
 //   layout SoA (level 0): element (site s, component k) at k * V + s
 //   layout AoS (levels >= 1): element at s * ns + k

@@ -92,6 +92,24 @@ struct BatchGmres {
 template <typename R>
 using BatchOp = std::function<void(const cplx<R>*, cplx<R>*, const int*, int)>;
 
+// Autotuner: for each launch configuration (operator, shape, batch size) it
+// times every applicable kernel variant once on the live operands, keeps the
+// fastest, and reuses that choice for the rest of the context's life.  The
+// table can be saved to and loaded from a small JSON file.
+struct Tuner {
+  bool enabled = true;
+  std::map<std::string, int> choice;
+  std::map<std::string, std::vector<double>> ms;  // measured mean ms per variant
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~Tuner();
+  // variant for key: looked up, or measured with run(v) for v < nvar (each
+  // candidate is launched reps + 1 times on stream st; its output is that of
+  // a normal launch, so the caller's result is unaffected)
+  int pick(const std::string& key, int nvar, const std::function<void(int)>& run, hipStream_t st, int fallback);
+  std::string to_json() const;
+  void from_json(const std::string& text);
+};
+
 // A captured preconditioner application (one batched cycle) and the buffers
 // and flags it was captured with.
 struct CycleGraph {
@@ -132,8 +150,11 @@ struct Context {
   std::map<std::string, std::unique_ptr<BatchGmres>> bgm;
   DevBuf bpart;               // reduction partials [B][blocks][m]
   int coarse_kernel = 0;      // 0 auto, 1 per-row vector kernel, 2 matrix cores
+  bool dslash_per_rhs = false;  // batched FP32 Dslash without shared links/clover
   bool use_graph = false;     // capture the batched cycle in a HIP graph
-  bool capturing = false;
+  bool no_checks = false;     // batched cycle without host checks (graph semantics)
+  bool capturing = false;     // inside stream capture: no events, no tuning
+  Tuner tuner;
   hipStream_t cap_stream = nullptr;
   CycleGraph cgraph;
   int64_t graph_launches = 0;
@@ -202,6 +223,8 @@ struct Context {
               int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent, int prs,
               int check_every, int* iters);
   void drop_graph();
+  void dslash32_batch(const cf32* in, cf32* out, int B, const int* run, int rs, cd64* dots);
+  std::string dslash_key(int B) const;
   // solve D x_r = b_r, r < B (device-order FP64 fields); per-RHS outer iterations
   void solve_batched(const cd64* b, cd64* x, int B, int* iters);
 };

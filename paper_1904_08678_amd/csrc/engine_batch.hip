@@ -22,6 +22,76 @@ long scalars_per_rhs(int m) { return (long)(m + 1) * m + 2 * m + (m + 1) + m + 8
 constexpr int kMaxBatch = 16;
 }  // namespace
 
+Tuner::~Tuner() {
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>& run, hipStream_t st,
+                int fallback) {
+  auto it = choice.find(key);
+  if (it != choice.end()) return it->second;
+  if (!enabled || nvar <= 1) return fallback;
+  if (!ev[0]) {
+    WCMG_HIP(hipEventCreate(&ev[0]));
+    WCMG_HIP(hipEventCreate(&ev[1]));
+  }
+  constexpr int reps = 3;
+  std::vector<double> t(nvar, 0.0);
+  for (int v = 0; v < nvar; ++v) {
+    run(v);  // warm: first-touch, caches, code load
+    WCMG_HIP(hipEventRecord(ev[0], st));
+    for (int q = 0; q < reps; ++q) run(v);
+    WCMG_HIP(hipEventRecord(ev[1], st));
+    WCMG_HIP(hipEventSynchronize(ev[1]));
+    float e = 0.f;
+    WCMG_HIP(hipEventElapsedTime(&e, ev[0], ev[1]));
+    t[v] = e / reps;
+  }
+  int best = 0;
+  for (int v = 1; v < nvar; ++v)
+    if (t[v] < t[best]) best = v;
+  choice[key] = best;
+  ms[key] = t;
+  return best;
+}
+
+std::string Tuner::to_json() const {
+  std::string o = "{";
+  bool first = true;
+  for (auto& kv : choice) {
+    o += first ? "\"" : ", \"";
+    first = false;
+    o += kv.first + "\": {\"choice\": " + std::to_string(kv.second) + ", \"ms\": [";
+    auto m = ms.find(kv.first);
+    if (m != ms.end())
+      for (size_t i = 0; i < m->second.size(); ++i) {
+        char b[32];
+        snprintf(b, sizeof b, "%s%.5f", i ? ", " : "", m->second[i]);
+        o += b;
+      }
+    o += "]}";
+  }
+  return o + "}";
+}
+
+// Reads back what to_json wrote: "key": {"choice": n, ...} entries.
+void Tuner::from_json(const std::string& text) {
+  size_t pos = 0;
+  while (true) {
+    const size_t k0 = text.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = text.find('"', k0 + 1);
+    require(k1 != std::string::npos, WCMG_ERR_ARG, "tuning table: unterminated key");
+    const std::string key = text.substr(k0 + 1, k1 - k0 - 1);
+    const size_t c = text.find("\"choice\":", k1);
+    require(c != std::string::npos, WCMG_ERR_ARG, "tuning table: entry without a choice");
+    choice[key] = std::atoi(text.c_str() + c + 9);
+    pos = text.find('}', c);
+    if (pos == std::string::npos) break;
+  }
+}
+
 BatchGmres& Context::bgmres_state(const std::string& tag, int m, long n_, int B, int prec, bool flex) {
   auto& g = bgm[tag];
   if (!g) g.reset(new BatchGmres());
@@ -49,6 +119,29 @@ void Context::drop_graph() {
   cgraph = CycleGraph();
 }
 
+// FP32 Dslash on a batch: variant 0 launches the per-field kernel (fields of
+// one site block grouped on one XCD), variant 1 the multi-RHS kernel that
+// stages the gauge data in LDS.
+void Context::dslash32_batch(const cf32* in, cf32* out, int B, const int* run, int rs, cd64* dots) {
+  auto launch = [&](int v) {
+    if (v == 1)
+      launch_wilson_mrhs(in, out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V, B, run, rs,
+                         dots, stream);
+    else
+      launch_wilson<float>(in, out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V, 0x1ff, B,
+                           run, stream, dots, rs);
+  };
+  int v = 0;
+  if (dslash_per_rhs || B < 2) v = 0;
+  else if (capturing) v = tuner.choice.count(dslash_key(B)) ? tuner.choice[dslash_key(B)] : 1;
+  else v = tuner.pick(dslash_key(B), 2, launch, stream, 1);
+  launch(v);
+}
+
+std::string Context::dslash_key(int B) const {
+  return "dslash_f32 V=" + std::to_string(geo[0].V) + " nrhs=" + std::to_string(B);
+}
+
 template <typename R>
 void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int* run, int rs) {
   const bool single = sizeof(R) == 4;
@@ -56,8 +149,7 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
     const char* fam = single ? "dslash_f32" : "dslash_f64";
     if (!capturing) prof.begin(fam, stream);
     if (single)
-      launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
-                           geo[0].V, 0x1ff, B, run, stream, nullptr, rs);
+      dslash32_batch((const cf32*)in, (cf32*)out, B, run, rs, nullptr);
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
                             geo[0].V, 0x1ff, B, run, stream, nullptr, rs);
@@ -66,8 +158,18 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
   }
   const int prec = store_prec_for(l, single);
   CoarseOp& C = *cop[l - 1];
-  const bool mfma = prec != WCMG_F64 && mfma_supported_nb(C.nb) &&
-                    (coarse_kernel == 2 || (coarse_kernel == 0 && B >= 4));
+  const bool can_mfma = prec != WCMG_F64 && mfma_supported_nb(C.nb);
+  bool mfma = false;
+  if (can_mfma && coarse_kernel == 2) mfma = true;
+  else if (can_mfma && coarse_kernel == 0) {
+    C.refresh_mfma(prec, stream);
+    const std::string key = "coarse_apply prec=" + std::to_string(prec) + " Vc=" + std::to_string(C.V) +
+                            " nb=" + std::to_string(C.nb) + " nrhs=" + std::to_string(B);
+    if (capturing) mfma = tuner.choice.count(key) ? tuner.choice[key] == 1 : B >= 4;
+    else
+      mfma = tuner.pick(key, 2, [&](int v) { C.apply_batch(prec, in, out, B, v == 1 ? 2 : 1, run, rs, stream); },
+                        stream, B >= 4 ? 1 : 0) == 1;
+  }
   if (mfma) C.refresh_mfma(prec, stream);
   const char* fam = mfma ? (prec == WCMG_F32 ? "coarse_mfma_f32" : "coarse_mfma_bf16")
                          : prec == WCMG_F64 ? "coarse_apply_f64"
@@ -93,8 +195,7 @@ void Context::mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const i
     cd64* part = buf<cd64>("bmr_part" + t, 2L * G * B);
     for (int k = 0; k < steps; ++k) {
       if (sizeof(R) == 4)
-        launch_wilson<float>((const cf32*)r, (cf32*)pp, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
-                             geo[0].V, 0x1ff, B, run, stream, part, rs);
+        dslash32_batch((const cf32*)r, (cf32*)pp, B, run, rs, part);
       else
         launch_wilson<double>((const cd64*)r, (cd64*)pp, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
                               geo[0].V, 0x1ff, B, run, stream, part, rs);
@@ -167,8 +268,15 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
       A(zj, w, run, 8);
       // classical Gram-Schmidt applied twice; |w|^2 from the last update
       launch_bdot<R>(V, bn, nn, j + 1, w, nn, nn, B, part, H + j, m, ss, 0, run, 8, stream);
-      launch_bmulti_axpy<R>(w, nn, V, bn, nn, j + 1, nullptr, 0, H + j, m, ss, -1.0, nn, B, nullptr, run, 8, stream);
-      launch_bdot<R>(V, bn, nn, j + 1, w, nn, nn, B, part, tmp, 1, ss, 0, run, 8, stream);
+      if (j + 1 <= kFusedMaxM) {
+        // first update and second projection in one sweep over the basis
+        launch_bmulti_axpy_dot<R>(w, nn, V, bn, nn, j + 1, H + j, m, ss, nn, B, part, run, 8, stream);
+        launch_bdot_finish(part, Gb, j + 1, j + 1, B, tmp, 1, ss, 0, run, 8, stream);
+      } else {
+        launch_bmulti_axpy<R>(w, nn, V, bn, nn, j + 1, nullptr, 0, H + j, m, ss, -1.0, nn, B, nullptr, run, 8,
+                              stream);
+        launch_bdot<R>(V, bn, nn, j + 1, w, nn, nn, B, part, tmp, 1, ss, 0, run, 8, stream);
+      }
       launch_bdot_finish(part, Gb, j + 1, j + 1, B, H + j, m, ss, 1, run, 8, stream);
       launch_bmulti_axpy<R>(w, nn, V, bn, nn, j + 1, nullptr, 0, tmp, 1, ss, -1.0, nn, B, part, run, 8, stream);
       launch_bdot_finish(part, Gb, 1, 1, B, misc + 3, 1, ss, 0, run, 8, stream);
@@ -212,7 +320,7 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
     launch_restrict<R>(r, rc, P, geo[l].lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nb, B, run, stream, rs);
     if (!capturing) prof.end(fam, stream);
   }
-  const int check = (capturing || (p.reserved[0] & 1)) ? 0 : 4;
+  const int check = (no_checks || (p.reserved[0] & 1)) ? 0 : 4;
   const int prec = sizeof(R) == 8 ? 0 : 1;
   BatchOp<R> Ab = [this, lc, B](const cplx<R>* i, cplx<R>* o, const int* rn, int s) {
     apply_opB<R>(lc, i, o, B, rn, s);
@@ -220,8 +328,11 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
   std::vector<int> its(B, 0);
   if (lc + 1 >= nlev) {
     BatchGmres& G = bgmres_state("bcg" + t, p.coarse_restart, nc, B, prec, false);
-    gmresB<R>(G, Ab, nullptr, rc, ec, true, p.coarse_restart, p.coarse_maxit, p.coarse_tol, p.coarse_fixed_iters, true,
-              run, rs, check, check > 0 ? its.data() : nullptr);
+    // without host checks every enqueued iteration costs launches even once
+    // predicated off, so the graph form runs at most one restart cycle
+    const int maxit = no_checks ? std::min(p.coarse_maxit, p.coarse_restart) : p.coarse_maxit;
+    gmresB<R>(G, Ab, nullptr, rc, ec, true, p.coarse_restart, maxit, p.coarse_tol, p.coarse_fixed_iters, true, run, rs,
+              check, check > 0 ? its.data() : nullptr);
   } else if (p.kcycle) {
     BatchOp<R> Mc = [this, lc, B](const cplx<R>* i, cplx<R>* o, const int* rn, int s) {
       cycleB<R>(lc, i, o, B, rn, s);
@@ -267,10 +378,9 @@ void Context::precondition64B(int l, const cd64* r, cd64* x, int B, const int* r
   } else if (!same || !cgraph.warm) {
     // first use with these buffers: run eagerly (allocates every workspace)
     drop_graph();
-    const bool save = capturing;
-    capturing = true;  // same launch sequence as the captured one: no host checks
+    no_checks = true;  // same launch sequence as the captured one: no host checks
     cycleB<float>(l, r32, x32, B, run, rs);
-    capturing = save;
+    no_checks = false;
     cgraph.l = l;
     cgraph.B = B;
     cgraph.rs = rs;
@@ -282,7 +392,7 @@ void Context::precondition64B(int l, const cd64* r, cd64* x, int B, const int* r
     if (!cap_stream) WCMG_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     hipStream_t saved = stream;
     stream = cap_stream;
-    capturing = true;
+    capturing = no_checks = true;
     hipGraph_t graph = nullptr;
     WCMG_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
     try {
@@ -291,12 +401,12 @@ void Context::precondition64B(int l, const cd64* r, cd64* x, int B, const int* r
       (void)hipStreamEndCapture(cap_stream, &graph);
       if (graph) (void)hipGraphDestroy(graph);
       stream = saved;
-      capturing = false;
+      capturing = no_checks = false;
       throw;
     }
     WCMG_HIP(hipStreamEndCapture(cap_stream, &graph));
     stream = saved;
-    capturing = false;
+    capturing = no_checks = false;
     hipGraphExec_t exec = nullptr;
     WCMG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);

@@ -22,6 +22,10 @@ template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0);
 int wilson_blocks(long V);
+// FP32 D on nrhs fields with the links and clover read once per launch; MR
+// partials (optional) at dots[2 * (r * wilson_blocks(V) + blk)]
+void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* clov, const int* nbr, long V, int nrhs,
+                        const int* run, int rs, cd64* dots, hipStream_t st);
 
 // ---- coarse operator (coarse.hip)
 size_t device_block_bytes(long Vc, int nb, int prec);
@@ -110,6 +114,12 @@ void launch_bdot(const cplx<R>* a, long avs, long ars, int m, const cplx<R>* b, 
                  cd64* partial, cd64* out, int ostride, long ors, int mode, const int* run, int rs, hipStream_t st);
 void launch_bdot_finish(const cd64* partial, int G, int m, int mstride, int B, cd64* out, int ostride, long ors,
                         int mode, const int* run, int rs, hipStream_t st);
+// y_r -= V_r coef_r and partials of V_r^dag y_r in one sweep (m <= kFusedMaxM);
+// partial layout [r][bred_blocks(n)][m]
+constexpr int kFusedMaxM = 20;
+template <typename R>
+void launch_bmulti_axpy_dot(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const cd64* coef,
+                            int cks, long crs, long n, int B, cd64* partial, const int* run, int rs, hipStream_t st);
 template <typename R>
 void launch_bmulti_axpy(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const int* m_dev, int ms,
                         const cd64* coef, int cks, long crs, double sign, long n, int B, cd64* norm_part,

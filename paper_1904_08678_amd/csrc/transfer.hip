@@ -40,18 +40,18 @@ __device__ inline void block_sum(cd64 (&acc)[NB], cd64* lds /*[16][NB]*/, cd64* 
 }
 
 // coarse(c, b) = sum_{x in c} sum_{k in chi(b)} conj(P_{b mod nv}(x)_k) fine(x)_k
-// grid (Vc, nrhs), block 256.
+// grid item_rhs_grid(Vc, nrhs), block 256.
 template <typename R, int NB>
 __global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fine, cplx<R>* __restrict__ coarse,
                                                    const cplx<R>* __restrict__ P, FieldLayout lay,
                                                    const int* __restrict__ agg_sites, int A, long Vc,
-                                                   const int* __restrict__ run, int rs) {
-  if (run && !run[(long)blockIdx.y * rs]) return;
+                                                   int nrhs, const int* __restrict__ run, int rs) {
+  long c, r;
+  if (!item_rhs(Vc, nrhs, &c, &r)) return;
+  if (run && !run[r * rs]) return;
   constexpr int nv = NB / 2;
   __shared__ cd64 lds[16 * NB];
   __shared__ cd64 res[NB];
-  const long c = blockIdx.x;
-  const long r = blockIdx.y;
   fine += r * lay.size();
   coarse += r * Vc * NB;
   const int h = lay.ns / 2;
@@ -80,17 +80,19 @@ __global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fi
   if (threadIdx.x < NB) coarse[c * NB + threadIdx.x] = ccast<R>(res[threadIdx.x]);
 }
 
-// fine(x)_k (+)= sum_{i} P_i(x)_k coarse(c(x), chi(k) * nv + i); thread per site.
+// fine(x)_k (+)= sum_{i} P_i(x)_k coarse(c(x), chi(k) * nv + i); thread per site,
+// grid item_rhs_grid(site blocks, nrhs).
 template <typename R, int NB>
 __global__ void __launch_bounds__(256) k_prolong(const cplx<R>* __restrict__ coarse, cplx<R>* __restrict__ fine,
                                                   const cplx<R>* __restrict__ P, FieldLayout lay,
                                                   const int* __restrict__ coarse_of, long Vc, int accumulate,
-                                                  const int* __restrict__ run, int rs) {
-  if (run && !run[(long)blockIdx.y * rs]) return;
+                                                  int nrhs, const int* __restrict__ run, int rs) {
+  long sb, r;
+  if (!item_rhs((lay.V + blockDim.x - 1) / blockDim.x, nrhs, &sb, &r)) return;
+  if (run && !run[r * rs]) return;
   constexpr int nv = NB / 2;
-  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long s = sb * blockDim.x + threadIdx.x;
   if (s >= lay.V) return;
-  const long r = blockIdx.y;
   fine += r * lay.size();
   coarse += r * Vc * NB;
   const long c = coarse_of[s];
@@ -270,15 +272,15 @@ bool supported_nb(int nb) {
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, hipLaunchKernelGGL((k_restrict<R, NBc>), dim3(Vc, nrhs), dim3(kBlock), 0, st, fine, coarse, P, lay,
-                                    agg_sites, A, Vc, run, rs));
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(kBlock), 0, st, fine,
+                                    coarse, P, lay, agg_sites, A, Vc, nrhs, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 template <typename R>
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
                     long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, hipLaunchKernelGGL((k_prolong<R, NBc>), dim3(nblocks(lay.V), nrhs), dim3(kBlock), 0, st, coarse,
-                                    fine, P, lay, coarse_of, Vc, accumulate, run, rs));
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
+                                    coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 #define INST_TR(R)                                                                                                 \

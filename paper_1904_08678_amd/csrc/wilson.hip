@@ -283,19 +283,12 @@ __device__ inline void reconstruct_add(cplx<R> (&acc)[12], const cplx<R> (&h)[6]
   }
 }
 
+// acc += the hop term along (MU, FWD) for neighbour spinor p and link u
+// (u = U_mu(x) for +mu, U_mu(x - mu) for -mu, whose adjoint is applied).
 template <typename R, int MU, bool FWD>
-__device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
-                           const int* __restrict__ nbr, long V, long s) {
-  const long y = nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s];
-  cplx<R> p[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = in[(long)k * V + y];
+__device__ inline void hop_core(cplx<R> (&acc)[12], const cplx<R> (&p)[12], const cplx<R> (&u)[9]) {
   cplx<R> h[6];
   project<R, MU, FWD>(p, h);
-  const long ls = FWD ? s : y;
-  cplx<R> u[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[(long)(MU * 9 + e) * V + ls];
   cplx<R> g[6];
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
@@ -312,6 +305,20 @@ __device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, c
   reconstruct_add<R, MU, FWD>(acc, g);
 }
 
+template <typename R, int MU, bool FWD>
+__device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                           const int* __restrict__ nbr, long V, long s) {
+  const long y = nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s];
+  cplx<R> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = in[(long)k * V + y];
+  const long ls = FWD ? s : y;
+  cplx<R> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[(long)(MU * 9 + e) * V + ls];
+  hop_core<R, MU, FWD>(acc, p, u);
+}
+
 // out = sum of the selected terms of D applied to in.
 // terms: bit 0 = Mdiag ((4+m0) + C), bit d (1..8) = Mdir_d.
 //
@@ -323,6 +330,23 @@ __device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, c
 // dots != nullptr: per-workgroup partials of <out, in> and <out, out> (the
 // inner products of an MR step, where in = r and out = D r) go to
 // dots[2*blk], dots[2*blk+1].
+// acc[chi*6 .. chi*6+5] += (block chi of (4 + m0) + C) p, block given by its
+// 36 packed reals e (6 diagonal entries, then the 15 entries below the diagonal).
+template <typename R, int chi>
+__device__ inline void clover_block_apply(cplx<R> (&acc)[12], const R (&e)[36], const cplx<R> (&p)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[chi * 6 + i] = cadd(acc[chi * 6 + i], cscale(e[i], p[i]));
+  int idx = 0;
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j, ++idx) {
+      const cplx<R> a = mkc(e[6 + 2 * idx], e[7 + 2 * idx]);
+      cfma(acc[chi * 6 + i], a, p[j]);
+      cfmac(acc[chi * 6 + j], a, p[i]);
+    }
+}
+
 template <typename R, int chi>
 __device__ inline void clover_chirality(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in,
                                         const R* __restrict__ clov, long V, long s) {
@@ -346,33 +370,24 @@ __device__ inline void clover_chirality(cplx<R> (&acc)[12], const cplx<R>* __res
   cplx<R> p[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) p[k] = in[(long)(chi * 6 + k) * V + s];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) acc[chi * 6 + i] = cadd(acc[chi * 6 + i], cscale(e[i], p[i]));
-  int idx = 0;
-#pragma unroll
-  for (int i = 1; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < i; ++j, ++idx) {
-      const cplx<R> a = mkc(e[6 + 2 * idx], e[7 + 2 * idx]);
-      cfma(acc[chi * 6 + i], a, p[j]);
-      cfmac(acc[chi * 6 + j], a, p[i]);
-    }
+  clover_block_apply<R, chi>(acc, e, p);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
-                                                 const int* __restrict__ nbr, long V, int terms,
+                                                 const int* __restrict__ nbr, long V, int terms, int nrhs,
                                                  cd64* __restrict__ dots, const int* __restrict__ run, int rs) {
-  if (run && !run[(long)blockIdx.y * rs]) return;
+  const long nblk = (V + 63) / 64;
+  long blk, r;
+  if (!item_rhs(nblk, nrhs, &blk, &r)) return;
+  if (run && !run[r * rs]) return;
   __shared__ cplx<R> part[4][12][64];
   __shared__ cd64 red[8];
   const int lane = threadIdx.x & 63;
   const int mu = threadIdx.x >> 6;  // wave-uniform
-  const long blk = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
   const long s = blk * 64 + lane;
   const bool valid = s < V;
-  const long r = blockIdx.y;
   in += r * 12 * V;
   out += r * 12 * V;
   cplx<R> acc[12];
@@ -435,9 +450,150 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
         a = cadd(a, red[2 * w]);
         b = cadd(b, red[2 * w + 1]);
       }
-      const long bi = blockIdx.y * gridDim.x + blockIdx.x;
+      const long bi = r * nblk + blk;
       dots[2 * bi] = a;
       dots[2 * bi + 1] = b;
+    }
+  }
+}
+
+// Raw buffer access to one FP32 spinor field [12][V]: a 32-bit per-lane byte
+// offset (the site) plus a wave-uniform one (the component), so a neighbour
+// costs one address VGPR instead of a 64-bit pointer per component.  Accesses
+// past the field's size read 0 and are not written.
+struct SpinorBuf {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ SpinorBuf(const cf32* base, long V)
+      : rs(__builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(12 * V * 8), 0x00020000)) {}
+  __device__ cf32 ld(unsigned site_off, unsigned comp_off) const {
+    return __builtin_bit_cast(cf32, __builtin_amdgcn_raw_buffer_load_b64(rs, site_off, comp_off, 0));
+  }
+  __device__ void st(cf32 v, unsigned site_off, unsigned comp_off) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
+                                          rs, site_off, comp_off, 0);
+  }
+};
+
+// Several right-hand sides at once (FP32).  A workgroup owns 64 consecutive
+// sites and first stages their links (U_mu(x) and U_mu(x - mu), 8 x 9 complex)
+// and clover blocks (2 x 36 reals) in LDS; wave w then applies the whole
+// operator to right-hand sides w, w + 4, ... with lane = site, reading the
+// gauge data from LDS.  Links and clover thus cross HBM once per launch
+// instead of once per right-hand side.  dots: per-(RHS, workgroup) partials
+// of <out, in> and <out, out> at dots[2 * (r * gridDim.x + blk)].
+__global__ void __launch_bounds__(512) k_wilson_mrhs(const cf32* __restrict__ in, cf32* __restrict__ out,
+                                                      const cf32* __restrict__ U, const float* __restrict__ clov,
+                                                      const int* __restrict__ nbr, long V, int B,
+                                                      cd64* __restrict__ dots, const int* __restrict__ run, int rs) {
+  __shared__ cf32 lnk[8][9][64];
+  __shared__ float4 clv[2][9][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar)
+  const int nw = blockDim.x >> 6;
+  const long blk = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
+  const long s = blk * 64 + lane;
+  const bool valid = s < V;
+  const long sv = valid ? s : 0;  // in-bounds stand-in for the tail lanes
+  // stage: thread (wave, lane) loads rows wave, wave + nw, ... of its site
+  {
+    int yb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) yb[mu] = nbr[(long)(2 * mu + 1) * V + sv];
+    for (int q = wave; q < 72; q += nw) {
+      const int d = q / 9, e = q - 9 * (q / 9), mu = d >> 1;
+      const long site = (d & 1) ? (long)yb[mu] : sv;
+      lnk[d][e][lane] = U[(long)(mu * 9 + e) * V + site];
+    }
+    const float4* cb = (const float4*)clov;
+    for (int q = wave; q < 18; q += nw) {
+      const int chi = q / 9, c = q - 9 * (q / 9);
+      clv[chi][c][lane] = cb[((long)chi * 9 + c) * V + sv];
+    }
+  }
+  // right-hand sides still running, as a wave-uniform bit mask (B <= 64)
+  const bool on_lane = lane < B && (!run || run[(long)lane * rs]);
+  const uint64_t act = __ballot(on_lane);
+  const int nact = __popcll(act);
+  __syncthreads();
+  int yn[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) yn[d] = nbr[(long)d * V + sv];
+  const unsigned so = (unsigned)sv * 8u;
+  const unsigned cs = (unsigned)V * 8u;  // component stride in bytes
+  // wave w takes the active right-hand sides w, w + nw, ...
+  for (int j = wave; j < nact; j += nw) {
+    // re-read the gauge data from LDS per right-hand side: kept in registers
+    // across the loop it would not fit the register file
+    asm volatile("" ::: "memory");
+    uint64_t m = act;
+    for (int t = 0; t < j; ++t) m &= m - 1;  // drop the j lowest set bits
+    const long r = __builtin_ctzll(m);
+    const SpinorBuf inb(in + r * 12 * V, V);
+    cf32 acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = mkc(0.f, 0.f);
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      float e[36];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const float4 v = clv[chi][c][lane];
+        e[4 * c] = v.x;
+        e[4 * c + 1] = v.y;
+        e[4 * c + 2] = v.z;
+        e[4 * c + 3] = v.w;
+      }
+      cf32 p[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) p[k] = inb.ld(so, (chi * 6 + k) * cs);
+      if (chi == 0) clover_block_apply<float, 0>(acc, e, p);
+      else clover_block_apply<float, 1>(acc, e, p);
+    }
+#define WCMG_MRHS_HOP(MU, FWD)                                                  \
+    {                                                                           \
+      constexpr int d = 2 * MU + (FWD ? 0 : 1);                                 \
+      cf32 p[12], u[9];                                                         \
+      const unsigned yo = (unsigned)yn[d] * 8u;                                 \
+      _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = inb.ld(yo, k * cs); \
+      _Pragma("unroll") for (int e = 0; e < 9; ++e) u[e] = lnk[d][e][lane];     \
+      hop_core<float, MU, FWD>(acc, p, u);                                      \
+    }
+    WCMG_MRHS_HOP(0, true)
+    WCMG_MRHS_HOP(0, false)
+    WCMG_MRHS_HOP(1, true)
+    WCMG_MRHS_HOP(1, false)
+    WCMG_MRHS_HOP(2, true)
+    WCMG_MRHS_HOP(2, false)
+    WCMG_MRHS_HOP(3, true)
+    WCMG_MRHS_HOP(3, false)
+#undef WCMG_MRHS_HOP
+    double pr = 0.0, pi = 0.0, pp = 0.0;
+    if (valid) {
+      const SpinorBuf outb(out + r * 12 * V, V);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) outb.st(acc[k], so, k * cs);
+      if (dots) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          const cf32 x = inb.ld(so, k * cs);
+          pr += (double)acc[k].re * x.re + (double)acc[k].im * x.im;
+          pi += (double)acc[k].re * x.im - (double)acc[k].im * x.re;
+          pp += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+        }
+      }
+    }
+    if (dots) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        pr += __shfl_xor(pr, off, 64);
+        pi += __shfl_xor(pi, off, 64);
+        pp += __shfl_xor(pp, off, 64);
+      }
+      if (lane == 0) {
+        const long bi = r * gridDim.x + blockIdx.x;
+        dots[2 * bi] = mkc(pr, pi);
+        dots[2 * bi + 1] = mkc(pp, 0.0);
+      }
     }
   }
 }
@@ -495,8 +651,8 @@ INST_PACK(float, double)
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs) {
-  hipLaunchKernelGGL(k_wilson<R>, dim3(nblocks(V, 64), nrhs), dim3(kBlock), 0, st, in, out, U, clov, nbr, V, terms,
-                     dots, run, rs);
+  hipLaunchKernelGGL(k_wilson<R>, dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
+                     nbr, V, terms, nrhs, dots, run, rs);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
@@ -505,5 +661,17 @@ template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*
                                    const int*, hipStream_t, cd64*, int);
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
+
+void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* clov, const int* nbr, long V, int nrhs,
+                        const int* run, int rs, cd64* dots, hipStream_t st) {
+  require(12L * V * 8 < (1L << 31), WCMG_ERR_DIMS, "multi-RHS Dslash: field exceeds the 2 GiB buffer range");
+  require(nrhs >= 1 && nrhs <= 64, WCMG_ERR_ARG, "multi-RHS Dslash takes 1..64 right-hand sides");
+  // waves per workgroup: at most 8, as few as keep every wave's share equal
+  const int per = (nrhs + 7) / 8;
+  const int nw = (nrhs + per - 1) / per;
+  hipLaunchKernelGGL(k_wilson_mrhs, dim3(nblocks(V, 64)), dim3(64 * nw), 0, st, in, out, U, clov, nbr, V, nrhs, dots,
+                     run, rs);
+  WCMG_CHECK_LAUNCH();
+}
 
 }  // namespace wcmg

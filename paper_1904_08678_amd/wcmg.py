@@ -6,12 +6,13 @@ kernels of libwcmg.so.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import torch
 
 F64, F32, BF16 = 0, 1, 2
-BATCH_GRAPH, BATCH_VECTOR, BATCH_MFMA = 1, 2, 4
+BATCH_GRAPH, BATCH_VECTOR, BATCH_MFMA, BATCH_DSLASH_PER_RHS = 1, 2, 4, 8
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libwcmg.so")
 _lib = None
@@ -71,6 +72,9 @@ def lib():
         l.wcmg_cycle.argtypes = [vp, vp, vp]
         l.wcmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(SolveInfo)]
         l.wcmg_solve_batched.argtypes = [vp, vp, vp, ip, ip, C.POINTER(SolveInfo)]
+        l.wcmg_tune_enable.argtypes = [vp, ip]
+        l.wcmg_tune_table.argtypes = [vp, C.c_char_p, ip, C.POINTER(C.c_int)]
+        l.wcmg_tune_load.argtypes = [vp, C.c_char_p]
         l.wcmg_timers.argtypes = [vp, C.POINTER(C.c_double), ip]
         l.wcmg_profile_enable.argtypes = [vp, C.c_char_p, ip]
         l.wcmg_profile_stats.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -251,12 +255,14 @@ class Context:
         return x, infos, st
 
     def solve_batched(self, b: torch.Tensor, x: torch.Tensor | None = None, graph=False, kernel="auto",
-                      check=True):
+                      dslash_per_rhs=False, check=True):
         """wcmg_solve_batched: groups of up to 16 right-hand sides solved together."""
         nrhs = b.numel() // (self.V * 12)
         if x is None:
             x = torch.zeros_like(b)
         flags = (BATCH_GRAPH if graph else 0) | {"auto": 0, "vector": BATCH_VECTOR, "mfma": BATCH_MFMA}[kernel]
+        if dslash_per_rhs:
+            flags |= BATCH_DSLASH_PER_RHS
         info = (SolveInfo * nrhs)()
         st = lib().wcmg_solve_batched(self.h, _ptr(b), _ptr(x), nrhs, flags, info)
         if check and st not in (0,):
@@ -264,6 +270,20 @@ class Context:
         infos = [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
                       t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters, cycles=i.cycles) for i in info]
         return x, infos, st
+
+    def tune_enable(self, enable=True):
+        self._chk(lib().wcmg_tune_enable(self.h, int(enable)))
+
+    def tune_table(self) -> dict:
+        """The autotuner's decisions so far: {configuration: {"choice": v, "ms": [...]}}."""
+        need = C.c_int(0)
+        lib().wcmg_tune_table(self.h, None, 0, C.byref(need))
+        buf = C.create_string_buffer(max(need.value, 1))
+        self._chk(lib().wcmg_tune_table(self.h, buf, len(buf), C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def tune_load(self, table: dict):
+        self._chk(lib().wcmg_tune_load(self.h, json.dumps(table).encode()))
 
     def timers(self):
         out = (C.c_double * 6)()

@@ -144,3 +144,31 @@ def test_batched_flag_errors():
     with pytest.raises(w.WcmgError) as e:
         ctx.solve_batched(b, graph=True)  # FP64 cycle cannot be captured
     assert e.value.code == 1
+
+
+def test_autotuner_table_and_forced_variants():
+    """The autotuner records one decision per launch configuration of the
+    batched solve; a loaded table forces each variant, and every variant
+    solves to 1e-10 with the same iteration counts to within one."""
+    w = wc()
+    L = (8, 8, 8, 8)
+    ctx, H, V = _mixed_pair(L, 771, w.F32)
+    b = syn.complex_gaussian((8, V, 4, 3), 772)
+    x, info, st = ctx.solve_batched(dev(b))
+    assert st == 0
+    table = ctx.tune_table()
+    dkeys = [k for k in table if k.startswith("dslash_f32")]
+    ckeys = [k for k in table if k.startswith("coarse_apply")]
+    assert dkeys and ckeys, table
+    for k in dkeys + ckeys:
+        assert table[k]["choice"] in (0, 1) and len(table[k]["ms"]) == 2
+    base = [i["outer_iters"] for i in info]
+    for v in (0, 1):
+        c2, _, _ = _mixed_pair(L, 771, w.F32)
+        c2.tune_load({k: {"choice": v} for k in dkeys + ckeys})
+        x2, i2, st2 = c2.solve_batched(dev(b))
+        assert st2 == 0
+        assert all(c2.tune_table()[k]["choice"] == v for k in dkeys + ckeys)
+        res = residuals(H, b, host(x2))
+        assert np.all(res <= 1.01e-10), res
+        assert all(abs(a - c) <= 1 for a, c in zip(base, [i["outer_iters"] for i in i2]))

@@ -113,6 +113,27 @@ def test_dslash_parity(L, block):
     assert rel(got32, ref) < 1e-5
 
 
+@pytest.mark.parametrize("nrhs", [2, 5, 16])
+def test_dslash_multi_rhs_fp32_ragged(nrhs):
+    """FP32 Dslash on several right-hand sides in one launch (links and clover
+    staged once per workgroup) on a lattice whose volume (210) leaves a ragged
+    last workgroup: against the oracle and against one launch per field."""
+    w = wc()
+    L = (3, 5, 2, 7)
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.3, 211)
+    ctx = w.Context(dims=L, m0=-0.08, c_sw=1.0, n_levels=1)
+    ctx.set_gauge(dev(U))
+    H = oracle.Hierarchy(L, U, m0=-0.08, csw=1.0, n_levels=1, blocks=())
+    psi = syn.complex_gaussian((nrhs, V, 4, 3), 212)
+    ref = np.stack([H.apply(0, psi[r]).reshape(V, 4, 3) for r in range(nrhs)])
+    x32 = psi.astype(np.complex64)
+    got = host(ctx.apply_D(0, dev(x32), w.F32))
+    assert rel(got, ref) < 1e-5
+    one = np.stack([host(ctx.apply_D(0, dev(x32[r:r + 1]), w.F32))[0] for r in range(nrhs)])
+    assert rel(got, one) < 1e-6
+
+
 def test_dslash_single_point_source_response():
     """A point source picks out one column of D: diagonal block plus 8 hops."""
     w = wc()
@@ -203,11 +224,13 @@ def test_breakdown_reported():
 
 
 # ---------------------------------------------------------------- restriction and prolongation
-def test_restrict_prolong_parity():
+@pytest.mark.parametrize("L,block,nrhs", [((8, 4, 4, 8), (4, 2, 2, 4), 2), ((6, 4, 4, 6), (3, 2, 2, 2), 5)])
+def test_restrict_prolong_parity(L, block, nrhs):
     """GPU and oracle build P from the same start vectors; each restricts and
-    prolongs with its own P."""
+    prolongs with its own P.  The second case leaves (aggregates x fields) and
+    (site blocks x fields) off a multiple of 8 (padded launch grids)."""
     w = wc()
-    L, block, nv = (8, 4, 4, 8), (4, 2, 2, 4), 6
+    nv = 6
     ctx, H, U = make_pair(L, 0.3, 501, blocks=(block,), nv=(nv,))
     V = int(np.prod(L))
     start = syn.complex_gaussian((nv, V, 12), 502)
@@ -216,12 +239,12 @@ def test_restrict_prolong_parity():
     H.set_start(0, start)
     H.setup()
     Pv = H.P(0)
-    v = syn.complex_gaussian((2, V, 12), 503)
+    v = syn.complex_gaussian((nrhs, V, 12), 503)
     ref = oracle.restrict(L, block, 12, Pv, v)
     assert rel(host(ctx.restrict(0, dev(v), w.F64)), ref) < 1e-12
     assert rel(host(ctx.restrict(0, dev(v.astype(np.complex64)), w.F32)), ref) < 1e-5
-    Vc = V // 64
-    phi = syn.complex_gaussian((2, Vc, 2 * nv), 504)
+    Vc = V // int(np.prod(block))
+    phi = syn.complex_gaussian((nrhs, Vc, 2 * nv), 504)
     ref = oracle.prolong(L, block, 12, Pv, phi)
     assert rel(host(ctx.prolong(0, dev(phi), w.F64)), ref) < 1e-12
     assert rel(host(ctx.prolong(0, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
