@@ -196,6 +196,53 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
 #define WCMG_BATCH_DSLASH_PER_RHS 8
 int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flags, wcmg_solve_info* info);
 
+/* ---------------------------------------------------------------------------
+ * Learned near-null proposal (a setup accelerator; not part of the paper's
+ * method).  A gauge-covariant network of three parallel-transport convolution
+ * layers, n_vec -> channels -> channels -> n_vec channels, maps the n_vec start
+ * vectors of a context (the Gaussian draws the plain setup relaxes) to n_vec
+ * proposed near-null vectors of level 0.  Layer l:
+ *   z_o(x) = sum_i sum_h W_l[h][o][i] (T_h a_i)(x),
+ *   T_0 a = a(x), T_{2mu+1} a = U_mu(x) a(x+mu), T_{2mu+2} a = U_mu(x-mu)^dag a(x-mu)
+ * (fermion boundary sign on t hops), then a = z / sqrt(1 + |z(x)|^2) per
+ * channel and site except after the last layer.  Weights are FP32 complex,
+ * activations BF16 (or FP32), accumulation FP32 on the matrix cores.
+ * Loss against the context's current near-null vectors v_j (the targets):
+ * per aggregate and chirality, c_j = argmin |v_j - Y c|, and
+ *   L = sum |v_j - Y c_j|^2 / sum |v_j|^2.
+ * Weights, host layout: layer 0, 1, 2, each [9][c_out][c_in] complex as
+ * (re, im) float pairs; wcmg_nn_num_weights gives the float count.
+ * Errors: WCMG_ERR_ARG for bad sizes (n_vec in {4, 8, 12, 16} and equal to the
+ * context's, channels a multiple of 4 up to 32), WCMG_ERR_STATE when the
+ * context lacks a gauge field, start vectors or (for the loss) near-null
+ * vectors. */
+typedef struct wcmg_nn wcmg_nn;
+/* act_prec: WCMG_BF16 or WCMG_F32 activations; seed: initial weights (self
+ * hop near the identity, other hops small Gaussian). */
+int wcmg_nn_create(int n_vec, int channels, int act_prec, uint64_t seed, void* stream, wcmg_nn** out);
+int wcmg_nn_destroy(wcmg_nn* nn);
+const char* wcmg_nn_last_error(const wcmg_nn* nn);
+int wcmg_nn_num_weights(const wcmg_nn* nn, int64_t* n_floats);
+int wcmg_nn_get_weights(wcmg_nn* nn, float* host, int64_t n_floats);
+int wcmg_nn_set_weights(wcmg_nn* nn, const float* host, int64_t n_floats);
+/* out_dev: complex128 [n_vec][V][4][3] (lexicographic), the network applied to
+ * the context's start vectors of level 0. */
+int wcmg_nn_forward(wcmg_nn* nn, wcmg_ctx* ctx, void* out_dev);
+/* Loss against the context's near-null vectors and its gradient with respect
+ * to the real parameters (dL/dRe W, dL/dIm W in the weight layout) on the host;
+ * grad_host may be NULL. */
+int wcmg_nn_loss_grad(wcmg_nn* nn, wcmg_ctx* ctx, double* loss, float* grad_host, int64_t n_floats);
+/* One Adam step (beta 0.9, 0.999) of learning rate lr on that loss; *loss is
+ * the loss before the step. */
+int wcmg_nn_train_step(wcmg_nn* nn, wcmg_ctx* ctx, float lr, double* loss);
+/* Setup with the network's proposals as the level-0 near-null vectors (P and
+ * D_c built from them, deeper levels relaxed as usual, then refine_iters
+ * refinement iterations).  Quality q = max_i |D y_i| / |y_i| of the proposals;
+ * if q is not finite, exceeds threshold, or Gram-Schmidt breaks down, the plain
+ * setup (wcmg_setup) runs instead and *fell_back = 1.  Needs start vectors of
+ * every level that the plain setup would. */
+int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int* fell_back, double* quality);
+
 /* Kernel autotuner of the batched path.  For each launch configuration met
  * (operator, lattice or coarse-lattice size, block size, precision, number of
  * right-hand sides) the library times every applicable kernel variant once on

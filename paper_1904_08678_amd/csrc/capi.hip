@@ -441,6 +441,129 @@ int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flag
   return status;
 }
 
+}  // extern "C"
+
+struct wcmg_nn {
+  std::unique_ptr<Net> n;
+};
+
+namespace {
+template <typename F>
+int nn_guarded(wcmg_nn* h, F&& f) {
+  if (!h || !h->n) return WCMG_ERR_ARG;
+  try {
+    f(*h->n);
+    h->n->err.clear();
+    return WCMG_OK;
+  } catch (const Error& e) {
+    h->n->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    h->n->err = e.what();
+    return WCMG_ERR_HIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int wcmg_nn_create(int n_vec, int channels, int act_prec, uint64_t seed, void* stream, wcmg_nn** out) {
+  if (!out) return WCMG_ERR_ARG;
+  *out = nullptr;
+  try {
+    require(act_prec == WCMG_BF16 || act_prec == WCMG_F32, WCMG_ERR_ARG, "network activations: WCMG_BF16 or WCMG_F32");
+    auto h = new wcmg_nn();
+    h->n.reset(new Net(n_vec, channels, act_prec == WCMG_BF16 ? 16 : 32, seed, (hipStream_t)stream));
+    *out = h;
+    return WCMG_OK;
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return WCMG_ERR_HIP;
+  }
+}
+
+int wcmg_nn_destroy(wcmg_nn* nn) {
+  if (!nn) return WCMG_ERR_ARG;
+  if (nn->n) (void)hipStreamSynchronize(nn->n->stream);
+  delete nn;
+  return WCMG_OK;
+}
+
+const char* wcmg_nn_last_error(const wcmg_nn* nn) {
+  if (!nn || !nn->n) return g_create_error.c_str();
+  return nn->n->err.c_str();
+}
+
+int wcmg_nn_num_weights(const wcmg_nn* nn, int64_t* n_floats) {
+  if (!nn || !nn->n || !n_floats) return WCMG_ERR_ARG;
+  *n_floats = nn->n->n_floats();
+  return WCMG_OK;
+}
+
+int wcmg_nn_get_weights(wcmg_nn* nn, float* host, int64_t n) {
+  return nn_guarded(nn, [&](Net& N) {
+    require(host && n == N.n_floats(), WCMG_ERR_ARG, "weight buffer size differs from wcmg_nn_num_weights");
+    N.get_weights(host);
+  });
+}
+
+int wcmg_nn_set_weights(wcmg_nn* nn, const float* host, int64_t n) {
+  return nn_guarded(nn, [&](Net& N) {
+    require(host && n == N.n_floats(), WCMG_ERR_ARG, "weight buffer size differs from wcmg_nn_num_weights");
+    N.set_weights(host);
+  });
+}
+
+int wcmg_nn_forward(wcmg_nn* nn, wcmg_ctx* ctx, void* out_dev) {
+  if (!ctx || !ctx->c) return WCMG_ERR_ARG;
+  return nn_guarded(nn, [&](Net& N) {
+    Context& c = *ctx->c;
+    require(out_dev != nullptr, WCMG_ERR_ARG, "null output");
+    N.forward(c);
+    const long n = (long)N.nv * c.n(0);
+    cd64* y = c.buf<cd64>("nn_out64", n);
+    launch_nn_to64(N.act[3].as<cf32>(), y, n, c.stream);
+    launch_unpack_fermion<double, double>(y, c.perm0.as<int>(), c.geo[0].V, N.nv, (cd64*)out_dev, c.stream);
+    c.sync();
+  });
+}
+
+int wcmg_nn_loss_grad(wcmg_nn* nn, wcmg_ctx* ctx, double* loss, float* grad_host, int64_t n) {
+  if (!ctx || !ctx->c) return WCMG_ERR_ARG;
+  return nn_guarded(nn, [&](Net& N) {
+    require(loss != nullptr, WCMG_ERR_ARG, "null loss");
+    require(!grad_host || n == N.n_floats(), WCMG_ERR_ARG, "gradient buffer size differs from wcmg_nn_num_weights");
+    *loss = N.loss_grad(*ctx->c);
+    if (grad_host) N.get_grads(grad_host);
+  });
+}
+
+int wcmg_nn_train_step(wcmg_nn* nn, wcmg_ctx* ctx, float lr, double* loss) {
+  if (!ctx || !ctx->c) return WCMG_ERR_ARG;
+  return nn_guarded(nn, [&](Net& N) {
+    require(lr > 0.f, WCMG_ERR_ARG, "learning rate must be positive");
+    const double l = N.loss_grad(*ctx->c);
+    require(l == l, WCMG_ERR_NAN, "network loss is NaN");
+    N.adam(lr, ctx->c->stream);
+    ctx->c->sync();
+    if (loss) *loss = l;
+  });
+}
+
+int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int* fell_back, double* quality) {
+  if (!nn || !nn->n) return WCMG_ERR_ARG;
+  return guarded(ctx, [&](Context& c) {
+    int fb = 0;
+    double q = 0.0;
+    c.setup_learned(*nn->n, threshold, &fb, &q);
+    if (fell_back) *fell_back = fb;
+    if (quality) *quality = q;
+  });
+}
+
 int wcmg_tune_enable(wcmg_ctx* ctx, int enable) {
   return guarded(ctx, [&](Context& c) { c.tuner.enabled = enable != 0; });
 }

@@ -121,6 +121,33 @@ struct CycleGraph {
   bool warm = false;
 };
 
+struct Context;
+
+// The learned near-null proposal network (three parallel-transport
+// convolution layers nv -> ch -> ch -> nv) with its training state and the
+// activations of its last forward pass over a context's lattice.
+struct Net {
+  int nv, ch, act_bits;  // act_bits: 16 = BF16 activations, 32 = FP32
+  int cin[3], cout[3];
+  DevBuf W[3], Wadj[3], gW[3], m[3], v[3];  // weights [9][cout][cin], their adjoint, gradients, Adam moments
+  int step = 0;
+  double last_loss = 0.0;
+  hipStream_t stream;
+  long V = 0;
+  DevBuf act[4], scale[2], g0, g1, tgt, part;
+  std::string err;
+  Net(int nv_, int ch_, int act_bits_, uint64_t seed, hipStream_t st);
+  long n_complex(int l) const;
+  long n_floats() const;
+  void set_weights(const float* host);
+  void get_weights(float* host);
+  void get_grads(float* host);
+  void ensure(long V_);
+  void forward(Context& c);
+  double loss_grad(Context& c);
+  void adam(float lr, hipStream_t st);
+};
+
 struct GmresState {
   int m = 0;
   long n = 0;
@@ -188,6 +215,7 @@ struct Context {
   void regalerkin_below(int l);
   void refine_iteration(int l);
   void setup_all();
+  void setup_learned(Net& net, double threshold, int* fell_back, double* quality);
 
   template <typename R>
   void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run);

@@ -138,6 +138,20 @@ void launch_bgmres_givens(int* st_, cd64* S, long ss, int B, int m, int j, doubl
 void launch_bgmres_solve_y(const int* st_, cd64* S, long ss, int B, int m, hipStream_t st);
 void launch_bgmres_cycle_end(int* st_, int B, hipStream_t st);
 
+// ---- learned near-null proposal (nn.hip); activations: 16 = BF16, 32 = FP32
+void launch_nn_layer(int act_bits_in, const void* in, int Cin, const cf32* W, int Cout, int act_bits_out, void* out,
+                     float* scale, int squash, const cf32* U, const int* nbr, long V, hipStream_t st);
+int nn_wgrad_blocks(long V);
+void launch_nn_wgrad(const cf32* g, int Cout, int act_bits, const void* a, int Cin, const cf32* U, const int* nbr,
+                     long V, cd64* part, cf32* gW, hipStream_t st);
+void launch_nn_squash_bwd(cf32* g, int act_bits, const void* a, const float* scale, int C, long V, hipStream_t st);
+void launch_nn_loss(const cf32* Y, const cf32* T, int nv, const int* agg_sites, int A, long Vc, long V, double norm,
+                    cf32* gY, double* loss_part, hipStream_t st);
+void launch_nn_adam(float* w, const cf32* gW, float* m, float* v, long n_complex, float lr, int step, hipStream_t st);
+void launch_nn_adjoint_weights(const cf32* W, int Cout, int Cin, cf32* Wadj, hipStream_t st);
+void launch_nn_from64(const cd64* x, int act_bits, void* y, long n, hipStream_t st);
+void launch_nn_to64(const cf32* x, cd64* y, long n, hipStream_t st);
+
 constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
 
 }  // namespace wcmg

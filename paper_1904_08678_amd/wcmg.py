@@ -9,6 +9,7 @@ import ctypes as C
 import json
 import os
 
+import numpy as np
 import torch
 
 F64, F32, BF16 = 0, 1, 2
@@ -86,6 +87,17 @@ def lib():
         l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
         l.wcmg_coarse_last_error.argtypes = [vp]
         l.wcmg_coarse_last_error.restype = C.c_char_p
+        l.wcmg_nn_create.argtypes = [ip, ip, ip, C.c_uint64, vp, C.POINTER(vp)]
+        l.wcmg_nn_destroy.argtypes = [vp]
+        l.wcmg_nn_last_error.argtypes = [vp]
+        l.wcmg_nn_last_error.restype = C.c_char_p
+        l.wcmg_nn_num_weights.argtypes = [vp, C.POINTER(C.c_int64)]
+        l.wcmg_nn_get_weights.argtypes = [vp, vp, C.c_int64]
+        l.wcmg_nn_set_weights.argtypes = [vp, vp, C.c_int64]
+        l.wcmg_nn_forward.argtypes = [vp, vp, vp]
+        l.wcmg_nn_loss_grad.argtypes = [vp, vp, C.POINTER(C.c_double), vp, C.c_int64]
+        l.wcmg_nn_train_step.argtypes = [vp, vp, C.c_float, C.POINTER(C.c_double)]
+        l.wcmg_setup_learned.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         _lib = l
     return _lib
 
@@ -271,6 +283,13 @@ class Context:
                       t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters, cycles=i.cycles) for i in info]
         return x, infos, st
 
+    def setup_learned(self, net: "Network", threshold=float("inf")):
+        """wcmg_setup_learned: returns (fell_back, quality)."""
+        fb = C.c_int(0)
+        q = C.c_double(0.0)
+        self._chk(lib().wcmg_setup_learned(self.h, net.h, float(threshold), C.byref(fb), C.byref(q)))
+        return bool(fb.value), q.value
+
     def tune_enable(self, enable=True):
         self._chk(lib().wcmg_tune_enable(self.h, int(enable)))
 
@@ -298,6 +317,58 @@ class Context:
         ms = C.c_double(0.0)
         self._chk(lib().wcmg_profile_stats(self.h, family.encode(), C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+class Network:
+    """Learned near-null proposal (wcmg_nn): three parallel-transport
+    convolution layers n_vec -> channels -> channels -> n_vec."""
+
+    def __init__(self, n_vec, channels=32, act_prec=BF16, seed=0):
+        h = C.c_void_p()
+        st = lib().wcmg_nn_create(int(n_vec), int(channels), int(act_prec), int(seed), _stream(), C.byref(h))
+        if st:
+            raise WcmgError(st, lib().wcmg_nn_last_error(None).decode())
+        self.h = h
+        self.n_vec, self.channels = n_vec, channels
+        n = C.c_int64(0)
+        lib().wcmg_nn_num_weights(self.h, C.byref(n))
+        self.n_floats = n.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().wcmg_nn_destroy(self.h)
+            self.h = None
+
+    def _chk(self, st):
+        if st:
+            raise WcmgError(st, lib().wcmg_nn_last_error(self.h).decode())
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(self.n_floats, np.float32)
+        self._chk(lib().wcmg_nn_get_weights(self.h, w.ctypes.data, self.n_floats))
+        return w
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.n_floats
+        self._chk(lib().wcmg_nn_set_weights(self.h, w.ctypes.data, self.n_floats))
+
+    def forward(self, ctx) -> torch.Tensor:
+        out = torch.empty((self.n_vec, ctx.V, 4, 3), dtype=torch.complex128, device="cuda")
+        self._chk(lib().wcmg_nn_forward(self.h, ctx.h, _ptr(out)))
+        return out
+
+    def loss_grad(self, ctx, grad=True):
+        loss = C.c_double(0.0)
+        g = np.zeros(self.n_floats, np.float32) if grad else None
+        self._chk(lib().wcmg_nn_loss_grad(self.h, ctx.h, C.byref(loss), g.ctypes.data if grad else None,
+                                          self.n_floats))
+        return loss.value, g
+
+    def train_step(self, ctx, lr=1e-2) -> float:
+        loss = C.c_double(0.0)
+        self._chk(lib().wcmg_nn_train_step(self.h, ctx.h, float(lr), C.byref(loss)))
+        return loss.value
 
 
 class CoarseOperator:
