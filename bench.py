@@ -244,6 +244,38 @@ def batched_point_sources(w, torch, wl, fp64=True):
     return out
 
 
+def ragged_batch(w, torch, nrhs=12, reps=50):
+    """One matrix-core launch over the coarse operators of three lattices (8^4,
+    16^4 and 24^3 x 48 under 4^4 aggregates: 16 + 256 + 2592 coarse sites,
+    Nb = 24, nrhs fields each) against the three operators launched one after
+    another (sum of their back-to-back launch times)."""
+    lats = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 6, 6, 12)]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    out = {"coarse_lattices": [list(l) for l in lats], "nb": 24, "nrhs": nrhs}
+    for store, name in ((w.F32, "f32"), (w.BF16, "bf16")):
+        ops, ins = [], []
+        for Lc in lats:
+            Vc = int(np.prod(Lc))
+            op = w.CoarseOperator(Lc, 24, store)
+            op.set(torch.randn((Vc, 9, 24, 24), dtype=torch.complex64, device="cuda", generator=g))
+            op.set_kernel(2)
+            ops.append(op)
+            ins.append(torch.randn((nrhs, Vc, 24), dtype=torch.complex64, device="cuda", generator=g))
+        w.coarse_time_ragged(ops, ins, reps=3)
+        t_rag = w.coarse_time_ragged(ops, ins, reps=reps)
+        t_sep = 0.0
+        for op, x in zip(ops, ins):
+            y = torch.empty_like(x)
+            op.time(x, y, reps=3)
+            t_sep += op.time(x, y, reps=reps)
+        sb = 8 if name == "f32" else 4
+        byts = sum((9.0 * 24 * 24 * sb + 2.0 * 24 * nrhs * 8) * int(np.prod(l)) for l in lats)
+        out[name] = {"ragged_ms": t_rag, "separate_ms": t_sep, "speedup": t_sep / t_rag,
+                     "ragged_GB_s": byts / t_rag / 1e6}
+    return out
+
+
 def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
     """Oracle (plain FP64 C++) on the host cores: seconds per outer FGMRES
     iteration at the same lattice and parameters, scaled to the GPU's outer
@@ -455,6 +487,8 @@ def main():
     if not args.no_batched:
         print("[bench] batched point sources, 24^3x48", file=sys.stderr, flush=True)
         extra["batched_24x48"] = batched_point_sources(w, torch, WORKLOAD_BATCH, fp64=not args.no_fp64)
+        print("[bench] ragged batch of coarse operators", file=sys.stderr, flush=True)
+        extra["ragged_coarse_apply"] = ragged_batch(w, torch)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)

@@ -235,13 +235,16 @@ int wcmg_nn_loss_grad(wcmg_nn* nn, wcmg_ctx* ctx, double* loss, float* grad_host
 /* One Adam step (beta 0.9, 0.999) of learning rate lr on that loss; *loss is
  * the loss before the step. */
 int wcmg_nn_train_step(wcmg_nn* nn, wcmg_ctx* ctx, float lr, double* loss);
-/* Setup with the network's proposals as the level-0 near-null vectors (P and
- * D_c built from them, deeper levels relaxed as usual, then refine_iters
- * refinement iterations).  Quality q = max_i |D y_i| / |y_i| of the proposals;
- * if q is not finite, exceeds threshold, or Gram-Schmidt breaks down, the plain
- * setup (wcmg_setup) runs instead and *fell_back = 1.  Needs start vectors of
- * every level that the plain setup would. */
-int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int* fell_back, double* quality);
+/* Setup with the network's proposals as the level-0 near-null vectors: each
+ * proposal is smoothed by relax_sweeps MR steps on D x = 0 (0: used as
+ * proposed), P and D_c are built from them, deeper levels are relaxed as usual,
+ * then refine_iters refinement iterations run.  Quality q = max_i |D y_i| /
+ * |y_i| of the raw proposals; if q is not finite, exceeds threshold, or
+ * Gram-Schmidt breaks down, the plain setup (wcmg_setup) runs instead and
+ * *fell_back = 1.  Needs start vectors of every level that the plain setup
+ * would. */
+int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int relax_sweeps, int* fell_back,
+                       double* quality);
 
 /* Kernel autotuner of the batched path.  For each launch configuration met
  * (operator, lattice or coarse-lattice size, block size, precision, number of
@@ -298,6 +301,20 @@ int wcmg_coarse_set_kernel(wcmg_coarse* op, int kernel);
  * *avg_ms receives the mean launch duration. */
 int wcmg_coarse_time(wcmg_coarse* op, const void* in, void* out, int nrhs, int reps, double* avg_ms);
 const char* wcmg_coarse_last_error(const wcmg_coarse* op);
+
+/* Ragged batch (multi-lattice form of the batched coarse apply): nprob
+ * standalone coarse operators of equal Nb and storage precision (FP32 or BF16;
+ * Nb in {8,16,24,32,40}), each with its own lattice, blocks and neighbours,
+ * operator p applied to its nrhs[p] fields in[p] -> out[p] (complex64
+ * [nrhs[p]][Vc_p][Nb], device), in ONE matrix-core launch over the sum of
+ * their coarse sites, on ops[0]'s stream.  nprob in 1..8, nrhs[p] in 1..16.
+ * Errors (WCMG_ERR_ARG for mismatched operators or sizes) are reported through
+ * wcmg_coarse_last_error(ops[0]).  wcmg_coarse_time_ragged: reps launches,
+ * mean milliseconds per launch by HIP events. */
+int wcmg_coarse_apply_ragged(wcmg_coarse* const* ops, int nprob, const void* const* in, void* const* out,
+                             const int* nrhs);
+int wcmg_coarse_time_ragged(wcmg_coarse* const* ops, int nprob, const void* const* in, void* const* out,
+                            const int* nrhs, int reps, double* avg_ms);
 
 #ifdef __cplusplus
 }

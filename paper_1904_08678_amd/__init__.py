@@ -6,5 +6,6 @@ current HIP stream into those calls.  There is no CPU fallback: without the
 built library every call raises.
 """
 from .wcmg import (  # noqa: F401
-    F64, F32, BF16, Context, CoarseOperator, Network, WcmgError, default_params, lib, library_path,
+    F64, F32, BF16, Context, CoarseOperator, Network, WcmgError, coarse_apply_ragged, coarse_time_ragged,
+    default_params, lib, library_path,
 )

@@ -553,12 +553,14 @@ int wcmg_nn_train_step(wcmg_nn* nn, wcmg_ctx* ctx, float lr, double* loss) {
   });
 }
 
-int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int* fell_back, double* quality) {
+int wcmg_setup_learned(wcmg_ctx* ctx, wcmg_nn* nn, double threshold, int relax_sweeps, int* fell_back,
+                       double* quality) {
   if (!nn || !nn->n) return WCMG_ERR_ARG;
   return guarded(ctx, [&](Context& c) {
+    require(relax_sweeps >= 0, WCMG_ERR_ARG, "negative relaxation sweep count");
     int fb = 0;
     double q = 0.0;
-    c.setup_learned(*nn->n, threshold, &fb, &q);
+    c.setup_learned(*nn->n, threshold, relax_sweeps, &fb, &q);
     if (fell_back) *fell_back = fb;
     if (quality) *quality = q;
   });
@@ -626,6 +628,9 @@ static int guarded_c(wcmg_coarse* h, F&& f) {
   } catch (const Error& e) {
     h->err = e.what();
     return e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return WCMG_ERR_HIP;
   }
 }
 
@@ -691,6 +696,58 @@ int wcmg_coarse_set_kernel(wcmg_coarse* h, int kernel) {
     require(kernel != 2 || (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb)), WCMG_ERR_ARG,
             "matrix-core kernel needs FP32/BF16 storage and Nb in {8,16,24,32,40}");
     o.kernel = kernel;
+  });
+}
+
+}  // extern "C"
+
+static RaggedTable ragged_table(wcmg_coarse* const* ops, int nprob, const void* const* in, void* const* out,
+                                const int* nrhs) {
+  require(ops && in && out && nrhs && nprob >= 1 && nprob <= kRaggedMax, WCMG_ERR_ARG,
+          "ragged batch: 1..8 operators with fields");
+  RaggedTable t{};
+  t.n = nprob;
+  t.nb = ops[0]->op.nb;
+  for (int p = 0; p < nprob; ++p) {
+    wcmg_coarse& o = *ops[p];
+    require(o.op.nb == t.nb && o.store == ops[0]->store, WCMG_ERR_ARG,
+            "ragged batch: operators must share Nb and storage precision");
+    require(in[p] && out[p], WCMG_ERR_ARG, "ragged batch: null field");
+    require(o.op.mfma_fresh[o.store], WCMG_ERR_STATE, "ragged batch: operator blocks not set");
+    t.p[p] = RaggedProblem{o.op.mfma[o.store].p, (const cf32*)in[p], (cf32*)out[p], o.op.nbr.as<int>(), o.op.V,
+                           nrhs[p]};
+  }
+  return t;
+}
+
+extern "C" {
+
+int wcmg_coarse_apply_ragged(wcmg_coarse* const* ops, int nprob, const void* const* in, void* const* out,
+                             const int* nrhs) {
+  if (!ops || nprob < 1) return WCMG_ERR_ARG;
+  return guarded_c(ops[0], [&](wcmg_coarse& o) {
+    launch_coarse_apply_mfma_ragged(o.store, ragged_table(ops, nprob, in, out, nrhs), o.stream);
+  });
+}
+
+int wcmg_coarse_time_ragged(wcmg_coarse* const* ops, int nprob, const void* const* in, void* const* out,
+                            const int* nrhs, int reps, double* avg_ms) {
+  if (!ops || nprob < 1) return WCMG_ERR_ARG;
+  return guarded_c(ops[0], [&](wcmg_coarse& o) {
+    require(reps >= 1 && avg_ms, WCMG_ERR_ARG, "bad arguments");
+    const RaggedTable t = ragged_table(ops, nprob, in, out, nrhs);
+    hipEvent_t a, b;
+    WCMG_HIP(hipEventCreate(&a));
+    WCMG_HIP(hipEventCreate(&b));
+    WCMG_HIP(hipEventRecord(a, o.stream));
+    for (int i = 0; i < reps; ++i) launch_coarse_apply_mfma_ragged(o.store, t, o.stream);
+    WCMG_HIP(hipEventRecord(b, o.stream));
+    WCMG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    WCMG_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
   });
 }
 

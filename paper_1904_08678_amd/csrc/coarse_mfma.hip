@@ -80,11 +80,13 @@ __device__ __forceinline__ void mfma_load_chunks(BlockRegs<P, NCK>& r, const typ
   }
 }
 
+// One coarse site of one operator, all of its (up to 16) right-hand sides, by
+// one wave.  Shared by the single-operator and the ragged launches.
 template <int P, int NB>
-__global__ void __launch_bounds__(256) k_coarse_apply_mfma(const typename MfmaChunk<P>::T* __restrict__ blk,
-                                                            const cf32* __restrict__ in, cf32* __restrict__ out,
-                                                            const int* __restrict__ nbr, long Vc, int nrhs,
-                                                            const int* __restrict__ run, int run_stride) {
+__device__ __forceinline__ void mfma_site(const typename MfmaChunk<P>::T* __restrict__ blk,
+                                          const cf32* __restrict__ in, cf32* __restrict__ out,
+                                          const int* __restrict__ nbr, long Vc, int nrhs,
+                                          const int* __restrict__ run, int run_stride, long site) {
   constexpr int Q = NB / 16;                 // full 16-row blocks
   constexpr bool REM = (NB % 16) != 0;       // one 8-row remainder
   constexpr int NCK = NB / 8;                // chunks per lane
@@ -92,10 +94,6 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(const typename MfmaCh
   constexpr long CPD = mfma_chunks_per_dir(NB);
   typedef typename MfmaChunk<P>::T CT;
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const long blk_id = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
-  const long site = blk_id * (blockDim.x >> 6) + wv;
-  if (site >= Vc) return;  // wave-uniform
   const int col = lane & 15;   // RHS column
   const int kq = lane >> 4;    // k offset within a step
   const bool rhs_ok = col < nrhs && (!run || run[(long)col * run_stride]);
@@ -179,6 +177,35 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(const typename MfmaCh
   }
 }
 
+template <int P, int NB>
+__global__ void __launch_bounds__(256) k_coarse_apply_mfma(const typename MfmaChunk<P>::T* __restrict__ blk,
+                                                            const cf32* __restrict__ in, cf32* __restrict__ out,
+                                                            const int* __restrict__ nbr, long Vc, int nrhs,
+                                                            const int* __restrict__ run, int run_stride) {
+  const int wv = threadIdx.x >> 6;
+  const long blk_id = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
+  const long site = blk_id * (blockDim.x >> 6) + wv;
+  if (site >= Vc) return;  // wave-uniform
+  mfma_site<P, NB>(blk, in, out, nbr, Vc, nrhs, run, run_stride, site);
+}
+
+// Ragged batch: several coarse operators (same Nb and storage), each with its
+// own lattice, blocks, neighbour table and fields, in one launch over the sum
+// of their sites; wave w of the grid takes global site w, and the table's
+// prefix offsets name its operator.  The table travels as a kernel argument.
+template <int P, int NB>
+__global__ void __launch_bounds__(256) k_coarse_apply_mfma_ragged(RaggedTable t) {
+  const int wv = threadIdx.x >> 6;
+  const long blk_id = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
+  const long g = blk_id * (blockDim.x >> 6) + wv;
+  if (g >= t.site0[t.n]) return;  // wave-uniform
+  int p = 0;
+  while (p + 1 < t.n && g >= t.site0[p + 1]) ++p;
+  const RaggedProblem& q = t.p[p];
+  mfma_site<P, NB>((const typename MfmaChunk<P>::T*)q.blk, q.in, q.out, q.nbr, q.Vc, q.nrhs, nullptr, 0,
+                   g - t.site0[p]);
+}
+
 // canonical FP64 [Vc][9][Nb][Nb] -> fragment order of precision P
 template <int P>
 __global__ void k_blocks_to_mfma(const cd64* __restrict__ src, long Vc, int nb, typename MfmaChunk<P>::T* dst) {
@@ -257,6 +284,32 @@ static void mfma_nb(int nb, const void* blk, const cf32* in, cf32* out, const in
 }
 
 // out = D_c in for nrhs <= 16 right-hand sides (RHS-major fields, FP32).
+template <int P>
+static void mfma_ragged_nb(const RaggedTable& t, long total, hipStream_t st) {
+  const dim3 g((unsigned)((total + 3) / 4)), b(kBlock);
+  switch (t.nb) {
+    case 8: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 8>), g, b, 0, st, t); break;
+    case 16: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 16>), g, b, 0, st, t); break;
+    case 24: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 24>), g, b, 0, st, t); break;
+    case 32: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 32>), g, b, 0, st, t); break;
+    default: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 40>), g, b, 0, st, t); break;
+  }
+}
+
+void launch_coarse_apply_mfma_ragged(int prec, RaggedTable t, hipStream_t st) {
+  require(t.n >= 1 && t.n <= kRaggedMax, WCMG_ERR_ARG, "ragged batch takes 1..8 operators");
+  require(mfma_supported_nb(t.nb) && (prec == WCMG_F32 || prec == WCMG_BF16), WCMG_ERR_ARG,
+          "ragged batch: matrix-core layout (Nb in {8,16,24,32,40}, FP32 or BF16 storage)");
+  t.site0[0] = 0;
+  for (int p = 0; p < t.n; ++p) {
+    require(t.p[p].nrhs >= 1 && t.p[p].nrhs <= 16, WCMG_ERR_ARG, "ragged batch: 1..16 right-hand sides per operator");
+    t.site0[p + 1] = t.site0[p] + t.p[p].Vc;
+  }
+  if (prec == WCMG_F32) mfma_ragged_nb<WCMG_F32>(t, t.site0[t.n], st);
+  else mfma_ragged_nb<WCMG_BF16>(t, t.site0[t.n], st);
+  WCMG_CHECK_LAUNCH();
+}
+
 void launch_coarse_apply_mfma(int prec, int nb, const void* blk, const cf32* in, cf32* out, const int* nbr, long Vc,
                               int nrhs, const int* run, int run_stride, hipStream_t st) {
   require(nrhs >= 1 && nrhs <= 16, WCMG_ERR_ARG, "matrix-core coarse apply takes 1..16 right-hand sides");

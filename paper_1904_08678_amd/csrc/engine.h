@@ -210,12 +210,13 @@ struct Context {
   void set_clover(const cd64* blocks);
   void pack_clover();
   void initial_setup(int l);
+  void relax_vectors(int l, int sweeps);
   void rebuild(int l);
   void galerkin(int l);
   void regalerkin_below(int l);
   void refine_iteration(int l);
   void setup_all();
-  void setup_learned(Net& net, double threshold, int* fell_back, double* quality);
+  void setup_learned(Net& net, double threshold, int relax_sweeps, int* fell_back, double* quality);
 
   template <typename R>
   void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run);

@@ -241,6 +241,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
     WCMG_HIP(hipMemcpy(geo[l].nbr.p, cop[l - 1]->nbr.p, 8 * geo[l].V * sizeof(int), hipMemcpyDeviceToDevice));
   }
   partial.alloc(kPartialSlots * sizeof(cd64));
+  bpart.alloc((size_t)16 * kPartialSlots * sizeof(cd64));
   scratch64.alloc(64 * sizeof(cd64));
   WCMG_HIP(hipHostMalloc((void**)&pinned, 256 * sizeof(int), hipHostMallocDefault));
   const long V0 = geo[0].V;
@@ -678,26 +679,36 @@ void Context::regalerkin_below(int l) {
 void Context::initial_setup(int l) {
   Transfer& T = tr[l];
   require(T.has_start, WCMG_ERR_STATE, "start vectors of level " + std::to_string(l) + " not set");
+  WCMG_HIP(hipMemcpyAsync(T.vecs64.p, T.start64.p, T.nv * n(l) * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  relax_vectors(l, p.relax_sweeps);
+  rebuild(l);
+}
+
+// `sweeps` MR steps on D x = 0 from each of the level's current vectors (all
+// vectors advance together through the batched smoother), then normalise.
+void Context::relax_vectors(int l, int sweeps) {
+  Transfer& T = tr[l];
   const long nn = n(l);
   auto t0 = std::chrono::steady_clock::now();
-  WCMG_HIP(hipMemcpyAsync(T.vecs64.p, T.start64.p, T.nv * nn * sizeof(cd64), hipMemcpyDeviceToDevice, stream));
+  cd64* v = T.vecs64.as<cd64>();
+  if (sweeps > 0) {
+    if (p.setup_prec == WCMG_F64) {
+      mrB<double>(l, nullptr, v, T.nv, sweeps, nullptr, 0);
+    } else {
+      cf32* x32 = buf<cf32>("relax32_" + std::to_string(l), T.nv * nn);
+      launch_convert<double, float>(v, x32, T.nv * nn, nullptr, stream);
+      mrB<float>(l, nullptr, x32, T.nv, sweeps, nullptr, 0);
+      launch_convert<float, double>(x32, v, T.nv * nn, nullptr, stream);
+    }
+  }
   cd64* nrm = scratch64.as<cd64>() + 16;
   for (int i = 0; i < T.nv; ++i) {
-    cd64* x = T.vecs64.as<cd64>() + (long)i * nn;
-    if (p.setup_prec == WCMG_F64) {
-      mr<double>(l, nullptr, x, false, p.relax_sweeps, nullptr);
-    } else {
-      cf32* x32 = buf<cf32>("relax32" + std::to_string(l), nn);
-      launch_convert<double, float>(x, x32, nn, nullptr, stream);
-      mr<float>(l, nullptr, x32, false, p.relax_sweeps, nullptr);
-      launch_convert<float, double>(x32, x, nn, nullptr, stream);
-    }
+    cd64* x = v + (long)i * nn;
     launch_dot<double>(x, 0, 1, nullptr, x, nn, partial.as<cd64>(), 1, nrm, 1, 0, nullptr, stream);
     launch_scale_inv_norm<double>(x, x, nrm, nn, nullptr, stream);
   }
   sync();
   timers[1] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  rebuild(l);
 }
 
 // Iterative setup (Sec. 2.1, DDalphaAMG-style).  One iteration at level l:

@@ -179,7 +179,8 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
   if (!capturing) prof.end(fam, stream);
 }
 
-// MinimalResidual on each right-hand side (Sec. 2.1), as Context::mr.
+// MinimalResidual on each right-hand side (Sec. 2.1), as Context::mr; b ==
+// nullptr means b = 0 (relaxation on D x = 0).
 template <typename R>
 void Context::mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const int* run, int rs) {
   const long nn = n(l);
@@ -188,7 +189,8 @@ void Context::mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const i
   cplx<R>* pp = buf<cplx<R>>("bmr_p" + t, B * nn);
   cd64* dots = buf<cd64>("bmr_dots" + t, 2L * B);
   apply_opB<R>(l, x, pp, B, run, rs);
-  launch_belem<cplx<R>, cplx<R>>(r, nn, b, nn, pp, nn, nullptr, 0, nn, B, 2, run, rs, stream);
+  if (b) launch_belem<cplx<R>, cplx<R>>(r, nn, b, nn, pp, nn, nullptr, 0, nn, B, 2, run, rs, stream);
+  else launch_belem<cplx<R>, cplx<R>>(r, nn, pp, nn, nullptr, 0, nullptr, 0, nn, B, 4, run, rs, stream);  // b = 0
   if (l == 0) {
     // <p, r> and <p, p> per right-hand side from the Dslash epilogue
     const int G = wilson_blocks(geo[0].V);

@@ -152,6 +152,23 @@ void launch_nn_adjoint_weights(const cf32* W, int Cout, int Cin, cf32* Wadj, hip
 void launch_nn_from64(const cd64* x, int act_bits, void* y, long n, hipStream_t st);
 void launch_nn_to64(const cf32* x, cd64* y, long n, hipStream_t st);
 
+// ragged batch of matrix-core coarse applies (coarse_mfma.hip)
+constexpr int kRaggedMax = 8;
+struct RaggedProblem {
+  const void* blk;  // fragment-ordered blocks
+  const cf32* in;   // [nrhs][Vc][Nb]
+  cf32* out;
+  const int* nbr;   // [8][Vc]
+  long Vc;
+  int nrhs;
+};
+struct RaggedTable {
+  RaggedProblem p[kRaggedMax];
+  long site0[kRaggedMax + 1];  // prefix sums of Vc (filled by the launcher)
+  int n, nb;
+};
+void launch_coarse_apply_mfma_ragged(int prec, RaggedTable t, hipStream_t st);
+
 constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
 
 }  // namespace wcmg

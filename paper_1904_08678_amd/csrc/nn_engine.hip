@@ -175,12 +175,13 @@ void Net::adam(float lr, hipStream_t st) {
 }
 
 // Learned setup: the network maps the start vectors of level 0 to proposed
-// near-null vectors; P and the coarse operator are built from them, deeper
+// near-null vectors, which relax_sweeps MR steps on D x = 0 then smooth (0:
+// used as proposed); P and the coarse operator are built from them, deeper
 // levels are set up as usual, then refine_iters refinement iterations run.
 // Quality check: q = max_i |D y_i| / |y_i| over the proposals; when q is not
 // finite or exceeds the threshold (or Gram-Schmidt breaks down) the plain
 // setup runs instead.
-void Context::setup_learned(Net& net, double threshold, int* fell_back, double* quality) {
+void Context::setup_learned(Net& net, double threshold, int relax_sweeps, int* fell_back, double* quality) {
   require(gauge_set, WCMG_ERR_STATE, "gauge field not set");
   require(nlev >= 2, WCMG_ERR_STATE, "learned setup needs at least two levels");
   auto t0 = std::chrono::steady_clock::now();
@@ -209,6 +210,7 @@ void Context::setup_learned(Net& net, double threshold, int* fell_back, double* 
   bool ok = q <= threshold;
   if (ok) {
     try {
+      relax_vectors(0, relax_sweeps);
       rebuild(0);
     } catch (const Error& e) {
       if (e.code != WCMG_ERR_BREAKDOWN) throw;

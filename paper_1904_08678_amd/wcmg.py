@@ -87,6 +87,9 @@ def lib():
         l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
         l.wcmg_coarse_last_error.argtypes = [vp]
         l.wcmg_coarse_last_error.restype = C.c_char_p
+        l.wcmg_coarse_apply_ragged.argtypes = [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int)]
+        l.wcmg_coarse_time_ragged.argtypes = [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int), ip,
+                                              C.POINTER(C.c_double)]
         l.wcmg_nn_create.argtypes = [ip, ip, ip, C.c_uint64, vp, C.POINTER(vp)]
         l.wcmg_nn_destroy.argtypes = [vp]
         l.wcmg_nn_last_error.argtypes = [vp]
@@ -97,7 +100,7 @@ def lib():
         l.wcmg_nn_forward.argtypes = [vp, vp, vp]
         l.wcmg_nn_loss_grad.argtypes = [vp, vp, C.POINTER(C.c_double), vp, C.c_int64]
         l.wcmg_nn_train_step.argtypes = [vp, vp, C.c_float, C.POINTER(C.c_double)]
-        l.wcmg_setup_learned.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        l.wcmg_setup_learned.argtypes = [vp, vp, C.c_double, ip, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         _lib = l
     return _lib
 
@@ -283,11 +286,12 @@ class Context:
                       t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters, cycles=i.cycles) for i in info]
         return x, infos, st
 
-    def setup_learned(self, net: "Network", threshold=float("inf")):
+    def setup_learned(self, net: "Network", threshold=float("inf"), relax_sweeps=0):
         """wcmg_setup_learned: returns (fell_back, quality)."""
         fb = C.c_int(0)
         q = C.c_double(0.0)
-        self._chk(lib().wcmg_setup_learned(self.h, net.h, float(threshold), C.byref(fb), C.byref(q)))
+        self._chk(lib().wcmg_setup_learned(self.h, net.h, float(threshold), int(relax_sweeps), C.byref(fb),
+                                           C.byref(q)))
         return bool(fb.value), q.value
 
     def tune_enable(self, enable=True):
@@ -414,3 +418,32 @@ class CoarseOperator:
         ms = C.c_double(0.0)
         self._chk(lib().wcmg_coarse_time(self.h, _ptr(x), _ptr(out), nrhs, int(reps), C.byref(ms)))
         return ms.value
+
+
+def _ragged_args(ops, ins):
+    n = len(ops)
+    outs = [torch.empty_like(x) for x in ins]
+    h = (C.c_void_p * n)(*[o.h for o in ops])
+    pi = (C.c_void_p * n)(*[x.data_ptr() for x in ins])
+    po = (C.c_void_p * n)(*[y.data_ptr() for y in outs])
+    nr = (C.c_int * n)(*[x.numel() // (o.Vc * o.nb) for o, x in zip(ops, ins)])
+    return n, outs, h, pi, po, nr
+
+
+def coarse_apply_ragged(ops, ins):
+    """wcmg_coarse_apply_ragged: operator p applied to ins[p] ([nrhs][Vc_p][Nb]
+    complex64), all operators in one launch.  Returns the outputs."""
+    n, outs, h, pi, po, nr = _ragged_args(ops, ins)
+    st = lib().wcmg_coarse_apply_ragged(h, n, pi, po, nr)
+    if st:
+        raise WcmgError(st, lib().wcmg_coarse_last_error(ops[0].h).decode())
+    return outs
+
+
+def coarse_time_ragged(ops, ins, reps=20):
+    n, outs, h, pi, po, nr = _ragged_args(ops, ins)
+    ms = C.c_double(0.0)
+    st = lib().wcmg_coarse_time_ragged(h, n, pi, po, nr, int(reps), C.byref(ms))
+    if st:
+        raise WcmgError(st, lib().wcmg_coarse_last_error(ops[0].h).decode())
+    return ms.value

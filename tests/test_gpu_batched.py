@@ -172,3 +172,37 @@ def test_autotuner_table_and_forced_variants():
         res = residuals(H, b, host(x2))
         assert np.all(res <= 1.01e-10), res
         assert all(abs(a - c) <= 1 for a, c in zip(base, [i["outer_iters"] for i in i2]))
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_ragged_coarse_apply(store):
+    """One launch over three coarse operators of different lattices (the coarse
+    lattices of 8^4, 16^4 and 24^3 x 48 under 4^4 aggregates: 16 + 256 + 2592
+    sites, Nb = 24) with 12, 5 and 16 right-hand sides: bit-identical to the
+    operators applied one by one, and within FP32 rounding of the oracle
+    (applied to the BF16-rounded blocks for BF16 storage)."""
+    from tests.test_gpu_parity import bf16_round, rel
+    w = wc()
+    st = w.F32 if store == "f32" else w.BF16
+    lats = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 6, 6, 12)]
+    nrhs = [12, 5, 16]
+    ops, ins, refs = [], [], []
+    for q, (Lc, nr) in enumerate(zip(lats, nrhs)):
+        Vc = int(np.prod(Lc))
+        blocks = syn.complex_gaussian((Vc, 9, 24, 24), 780 + q)
+        phi = syn.complex_gaussian((nr, Vc, 24), 790 + q)
+        op = w.CoarseOperator(Lc, 24, st)
+        op.set(dev(blocks))
+        op.set_kernel(2)
+        ops.append(op)
+        ins.append(dev(phi.astype(np.complex64)))
+        refs.append(oracle.coarse_apply(Lc, bf16_round(blocks) if store == "bf16" else blocks, phi))
+    outs = w.coarse_apply_ragged(ops, ins)
+    for op, x, y, ref in zip(ops, ins, outs, refs):
+        one = host(op.apply(x))
+        got = host(y)
+        assert np.array_equal(got, one)
+        assert rel(got, ref) < 1e-5
+    assert w.coarse_time_ragged(ops, ins, reps=3) > 0
+    with pytest.raises(w.WcmgError):
+        w.coarse_apply_ragged([ops[0], w.CoarseOperator((2, 2, 2, 2), 16, st)], ins[:1] * 2)
