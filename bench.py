@@ -249,6 +249,7 @@ def ragged_batch(w, torch, nrhs=12, reps=50):
     16^4 and 24^3 x 48 under 4^4 aggregates: 16 + 256 + 2592 coarse sites,
     Nb = 24, nrhs fields each) against the three operators launched one after
     another (sum of their back-to-back launch times)."""
+    import numpy as np
     lats = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 6, 6, 12)]
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
@@ -274,6 +275,77 @@ def ragged_batch(w, torch, nrhs=12, reps=50):
         out[name] = {"ragged_ms": t_rag, "separate_ms": t_sep, "speedup": t_sep / t_rag,
                      "ragged_GB_s": byts / t_rag / 1e6}
     return out
+
+
+def learned_setup(w, torch, L=(16, 16, 16, 16), ntrain=6, ntest=4, epochs=8, nv=12, ch=32, lr=5e-3, seed=105):
+    """Learned near-null proposal: trained on the plain setup's vectors (20
+    sweeps + 2 refinement iterations) of ntrain seeded fields with eps ~
+    U[0.2, 0.35], m0 = -0.08; on ntest held-out fields the learned setup
+    (network + k MR sweeps, no refinement) is compared with the plain setup at
+    the same k and with the plain 2-iteration setup: setup s, outer iterations,
+    solve s.  Forward and backward throughput of the network kernels (FP32
+    matrix cores) from HIP events."""
+    import numpy as np
+    import synthetic as syn
+    V = int(np.prod(L))
+    s = syn.config_seeds(seed)
+    eps = np.random.default_rng(s["net"]).uniform(0.2, 0.35, ntrain + ntest)
+
+    def ctx_for(f, relax, refine):
+        c = w.Context(dims=L, m0=-0.08, c_sw=1.0, n_levels=2, block=((4, 4, 4, 4),), n_vec=(nv,),
+                      relax_sweeps=relax, refine_iters=refine, cycle_prec=w.F32, coarse_store_prec=w.F32,
+                      setup_prec=w.F32, outer_restart=20, outer_maxit=2000)
+        c.set_gauge(torch.from_numpy(syn.gauge_field(L, eps[f], s["gauge"] + f)).cuda())
+        c.set_null_vectors(0, torch.from_numpy(syn.start_vectors(nv, V, 12, s["start"] + f)).cuda())
+        return c
+
+    ctxs = []
+    for f in range(ntrain + ntest):
+        c = ctx_for(f, 20, 2)
+        c.setup()
+        ctxs.append(c)
+    net = w.Network(nv, ch, act_prec=w.BF16, seed=s["net"])
+    init = [net.loss_grad(c, grad=False)[0] for c in ctxs[ntrain:]]
+    for c in ctxs[:1]:
+        c.profile("nn_forward", True)
+        c.profile("nn_backward", True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = []
+    for e in range(epochs):
+        curve.append(float(np.mean([net.train_step(c, lr=lr) for c in ctxs[:ntrain]])))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    nf, msf = ctxs[0].profile_stats("nn_forward")
+    nb_, msb = ctxs[0].profile_stats("nn_backward")
+    # useful complex multiply-adds of the three layers per site: 9 (Cin Cout) 12, 8 flops each
+    fl = 8.0 * 9 * 12 * V * (nv * ch + ch * ch + ch * nv)
+    held = [net.loss_grad(c, grad=False)[0] for c in ctxs[ntrain:]]
+    b = torch.from_numpy(syn.complex_gaussian((V, 4, 3), s["rhs"])).cuda()
+    rows = []
+    for f in range(ntrain, ntrain + ntest):
+        r = {}
+        for name, relax, refine in (("plain_20sweeps_2refine", 20, 2), ("plain_20sweeps", 20, 0), ("plain_5sweeps", 5, 0)):
+            c = ctx_for(f, relax, refine)
+            c.setup()
+            x, info, st = c.solve(b)
+            r[name] = {"setup_s": c.timers()["setup"], "outer_iters": info[0]["outer_iters"],
+                       "solve_s": info[0]["t_solve_s"]}
+        for name, k in (("learned_5sweeps", 5), ("learned_20sweeps", 20)):
+            c = ctx_for(f, 20, 0)
+            fb, q = c.setup_learned(net, relax_sweeps=k)
+            x, info, st = c.solve(b)
+            r[name] = {"setup_s": c.timers()["setup"], "outer_iters": info[0]["outer_iters"],
+                       "solve_s": info[0]["t_solve_s"], "fell_back": fb, "quality": q}
+        rows.append(r)
+    return {"lattice": list(L), "n_vec": nv, "channels": ch, "train_fields": ntrain, "held_out_fields": ntest,
+            "epochs": epochs, "train_s": t_train, "train_loss_curve": curve, "held_out_loss_untrained": init,
+            "held_out_loss_trained": held, "held_out": rows,
+            "nn_forward": {"launches": nf, "avg_ms": msf / max(nf, 1), "TFLOP_s": fl / (msf / max(nf, 1)) / 1e9,
+                           "frac_fp32_mfma": fl / (msf / max(nf, 1)) / 1e9 / 157.3},
+            "nn_backward": {"launches": nb_, "avg_ms": msb / max(nb_, 1),
+                            "TFLOP_s": 2 * fl / (msb / max(nb_, 1)) / 1e9,
+                            "frac_fp32_mfma": 2 * fl / (msb / max(nb_, 1)) / 1e9 / 157.3}}
 
 
 def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
@@ -314,6 +386,12 @@ def kernel_mode(args):
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"family": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "reps": args.reps}))
+        return
+    if fam == "learned_setup":
+        # the learned-setup study at a chosen size: --lattice, --ntrain, --ntest, --epochs
+        L = tuple(int(v) for v in args.lattice.split(","))
+        res = learned_setup(w, torch, L=L, ntrain=args.ntrain, ntest=args.ntest, epochs=args.epochs)
+        print(json.dumps({"family": fam, **res}))
         return
     if fam == "batched_solve":
         # setup plus one batched solve of the twelve point sources on 24^3 x 48
@@ -379,11 +457,16 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mk", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
-                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve")
+                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
+    ap.add_argument("--lattice", default="24,24,24,48", help="learned_setup kernel mode: lattice")
+    ap.add_argument("--ntrain", type=int, default=48)
+    ap.add_argument("--ntest", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--mib", type=int, default=1024)
     ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides for the batched coarse-apply kernel mode")
     args = ap.parse_args()
@@ -489,6 +572,9 @@ def main():
         extra["batched_24x48"] = batched_point_sources(w, torch, WORKLOAD_BATCH, fp64=not args.no_fp64)
         print("[bench] ragged batch of coarse operators", file=sys.stderr, flush=True)
         extra["ragged_coarse_apply"] = ragged_batch(w, torch)
+    if not args.no_learned:
+        print("[bench] learned setup (16^4, 6 training / 4 held-out fields)", file=sys.stderr, flush=True)
+        extra["learned_setup"] = learned_setup(w, torch)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)

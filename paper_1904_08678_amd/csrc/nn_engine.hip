@@ -124,11 +124,13 @@ void Net::forward(Context& c) {
   const cf32* U = c.U32.as<cf32>();
   const int* nbr = c.geo[0].nbr.as<int>();
   launch_nn_from64(c.tr[0].start64.as<cd64>(), act_bits, act[0].p, (long)nv * 12 * V, c.stream);
+  c.prof.begin("nn_forward", c.stream);
   launch_nn_layer(act_bits, act[0].p, nv, W[0].as<cf32>(), ch, act_bits, act[1].p, scale[0].as<float>(), 1, U, nbr, V,
                   c.stream);
   launch_nn_layer(act_bits, act[1].p, ch, W[1].as<cf32>(), ch, act_bits, act[2].p, scale[1].as<float>(), 1, U, nbr, V,
                   c.stream);
   launch_nn_layer(act_bits, act[2].p, ch, W[2].as<cf32>(), nv, 32, act[3].p, nullptr, 0, U, nbr, V, c.stream);
+  c.prof.end("nn_forward", c.stream);
 }
 
 double Net::loss_grad(Context& c) {
@@ -148,6 +150,7 @@ double Net::loss_grad(Context& c) {
   cf32* gb = g1.as<cf32>();
   launch_nn_loss(act[3].as<cf32>(), tgt.as<cf32>(), nv, T.agg_sites.as<int>(), T.A, T.Vc, V, norm, ga,
                  lpart.as<double>(), c.stream);
+  c.prof.begin("nn_backward", c.stream);
   // layer 2 (linear): weight gradient, then the gradient of its input
   launch_nn_wgrad(ga, nv, act_bits, act[2].p, ch, U, nbr, V, part.as<cd64>(), gW[2].as<cf32>(), c.stream);
   launch_nn_layer(32, ga, nv, Wadj[2].as<cf32>(), ch, 32, gb, nullptr, 0, U, nbr, V, c.stream);
@@ -158,6 +161,7 @@ double Net::loss_grad(Context& c) {
   launch_nn_squash_bwd(ga, act_bits, act[1].p, scale[0].as<float>(), ch, V, c.stream);
   // layer 0
   launch_nn_wgrad(ga, ch, act_bits, act[0].p, nv, U, nbr, V, part.as<cd64>(), gW[0].as<cf32>(), c.stream);
+  c.prof.end("nn_backward", c.stream);
   WCMG_HIP(hipMemcpyAsync(lp.data(), lpart.p, lp.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
   WCMG_HIP(hipStreamSynchronize(c.stream));
   double loss = 0.0;
