@@ -66,6 +66,9 @@ def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int 
 TRAFFIC_SOURCES = {
     "dslash_f32": ("paper_1904_08678_amd/csrc/wilson.hip",),
     "coarse_apply_f32_large": ("paper_1904_08678_amd/csrc/coarse.hip", "paper_1904_08678_amd/csrc/coarse_common.h"),
+    "coarse_mfma_f32_12rhs": ("paper_1904_08678_amd/csrc/coarse_mfma.hip",),
+    "coarse_mfma_bf16_12rhs": ("paper_1904_08678_amd/csrc/coarse_mfma.hip",),
+    "dslash_f32_mrhs_12rhs": ("paper_1904_08678_amd/csrc/wilson.hip",),
 }
 
 
@@ -567,6 +570,10 @@ def main():
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)
         extra["coarse_apply_large"]["per_store"]["f32"]["traffic"] = counter_traffic("coarse_apply_f32_large")
+        for st in ("f32", "bf16"):
+            rec = extra["coarse_apply_large"]["batched"].get(st)
+            if rec:
+                rec["matrix_cores"]["traffic"] = counter_traffic("coarse_mfma_%s_12rhs" % st)
     if not args.no_batched:
         print("[bench] batched point sources, 24^3x48", file=sys.stderr, flush=True)
         extra["batched_24x48"] = batched_point_sources(w, torch, WORKLOAD_BATCH, fp64=not args.no_fp64)

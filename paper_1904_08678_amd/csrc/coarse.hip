@@ -105,8 +105,8 @@ static void launch_ca(const void* blk, const void* in, void* out, const int* nbr
                       int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
   typedef typename BlkTraits<P>::R R;
   long rows = Vc * nb;
-  hipLaunchKernelGGL((k_coarse_apply<P, NB, S>), dim3(nblocks(rows * S), nrhs), dim3(kBlock), 0, st,
-                     (const Chunk16*)blk, (const cplx<R>*)in, (cplx<R>*)out, nbr, Vc, nb, dmask, accumulate, run, rs);
+  WCMG_LAUNCH((k_coarse_apply<P, NB, S>), dim3(nblocks(rows * S), nrhs), dim3(kBlock), 0, st, (const Chunk16*)blk,
+              (const cplx<R>*)in, (cplx<R>*)out, nbr, Vc, nb, dmask, accumulate, run, rs);
 }
 
 template <int P, int NB>

@@ -273,8 +273,8 @@ template <int P, int NB, int S>
 static void cg_apply_t(const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2, void* V, int j,
                        void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
   typedef typename BlkTraits<P>::R R;
-  hipLaunchKernelGGL((k_cg_apply<P, NB, S>), dim3(nblocks(Vc * NB * S)), dim3(kBlock), 0, st, (const Chunk16*)blk,
-                     nbr, Vc, (const cplx<R>*)u, unrm2, (cplx<R>*)V, j, (cplx<R>*)wout, part, m1, run);
+  WCMG_LAUNCH((k_cg_apply<P, NB, S>), dim3(nblocks(Vc * NB * S)), dim3(kBlock), 0, st, (const Chunk16*)blk, nbr, Vc,
+              (const cplx<R>*)u, unrm2, (cplx<R>*)V, j, (cplx<R>*)wout, part, m1, run);
 }
 template <int P, int NB>
 static void cg_apply_s(int S, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2, void* V,

@@ -267,8 +267,8 @@ void launch_blocks_to_mfma(const cd64* src, long Vc, int nb, int prec, void* dst
 template <int P, int NB>
 static void mfma_t(const void* blk, const cf32* in, cf32* out, const int* nbr, long Vc, int nrhs, const int* run,
                    int run_stride, hipStream_t st) {
-  hipLaunchKernelGGL((k_coarse_apply_mfma<P, NB>), dim3((unsigned)((Vc + 3) / 4)), dim3(kBlock), 0, st,
-                     (const typename MfmaChunk<P>::T*)blk, in, out, nbr, Vc, nrhs, run, run_stride);
+  WCMG_LAUNCH((k_coarse_apply_mfma<P, NB>), dim3((unsigned)((Vc + 3) / 4)), dim3(kBlock), 0, st,
+              (const typename MfmaChunk<P>::T*)blk, in, out, nbr, Vc, nrhs, run, run_stride);
 }
 template <int P>
 static void mfma_nb(int nb, const void* blk, const cf32* in, cf32* out, const int* nbr, long Vc, int nrhs,

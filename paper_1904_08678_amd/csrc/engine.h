@@ -12,10 +12,14 @@
 
 namespace wcmg {
 
-// HIP-event timing of kernel families on the context stream.
+// HIP-event timing of kernel families on the context stream.  A family of
+// one kernel launch is timed by the dispatch itself (begin_kernel arms the
+// launch's event pair); a family of several launches by events recorded on
+// the stream around them (begin).
 struct Profiler {
   struct Family {
     bool on = false;
+    bool armed = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t used = 0;
   };
@@ -23,6 +27,7 @@ struct Profiler {
   ~Profiler();
   void enable(const std::string& f, bool on);
   void begin(const char* f, hipStream_t st);
+  void begin_kernel(const char* f);
   void end(const char* f, hipStream_t st);
   void stats(const std::string& f, int64_t* launches, double* ms);
   size_t pending_ = 0;

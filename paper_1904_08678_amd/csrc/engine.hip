@@ -29,10 +29,30 @@ void Profiler::begin(const char* f, hipStream_t st) {
   }
   WCMG_HIP(hipEventRecord(F.ev[F.used].first, st));
 }
+void Profiler::begin_kernel(const char* f) {
+  auto it = fam.find(f);
+  if (it == fam.end() || !it->second.on) return;
+  Family& F = it->second;
+  if (F.used == F.ev.size()) {
+    hipEvent_t a, b;
+    WCMG_HIP(hipEventCreate(&a));
+    WCMG_HIP(hipEventCreate(&b));
+    F.ev.push_back({a, b});
+  }
+  kernel_timing() = KernelTiming{F.ev[F.used].first, F.ev[F.used].second};
+  F.armed = true;
+}
 void Profiler::end(const char* f, hipStream_t st) {
   auto it = fam.find(f);
   if (it == fam.end() || !it->second.on) return;
   Family& F = it->second;
+  if (F.armed) {
+    F.armed = false;
+    const bool consumed = kernel_timing().start == nullptr;
+    kernel_timing() = KernelTiming();
+    if (consumed) F.used++;  // else no launch took the events: no sample
+    return;
+  }
   WCMG_HIP(hipEventRecord(F.ev[F.used].second, st));
   F.used++;
 }
@@ -300,7 +320,7 @@ void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const i
   const bool single = sizeof(R) == 4;
   if (l == 0) {
     const char* fam = terms != 0x1ff ? "wilson_term" : single ? "dslash_f32" : "dslash_f64";
-    prof.begin(fam, stream);
+    prof.begin_kernel(fam);
     if (single)
       launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
                            geo[0].V, terms, nrhs, run, stream, dots);
@@ -312,7 +332,7 @@ void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const i
     const int prec = store_prec_for(l, single);
     const char* fam = terms != 0x1ff ? "coarse_term" : prec == WCMG_F64 ? "coarse_apply_f64"
                                                       : prec == WCMG_F32 ? "coarse_apply_f32" : "coarse_apply_bf16";
-    prof.begin(fam, stream);
+    prof.begin_kernel(fam);
     cop[l - 1]->apply(prec, in, out, terms, 0, nrhs, run, stream);
     prof.end(fam, stream);
   }
@@ -357,7 +377,7 @@ void Context::restrict_(int l, const cplx<R>* fine, cplx<R>* coarse, int nrhs, c
   Transfer& T = tr[l];
   const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
   const char* fam = sizeof(R) == 8 ? "restrict_f64" : "restrict_f32";
-  prof.begin(fam, stream);
+  prof.begin_kernel(fam);
   launch_restrict<R>(fine, coarse, P, geo[l].lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nb, nrhs, run, stream);
   prof.end(fam, stream);
 }
@@ -367,7 +387,7 @@ void Context::prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumula
   Transfer& T = tr[l];
   const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
   const char* fam = sizeof(R) == 8 ? "prolong_f64" : "prolong_f32";
-  prof.begin(fam, stream);
+  prof.begin_kernel(fam);
   launch_prolong<R>(coarse, fine, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, accumulate, nrhs, run, stream);
   prof.end(fam, stream);
 }
@@ -547,7 +567,7 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
       const cplx<R>* u = j == 0 ? u0 : wb[j & 1];
       const cd64* unrm2 = j == 0 ? misc + 1 : misc + 3;
       cplx<R>* w = wb[(j + 1) & 1];
-      prof.begin(fam, stream);
+      prof.begin_kernel(fam);
       const int G1 = launch_cg_apply(prec, nb, blk, C.nbr.as<int>(), C.V, u, unrm2, V, j, w, partA, m1, run, stream);
       prof.end(fam, stream);
       launch_cg_orth<R>(V, j, w, nn, partA, G1, S, m, 0, partB, run, stream);

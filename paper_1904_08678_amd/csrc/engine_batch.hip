@@ -32,6 +32,9 @@ int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>
   auto it = choice.find(key);
   if (it != choice.end()) return it->second;
   if (!enabled || nvar <= 1) return fallback;
+  // the candidates' launches must not take a profiled launch's event pair
+  const KernelTiming armed = kernel_timing();
+  kernel_timing() = KernelTiming();
   if (!ev[0]) {
     WCMG_HIP(hipEventCreate(&ev[0]));
     WCMG_HIP(hipEventCreate(&ev[1]));
@@ -53,6 +56,7 @@ int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>
     if (t[v] < t[best]) best = v;
   choice[key] = best;
   ms[key] = t;
+  kernel_timing() = armed;
   return best;
 }
 
@@ -147,7 +151,7 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
   const bool single = sizeof(R) == 4;
   if (l == 0) {
     const char* fam = single ? "dslash_f32" : "dslash_f64";
-    if (!capturing) prof.begin(fam, stream);
+    if (!capturing) prof.begin_kernel(fam);
     if (single)
       dslash32_batch((const cf32*)in, (cf32*)out, B, run, rs, nullptr);
     else
@@ -174,7 +178,7 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
   const char* fam = mfma ? (prec == WCMG_F32 ? "coarse_mfma_f32" : "coarse_mfma_bf16")
                          : prec == WCMG_F64 ? "coarse_apply_f64"
                          : prec == WCMG_F32 ? "coarse_apply_f32" : "coarse_apply_bf16";
-  if (!capturing) prof.begin(fam, stream);
+  if (!capturing) prof.begin_kernel(fam);
   C.apply_batch(prec, in, out, B, mfma ? 2 : 1, run, rs, stream);
   if (!capturing) prof.end(fam, stream);
 }
@@ -316,7 +320,7 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
   cplx<R>* ec = buf<cplx<R>>("bcyc_ec" + t, B * nc);
   {
     const char* fam = sizeof(R) == 8 ? "restrict_f64" : "restrict_f32";
-    if (!capturing) prof.begin(fam, stream);
+    if (!capturing) prof.begin_kernel(fam);
     const Transfer& T = tr[l];
     const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
     launch_restrict<R>(r, rc, P, geo[l].lay, T.agg_sites.as<int>(), T.A, T.Vc, T.nb, B, run, stream, rs);
@@ -347,7 +351,7 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
   for (int q = 0; q < B; ++q) coarse_iters += its[q];
   {
     const char* fam = sizeof(R) == 8 ? "prolong_f64" : "prolong_f32";
-    if (!capturing) prof.begin(fam, stream);
+    if (!capturing) prof.begin_kernel(fam);
     const Transfer& T = tr[l];
     const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
     launch_prolong<R>(ec, x, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, 0, B, run, stream, rs);

@@ -1,6 +1,8 @@
 // Launcher declarations of the wcmg HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace wcmg {
@@ -137,6 +139,25 @@ void launch_bgmres_givens(int* st_, cd64* S, long ss, int B, int m, int j, doubl
                           int stop_on_est, hipStream_t st);
 void launch_bgmres_solve_y(const int* st_, cd64* S, long ss, int B, int m, hipStream_t st);
 void launch_bgmres_cycle_end(int* st_, int B, hipStream_t st);
+
+// ---- per-launch kernel timing
+// A profiled single-kernel launch takes its event pair from this thread-local
+// slot and records it in the dispatch itself (hipExtLaunchKernelGGL), so the
+// measured interval is the kernel's own execution; the slot is then cleared.
+struct KernelTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+KernelTiming& kernel_timing();
+#define WCMG_LAUNCH(K, G, B, S, ST, ...)                                                    \
+  do {                                                                                     \
+    ::wcmg::KernelTiming& kt_ = ::wcmg::kernel_timing();                                   \
+    if (kt_.start) {                                                                       \
+      hipExtLaunchKernelGGL(K, G, B, S, ST, kt_.start, kt_.stop, 0, __VA_ARGS__);          \
+      kt_ = ::wcmg::KernelTiming();                                                        \
+    } else {                                                                               \
+      hipLaunchKernelGGL(K, G, B, S, ST, __VA_ARGS__);                                     \
+    }                                                                                      \
+  } while (0)
 
 // ---- learned near-null proposal (nn.hip); activations: 16 = BF16, 32 = FP32
 void launch_nn_layer(int act_bits_in, const void* in, int Cin, const cf32* W, int Cout, int act_bits_out, void* out,

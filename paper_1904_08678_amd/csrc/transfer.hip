@@ -272,15 +272,15 @@ bool supported_nb(int nb) {
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, hipLaunchKernelGGL((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(kBlock), 0, st, fine,
-                                    coarse, P, lay, agg_sites, A, Vc, nrhs, run, rs));
+  NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(kBlock), 0, st, fine, coarse, P,
+                             lay, agg_sites, A, Vc, nrhs, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 template <typename R>
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
                     long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, hipLaunchKernelGGL((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
-                                    coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
+  NB_SWITCH(nb, WCMG_LAUNCH((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
+                             coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
   WCMG_CHECK_LAUNCH();
 }
 #define INST_TR(R)                                                                                                 \

@@ -651,8 +651,8 @@ INST_PACK(float, double)
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs) {
-  hipLaunchKernelGGL(k_wilson<R>, dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
-                     nbr, V, terms, nrhs, dots, run, rs);
+  WCMG_LAUNCH(k_wilson<R>, dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov, nbr, V,
+              terms, nrhs, dots, run, rs);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
@@ -662,6 +662,11 @@ template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 
+KernelTiming& kernel_timing() {
+  static thread_local KernelTiming slot;
+  return slot;
+}
+
 void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* clov, const int* nbr, long V, int nrhs,
                         const int* run, int rs, cd64* dots, hipStream_t st) {
   require(12L * V * 8 < (1L << 31), WCMG_ERR_DIMS, "multi-RHS Dslash: field exceeds the 2 GiB buffer range");
@@ -669,8 +674,8 @@ void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* c
   // waves per workgroup: at most 8, as few as keep every wave's share equal
   const int per = (nrhs + 7) / 8;
   const int nw = (nrhs + per - 1) / per;
-  hipLaunchKernelGGL(k_wilson_mrhs, dim3(nblocks(V, 64)), dim3(64 * nw), 0, st, in, out, U, clov, nbr, V, nrhs, dots,
-                     run, rs);
+  WCMG_LAUNCH(k_wilson_mrhs, dim3(nblocks(V, 64)), dim3(64 * nw), 0, st, in, out, U, clov, nbr, V, nrhs, dots, run,
+              rs);
   WCMG_CHECK_LAUNCH();
 }
 
