@@ -45,6 +45,56 @@ WORKLOAD_BATCH = dict(
 )
 
 
+WORKLOAD_THREE = dict(
+    name="three-level MG, 32^3x64, Nb=24 then 32 (4^4 then 2^4 aggregates), 3 refinement iterations, BF16 coarse "
+         "blocks with FP32 accumulation, K-cycle, FGMRES(20) to 1e-10",
+    L=(32, 32, 32, 64), eps=0.25, m0=-0.09, csw=1.0, blocks=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), relax=20,
+    refine=3, seed=103,
+)
+
+
+def three_level(w, torch, wl=WORKLOAD_THREE, fp64=True):
+    """Config 3: three-level hierarchy with BF16-stored coarse blocks and a
+    K-cycle on the intermediate level, against the same hierarchy run in FP64."""
+    import numpy as np
+    import synthetic as syn
+    L = wl["L"]
+    V = int(np.prod(L))
+    s = syn.config_seeds(wl["seed"])
+    Ud = torch.from_numpy(syn.gauge_field(L, wl["eps"], s["gauge"])).cuda()
+    starts = [torch.from_numpy(syn.start_vectors(wl["nv"][0], V, 12, s["start"])).cuda()]
+    V1 = V // int(np.prod(wl["blocks"][0]))
+    starts.append(torch.from_numpy(syn.start_vectors(wl["nv"][1], V1, 2 * wl["nv"][0], s["start"] + 500)).cuda())
+    b = torch.from_numpy(syn.complex_gaussian((V, 4, 3), s["rhs"])).cuda()
+    out = {"workload": wl["name"]}
+    for label, mixed in (("mixed_bf16_kcycle", True), ("fp64_kcycle", False)):
+        if label.startswith("fp64") and not fp64:
+            continue
+        kw = dict(dims=L, m0=wl["m0"], c_sw=wl["csw"], n_levels=3, block=wl["blocks"], n_vec=wl["nv"],
+                  relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000, kcycle=1)
+        if mixed:
+            kw.update(cycle_prec=w.F32, coarse_store_prec=w.BF16, setup_prec=w.F32)
+        ctx = w.Context(**kw)
+        ctx.set_gauge(Ud)
+        ctx.set_null_vectors(0, starts[0])
+        ctx.set_null_vectors(1, starts[1])
+        ctx.setup()
+        setup_s = ctx.timers()["setup"]
+        ctx.solve(b)
+        x, info, st = ctx.solve(b)
+        out[label] = {"setup_s": setup_s, "solve_s": info[0]["t_solve_s"], "outer_iters": info[0]["outer_iters"],
+                      "coarse_iters": info[0]["coarse_iters"], "true_rel_res": info[0]["true_rel_res"],
+                      "converged": bool(info[0]["converged"]) and st == 0}
+        print("[bench] three-level %s: setup %.3f s, solve %.3f s, %d outer iterations, res %.2e" % (
+            label, setup_s, out[label]["solve_s"], out[label]["outer_iters"], out[label]["true_rel_res"]),
+            file=sys.stderr, flush=True)
+        del ctx, x
+        torch.cuda.empty_cache()
+    if fp64:
+        out["speedup_mixed_vs_fp64"] = out["fp64_kcycle"]["solve_s"] / out["mixed_bf16_kcycle"]["solve_s"]
+    return out
+
+
 def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int = 1) -> float:
     """Bytes a launch must move at minimum (each operand read once, output written
     once); with nrhs fields per launch the gauge data and P are read once."""
@@ -390,6 +440,9 @@ def kernel_mode(args):
         torch.cuda.synchronize()
         print(json.dumps({"family": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "reps": args.reps}))
         return
+    if fam == "three_level":
+        print(json.dumps({"family": fam, **three_level(w, torch)}))
+        return
     if fam == "learned_setup":
         # the learned-setup study at a chosen size: --lattice, --ntrain, --ntest, --epochs
         L = tuple(int(v) for v in args.lattice.split(","))
@@ -463,7 +516,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
-                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup")
+                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, three_level")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
     ap.add_argument("--lattice", default="24,24,24,48", help="learned_setup kernel mode: lattice")
