@@ -209,44 +209,98 @@ __global__ void k_prolongator_columns(const cd64* __restrict__ P, FieldLayout la
 // W_b = Mdir_d(column b of P) (or Mdiag for d = 0) is projected on the rows of
 // P aggregate by aggregate; contributions of sites whose d-neighbour lies in
 // the same aggregate go to block 0, the rest to block d.
-// grid (Vc, NB columns, 2 targets), block 256.  FP64.
-template <int NB>
+//
+// One workgroup per aggregate computes, chirality by chirality, the small
+// product P_chi^dag W_chi (nv x NB, K = A * ns/2 rows) for both targets at once:
+// row tiles of P and W are staged in LDS (one coalesced read of each from
+// HBM), each thread accumulates an AB x BB block of outputs for both targets
+// over the rows of its row group, and the row groups are added in a fixed
+// order.  FP64.
+template <int NB, int AB, int BB>
 __global__ void __launch_bounds__(256) k_galerkin_project(const cd64* __restrict__ W, const cd64* __restrict__ P,
                                                            FieldLayout lay, const int* __restrict__ agg_sites,
                                                            const int* __restrict__ coarse_of,
                                                            const int* __restrict__ nbr_d, int A, long Vc, int d,
                                                            cd64* __restrict__ M) {
   constexpr int nv = NB / 2;
-  __shared__ cd64 lds[16 * NB];
-  __shared__ cd64 res[NB];
+  constexpr int T = 32;  // rows per tile
+  constexpr int TPG = (nv / AB) * (NB / BB);  // threads per row group
+  __shared__ cd64 Pt[T][nv], Wt[T][NB];
+  __shared__ cd64 res[2][nv][NB];
+  __shared__ unsigned char ext[T];
   const long c = blockIdx.x;
-  const int b = blockIdx.y;
-  const int target = blockIdx.z;  // 0: block 0 (interior), 1: block d (exterior)
-  if (d == 0 && target == 1) return;
+  const int tid = threadIdx.x;
+  const int ngroups = (int)blockDim.x / TPG;
+  const int grp = tid / TPG, q = tid - grp * TPG;
+  const bool active = grp < ngroups;
+  const int a0 = (q / (NB / BB)) * AB, b0 = (q % (NB / BB)) * BB;
   const int h = lay.ns / 2;
+  const int R = A * h;
   const long vs = lay.size();
-  const cd64* Wb = W + b * vs;
-  cd64 acc[NB];
+  for (int chi = 0; chi < 2; ++chi) {
+    cd64 acc[2][AB][BB];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) acc[a] = mkc(0.0, 0.0);
-  for (int o = threadIdx.x; o < A; o += blockDim.x) {
-    const long s = agg_sites[c * A + o];
-    bool interior = (d == 0) || (coarse_of[nbr_d[s]] == c);
-    if (interior != (target == 0)) continue;
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int chi = 0; chi < 2; ++chi)
-      for (int k = 0; k < h; ++k) {
-        const long e = lay.at(s, chi * h + k);
-        const cd64 w = Wb[e];
+      for (int x = 0; x < AB; ++x)
 #pragma unroll
-        for (int i = 0; i < nv; ++i) cfmac(acc[chi * nv + i], P[i * vs + e], w);
+        for (int y = 0; y < BB; ++y) acc[t][x][y] = mkc(0.0, 0.0);
+    for (int r0 = 0; r0 < R; r0 += T) {
+      const int nr = min(T, R - r0);
+      __syncthreads();
+      // rows ordered so that consecutive rows are consecutive in memory
+      for (int idx = tid; idx < nr * (nv + NB); idx += blockDim.x) {
+        const int rr = idx % nr, col = idx / nr;
+        const int r = r0 + rr;
+        const int o = lay.soa ? r % A : r / h, k = lay.soa ? r / A : r % h;
+        const long sidx = agg_sites[c * A + o];
+        const long e = lay.at(sidx, chi * h + k);
+        if (col < nv) Pt[rr][col] = P[col * vs + e];
+        else Wt[rr][col - nv] = W[(col - nv) * vs + e];
+        if (col == 0) ext[rr] = (d != 0 && coarse_of[nbr_d[sidx]] != c) ? 1 : 0;
       }
-  }
-  block_sum<NB>(acc, lds, res);
-  if (threadIdx.x < NB) {
-    const int dd = target == 0 ? 0 : d;
-    cd64* m = M + ((c * 9 + dd) * NB + threadIdx.x) * NB + b;
-    *m = cadd(*m, res[threadIdx.x]);
+      __syncthreads();
+      if (active) {
+        for (int rr = grp; rr < nr; rr += ngroups) {
+          cd64 p[AB], w[BB];
+#pragma unroll
+          for (int x = 0; x < AB; ++x) p[x] = Pt[rr][a0 + x];
+#pragma unroll
+          for (int y = 0; y < BB; ++y) w[y] = Wt[rr][b0 + y];
+          if (ext[rr]) {
+#pragma unroll
+            for (int x = 0; x < AB; ++x)
+#pragma unroll
+              for (int y = 0; y < BB; ++y) cfmac(acc[1][x][y], p[x], w[y]);
+          } else {
+#pragma unroll
+            for (int x = 0; x < AB; ++x)
+#pragma unroll
+              for (int y = 0; y < BB; ++y) cfmac(acc[0][x][y], p[x], w[y]);
+          }
+        }
+      }
+    }
+    // row groups added in index order
+    for (int g = 0; g < ngroups; ++g) {
+      __syncthreads();
+      if (active && grp == g)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int x = 0; x < AB; ++x)
+#pragma unroll
+            for (int y = 0; y < BB; ++y)
+              res[t][a0 + x][b0 + y] = g == 0 ? acc[t][x][y] : cadd(res[t][a0 + x][b0 + y], acc[t][x][y]);
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * nv * NB; e += blockDim.x) {
+      const int t = e / (nv * NB), ab = e - t * nv * NB, a = ab / NB, b = ab - a * NB;
+      if (t == 1 && d == 0) continue;
+      const int dd = t == 0 ? 0 : d;
+      cd64* m = M + ((c * 9 + dd) * NB + chi * nv + a) * NB + b;
+      *m = cadd(*m, res[t][a][b]);
+    }
   }
 }
 
@@ -305,8 +359,9 @@ void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* ou
 void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
                              const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
                              hipStream_t st) {
-  NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_project<NBc>), dim3(Vc, NBc, 2), dim3(kBlock), 0, st, W, P, lay,
-                                    agg_sites, coarse_of, nbr_d, A, Vc, d, M));
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_project<NBc, (NBc / 2) % 2 == 0 ? 2 : 1, NBc % 4 == 0 ? 4 : 2>),
+                                    dim3(Vc), dim3(kBlock), 0, st, W, P, lay, agg_sites, coarse_of, nbr_d, A, Vc, d,
+                                    M));
   WCMG_CHECK_LAUNCH();
 }
 
