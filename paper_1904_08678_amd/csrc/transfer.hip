@@ -191,6 +191,119 @@ __global__ void __launch_bounds__(256) k_block_orthonormalise(cd64* __restrict__
   }
 }
 
+// Register-resident variant for blocks of up to 4 * 512 elements: a workgroup
+// of 512 threads holds the whole (aggregate, chirality) block of all NV vectors
+// in registers (EPT elements per thread), reads and writes it once, and
+// orthonormalises with classical Gram-Schmidt applied twice: the projections
+// of vector i on all earlier vectors come out of one block reduction per pass
+// (fixed order: waves in index order).  Same result as the modified form up to
+// rounding; same breakdown rule.
+template <int NV, int EPT>
+__global__ void __launch_bounds__(512) k_block_orth_reg(cd64* __restrict__ vecs, FieldLayout lay,
+                                                         const int* __restrict__ agg_sites, int A,
+                                                         int* __restrict__ breakdown) {
+  __shared__ cd64 red[8][NV];
+  __shared__ cd64 tot[NV];
+  const long c = blockIdx.x;
+  const int chi = blockIdx.y;
+  const int h = lay.ns / 2;
+  const int nel = A * h;
+  const long vs = lay.size();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  long q[EPT];
+  bool ok[EPT];
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) {
+    const int e = threadIdx.x + t * (int)blockDim.x;
+    ok[t] = e < nel;
+    const int o = ok[t] ? e % A : 0, k = ok[t] ? e / A : 0;
+    q[t] = lay.at(agg_sites[c * A + o], chi * h + k);
+  }
+  cd64 v[NV][EPT];
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) v[j][t] = ok[t] ? vecs[j * vs + q[t]] : mkc(0.0, 0.0);
+  // wave-reduce one complex value into red[wave][slot]
+  auto wave_put = [&](double re, double im, int slot) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) red[wave][slot] = mkc(re, im);
+  };
+  // sum the n slots over the waves in index order into tot
+  auto finish = [&](int n) {
+    __syncthreads();
+    if ((int)threadIdx.x < n) {
+      cd64 s = mkc(0.0, 0.0);
+      for (int w = 0; w < nw; ++w) s = cadd(s, red[w][threadIdx.x]);
+      tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+  };
+  for (int i = 0; i < NV; ++i) {
+    cd64 vi[EPT];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j == i)
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) vi[t] = v[j][t];
+    double n2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) n2 += vi[t].re * vi[t].re + vi[t].im * vi[t].im;
+    wave_put(n2, 0.0, 0);
+    finish(1);
+    const double pre = sqrt(tot[0].re);
+    for (int pass = 0; pass < 2 && i > 0; ++pass) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+        if (j < i) {
+          double pr = 0.0, pim = 0.0;
+#pragma unroll
+          for (int t = 0; t < EPT; ++t) {
+            pr += v[j][t].re * vi[t].re + v[j][t].im * vi[t].im;
+            pim += v[j][t].re * vi[t].im - v[j][t].im * vi[t].re;
+          }
+          wave_put(pr, pim, j);
+        }
+      finish(i);
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+        if (j < i) {
+          const cd64 pj = tot[j];
+#pragma unroll
+          for (int t = 0; t < EPT; ++t) {
+            vi[t].re -= pj.re * v[j][t].re - pj.im * v[j][t].im;
+            vi[t].im -= pj.re * v[j][t].im + pj.im * v[j][t].re;
+          }
+        }
+    }
+    n2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) n2 += vi[t].re * vi[t].re + vi[t].im * vi[t].im;
+    wave_put(n2, 0.0, 0);
+    finish(1);
+    double post = sqrt(tot[0].re);
+    if (!(post > 1e-10 * pre) || pre == 0.0) {
+      if (threadIdx.x == 0) atomicOr(breakdown, 1);
+      post = post > 0.0 ? post : 1.0;
+    }
+    const double inv = 1.0 / post;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j == i)
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) v[j][t] = mkc(vi[t].re * inv, vi[t].im * inv);
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int t = 0; t < EPT; ++t)
+      if (ok[t]) vecs[j * vs + q[t]] = v[j][t];
+}
+
 // Column fields of P: col_b(x)_k = P_{b mod nv}(x)_k on chirality half b / nv,
 // zero on the other half.  out [NB][layout].  grid (sites, NB).
 __global__ void k_prolongator_columns(const cd64* __restrict__ P, FieldLayout lay, int nv, cd64* __restrict__ out) {
@@ -345,9 +458,33 @@ void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, Fiel
 INST_TR(double)
 INST_TR(float)
 
+template <int NV>
+static bool orth_reg(int ept, cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int* breakdown,
+                     hipStream_t st) {
+  const dim3 g((unsigned)Vc, 2), b(512);
+  switch (ept) {
+    case 1: hipLaunchKernelGGL((k_block_orth_reg<NV, 1>), g, b, 0, st, vecs, lay, agg_sites, A, breakdown); return true;
+    case 2: hipLaunchKernelGGL((k_block_orth_reg<NV, 2>), g, b, 0, st, vecs, lay, agg_sites, A, breakdown); return true;
+    case 3: hipLaunchKernelGGL((k_block_orth_reg<NV, 3>), g, b, 0, st, vecs, lay, agg_sites, A, breakdown); return true;
+    default: return false;
+  }
+}
+
 void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
                                  int* breakdown, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_orthonormalise, dim3(Vc, 2), dim3(kBlock), 0, st, vecs, lay, agg_sites, A, nv, breakdown);
+  const int ept = (A * (lay.ns / 2) + 511) / 512;
+  bool done = false;
+  switch (nv) {  // register-resident form for the common block sizes
+    case 4: done = orth_reg<4>(ept, vecs, lay, agg_sites, A, Vc, breakdown, st); break;
+    case 6: done = orth_reg<6>(ept, vecs, lay, agg_sites, A, Vc, breakdown, st); break;
+    case 8: done = orth_reg<8>(ept, vecs, lay, agg_sites, A, Vc, breakdown, st); break;
+    case 12: done = orth_reg<12>(ept, vecs, lay, agg_sites, A, Vc, breakdown, st); break;
+    case 16: done = ept <= 2 && orth_reg<16>(ept, vecs, lay, agg_sites, A, Vc, breakdown, st); break;
+    default: break;
+  }
+  if (!done)
+    hipLaunchKernelGGL(k_block_orthonormalise, dim3(Vc, 2), dim3(kBlock), 0, st, vecs, lay, agg_sites, A, nv,
+                       breakdown);
   WCMG_CHECK_LAUNCH();
 }
 
