@@ -673,15 +673,23 @@ void Context::galerkin(int l) {
   const LevelGeom& G = geo[l];
   CoarseOp& C = *cop[l];
   const long nn = G.n();
-  cd64* cols = buf<cd64>("gal_cols" + std::to_string(l), (long)T.nb * nn);
-  cd64* W = buf<cd64>("gal_W" + std::to_string(l), (long)T.nb * nn);
   WCMG_HIP(hipMemsetAsync(C.M64.p, 0, C.M64.bytes, stream));
-  launch_prolongator_columns(T.P64.as<cd64>(), G.lay, T.nv, cols, stream);
-  for (int d = 0; d <= 8; ++d) {
-    apply_op<double>(l, cols, W, T.nb, nullptr, 1 << d);
-    const int* nbr_d = d == 0 ? nullptr : G.nbr.as<int>() + (long)(d - 1) * G.V;
-    launch_galerkin_project(W, T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.coarse_of.as<int>(), nbr_d, T.A,
-                            T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+  if (l == 0) {
+    // fine level: the images of P's columns under each term are formed inside
+    // the projection (no intermediate fields)
+    for (int d = 0; d <= 8; ++d)
+      launch_galerkin_fused(T.P64.as<cd64>(), U64.as<cd64>(), clov64.as<double>(), G.nbr.as<int>(), G.V,
+                            T.agg_sites.as<int>(), T.coarse_of.as<int>(), T.A, T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+  } else {
+    cd64* cols = buf<cd64>("gal_cols" + std::to_string(l), (long)T.nb * nn);
+    cd64* W = buf<cd64>("gal_W" + std::to_string(l), (long)T.nb * nn);
+    launch_prolongator_columns(T.P64.as<cd64>(), G.lay, T.nv, cols, stream);
+    for (int d = 0; d <= 8; ++d) {
+      apply_op<double>(l, cols, W, T.nb, nullptr, 1 << d);
+      const int* nbr_d = d == 0 ? nullptr : G.nbr.as<int>() + (long)(d - 1) * G.V;
+      launch_galerkin_project(W, T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.coarse_of.as<int>(), nbr_d, T.A,
+                              T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+    }
   }
   C.invalidate();
   C.refresh(WCMG_F64, stream);

@@ -54,6 +54,11 @@ void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, Fiel
 void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
                                  int* breakdown, hipStream_t st);
 void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st);
+// level 0 Galerkin term d with the images of P's columns formed on the fly
+// (U, clov: packed FP64 links and (4 + m0) + C; nbr [8][V])
+void launch_galerkin_fused(const cd64* P, const cd64* U, const double* clov, const int* nbr, long V,
+                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, cd64* M,
+                           hipStream_t st);
 void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
                              const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
                              hipStream_t st);

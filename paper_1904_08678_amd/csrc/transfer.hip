@@ -11,7 +11,7 @@
 // half chi of vector i, orthonormalised aggregate by aggregate, is column
 // b = chi * nv + i of P (Sec. 2.2).  Chirality is implicit: nothing is stored
 // twice and no explicit zeros are kept.
-#include "kernels.h"
+#include "wilson_ops.h"
 
 namespace wcmg {
 
@@ -417,6 +417,139 @@ __global__ void __launch_bounds__(256) k_galerkin_project(const cd64* __restrict
   }
 }
 
+// Level 0 without the intermediate images: column (i, chi) of P is the
+// chirality-chi half of vector i, and its image under Mdir_d at site x is the
+// hop of that half-spinor from the d-neighbour (under Mdiag: the chirality-chi
+// block of (4 + m0) + C at x).  Per tile of TS sites the images of all NB
+// columns are formed in LDS for the components of the chirality being
+// projected, then projected as in k_galerkin_project.  FP64.
+namespace {
+__device__ inline void image_hop(int d, cd64 (&acc)[12], const cd64 (&p)[12], const cd64 (&u)[9]) {
+  switch (d) {
+    case 1: hop_core<double, 0, true>(acc, p, u); break;
+    case 2: hop_core<double, 0, false>(acc, p, u); break;
+    case 3: hop_core<double, 1, true>(acc, p, u); break;
+    case 4: hop_core<double, 1, false>(acc, p, u); break;
+    case 5: hop_core<double, 2, true>(acc, p, u); break;
+    case 6: hop_core<double, 2, false>(acc, p, u); break;
+    case 7: hop_core<double, 3, true>(acc, p, u); break;
+    default: hop_core<double, 3, false>(acc, p, u); break;
+  }
+}
+}  // namespace
+
+template <int NB, int AB, int BB>
+__global__ void __launch_bounds__(256) k_galerkin_fused(const cd64* __restrict__ P, const cd64* __restrict__ U,
+                                                         const double* __restrict__ clov, const int* __restrict__ nbr,
+                                                         long V, const int* __restrict__ agg_sites,
+                                                         const int* __restrict__ coarse_of, int A, int d,
+                                                         cd64* __restrict__ M) {
+  constexpr int nv = NB / 2;
+  constexpr int TS = 8, T = TS * 6;  // sites and rows per tile
+  constexpr int TPG = (nv / AB) * (NB / BB);
+  __shared__ cd64 Pt[T][nv], Wt[T][NB];
+  __shared__ cd64 res[2][nv][NB];
+  __shared__ unsigned char ext[TS];
+  const long c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ngroups = (int)blockDim.x / TPG;
+  const int grp = tid / TPG, q = tid - grp * TPG;
+  const bool active = grp < ngroups;
+  const int a0 = (q / (NB / BB)) * AB, b0 = (q % (NB / BB)) * BB;
+  const long vs = 12 * V;
+  for (int chi = 0; chi < 2; ++chi) {
+    cd64 acc[2][AB][BB];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int x = 0; x < AB; ++x)
+#pragma unroll
+        for (int y = 0; y < BB; ++y) acc[t][x][y] = mkc(0.0, 0.0);
+    for (int o0 = 0; o0 < A; o0 += TS) {
+      const int ns = min(TS, A - o0);
+      __syncthreads();
+      // rows of P for the components of chirality chi
+      for (int idx = tid; idx < ns * 6 * nv; idx += blockDim.x) {
+        const int ts = idx % ns, r2 = idx / ns, kk = r2 % 6, a = r2 / 6;
+        const long x = agg_sites[c * A + o0 + ts];
+        Pt[ts * 6 + kk][a] = P[a * vs + (long)(chi * 6 + kk) * V + x];
+      }
+      // images of the columns at the tile's sites
+      for (int item = tid; item < ns * NB; item += blockDim.x) {
+        const int ts = item % ns, b = item / ns;
+        const int cb = b / nv, i = b - cb * nv;
+        const long x = agg_sites[c * A + o0 + ts];
+        const cd64* Pi = P + i * vs;
+        cd64 img[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) img[k] = mkc(0.0, 0.0);
+        if (d == 0) {
+          if (cb == 0) clover_chirality<double, 0>(img, Pi, clov, V, x);
+          else clover_chirality<double, 1>(img, Pi, clov, V, x);
+        } else {
+          const long y = nbr[(long)(d - 1) * V + x];
+          const int mu = (d - 1) >> 1;
+          const long ls = (d & 1) ? x : y;
+          cd64 p[12], u[9];
+#pragma unroll
+          for (int k = 0; k < 12; ++k) p[k] = (k / 6 == cb) ? Pi[(long)k * V + y] : mkc(0.0, 0.0);
+#pragma unroll
+          for (int e = 0; e < 9; ++e) u[e] = U[(long)(mu * 9 + e) * V + ls];
+          image_hop(d, img, p, u);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) {
+          // select component chi * 6 + kk without dynamic register indexing
+          cd64 v = img[kk];
+          if (chi == 1) v = img[6 + kk];
+          Wt[ts * 6 + kk][b] = v;
+        }
+        if (b == 0) ext[ts] = (d != 0 && coarse_of[nbr[(long)(d - 1) * V + x]] != c) ? 1 : 0;
+      }
+      __syncthreads();
+      if (active) {
+        for (int rr = grp; rr < ns * 6; rr += ngroups) {
+          cd64 p[AB], w[BB];
+#pragma unroll
+          for (int x = 0; x < AB; ++x) p[x] = Pt[rr][a0 + x];
+#pragma unroll
+          for (int y = 0; y < BB; ++y) w[y] = Wt[rr][b0 + y];
+          if (ext[rr / 6]) {
+#pragma unroll
+            for (int x = 0; x < AB; ++x)
+#pragma unroll
+              for (int y = 0; y < BB; ++y) cfmac(acc[1][x][y], p[x], w[y]);
+          } else {
+#pragma unroll
+            for (int x = 0; x < AB; ++x)
+#pragma unroll
+              for (int y = 0; y < BB; ++y) cfmac(acc[0][x][y], p[x], w[y]);
+          }
+        }
+      }
+    }
+    for (int g = 0; g < ngroups; ++g) {
+      __syncthreads();
+      if (active && grp == g)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int x = 0; x < AB; ++x)
+#pragma unroll
+            for (int y = 0; y < BB; ++y)
+              res[t][a0 + x][b0 + y] = g == 0 ? acc[t][x][y] : cadd(res[t][a0 + x][b0 + y], acc[t][x][y]);
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * nv * NB; e += blockDim.x) {
+      const int t = e / (nv * NB), ab = e - t * nv * NB, a = ab / NB, b = ab - a * NB;
+      if (t == 1 && d == 0) continue;
+      const int dd = t == 0 ? 0 : d;
+      cd64* m = M + ((c * 9 + dd) * NB + chi * nv + a) * NB + b;
+      *m = cadd(*m, res[t][a][b]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 #define NB_SWITCH(nb, ...)                                     \
   switch (nb) {                                                 \
@@ -490,6 +623,14 @@ void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sit
 
 void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st) {
   hipLaunchKernelGGL(k_prolongator_columns, dim3(nblocks(lay.V), 2 * nv), dim3(kBlock), 0, st, P, lay, nv, out);
+  WCMG_CHECK_LAUNCH();
+}
+
+void launch_galerkin_fused(const cd64* P, const cd64* U, const double* clov, const int* nbr, long V,
+                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, cd64* M,
+                           hipStream_t st) {
+  NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_fused<NBc, (NBc / 2) % 2 == 0 ? 2 : 1, NBc % 4 == 0 ? 4 : 2>),
+                                    dim3(Vc), dim3(kBlock), 0, st, P, U, clov, nbr, V, agg_sites, coarse_of, A, d, M));
   WCMG_CHECK_LAUNCH();
 }
 
