@@ -114,11 +114,11 @@ def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int 
 
 
 TRAFFIC_SOURCES = {
-    "dslash_f32": ("paper_1904_08678_amd/csrc/wilson.hip",),
+    "dslash_f32": ("paper_1904_08678_amd/csrc/wilson.hip", "paper_1904_08678_amd/csrc/wilson_ops.h"),
     "coarse_apply_f32_large": ("paper_1904_08678_amd/csrc/coarse.hip", "paper_1904_08678_amd/csrc/coarse_common.h"),
     "coarse_mfma_f32_12rhs": ("paper_1904_08678_amd/csrc/coarse_mfma.hip",),
     "coarse_mfma_bf16_12rhs": ("paper_1904_08678_amd/csrc/coarse_mfma.hip",),
-    "dslash_f32_mrhs_12rhs": ("paper_1904_08678_amd/csrc/wilson.hip",),
+    "dslash_f32_mrhs_12rhs": ("paper_1904_08678_amd/csrc/wilson.hip", "paper_1904_08678_amd/csrc/wilson_ops.h"),
 }
 
 
@@ -182,7 +182,18 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
         byts = (9.0 * nb * nb * sb + 2.0 * nb * sv) * Vc
         out[name] = {"ms": ms, "GB_s": byts / ms / 1e6, "frac": byts / ms / 1e6 / HBM_PEAK_GBS,
                      "bytes_per_launch": byts}
-        del op, x, y
+        del op
+        # five-point storage: Mdiag and the forward blocks (the timing does not
+        # depend on the values; the backward blocks of `blocks` are ignored)
+        op5 = w.CoarseOperator(dims, nb, store)
+        op5.set_kernel(3)
+        op5.set(blocks)
+        op5.time(x, y, reps=3)
+        ms5 = op5.time(x, y, reps=reps)
+        b5 = (5.0 * nb * nb * sb + 2.0 * nb * sv) * Vc
+        out[name]["five_point"] = {"ms": ms5, "GB_s": b5 / ms5 / 1e6, "frac": b5 / ms5 / 1e6 / HBM_PEAK_GBS,
+                                   "bytes_per_launch": b5, "speedup_vs_nine": ms / ms5}
+        del op5, x, y
         torch.cuda.synchronize()
     # twelve right-hand sides in one launch: matrix-core kernel against the per-row kernel
     batched = {}

@@ -90,7 +90,11 @@ typedef struct {
   int32_t cycle_prec;      /* WCMG_F64 or WCMG_F32: arithmetic of the preconditioner */
   int32_t coarse_store_prec; /* storage of coarse blocks inside the cycle: F64, F32 or BF16 */
   int32_t setup_prec;      /* arithmetic of the relaxation in the setup: F64 or F32 */
-  int32_t reserved[5];
+  int32_t coarse_points;   /* blocks stored per coarse site: 9 (or 0) = Mdiag and all eight hops; 5 = Mdiag and
+                              the forward hops, the backward hops applied as sigma3-conjugated adjoints of the
+                              neighbours' forward blocks (Sec. 4: five independent stencil points; needs
+                              Nb in {8, 12, 16, 24, 32}, else nine are stored) */
+  int32_t reserved[4];
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;
@@ -295,7 +299,14 @@ int wcmg_coarse_set(wcmg_coarse* op, const void* blocks, int src_prec);
 int wcmg_coarse_apply(wcmg_coarse* op, const void* in, void* out, int nrhs);
 /* Kernel choice for wcmg_coarse_apply: 0 automatic (matrix cores from 4
  * right-hand sides on), 1 per-row vector kernel, 2 matrix cores (FP32/BF16
- * storage, Nb in {8, 16, 24, 32, 40}).  WCMG_ERR_ARG when unsupported. */
+ * storage, Nb in {8, 16, 24, 32, 40}), 3 per-row kernel on five-point
+ * storage (Nb in {8, 12, 16, 24, 32}): only Mdiag and the forward blocks of
+ * wcmg_coarse_set's input are kept and the backward hops are applied as
+ * Mdir_{-mu}(c) = s Mdir_{+mu}(c - mu)^dag s (s = +1 on the first Nb/2
+ * components, -1 on the rest), which is the operator itself when it is
+ * sigma3-hermitian as every Galerkin coarse operator of gamma5-hermitian D is
+ * (Sec. 2.2, Sec. 4).  Switching to or from 3 must precede wcmg_coarse_set
+ * (WCMG_ERR_STATE otherwise).  WCMG_ERR_ARG when unsupported. */
 int wcmg_coarse_set_kernel(wcmg_coarse* op, int kernel);
 /* Time `reps` back-to-back applies between HIP events on the op's stream;
  * *avg_ms receives the mean launch duration. */

@@ -245,7 +245,7 @@ int wcmg_apply_D(wcmg_ctx* ctx, int level, const void* in, void* out, int nrhs, 
       }
     } else {
       CoarseOp& C = *c.cop[level - 1];
-      require(C.fresh[WCMG_F64], WCMG_ERR_STATE, "coarse operator not built");
+      require(C.built(WCMG_F64), WCMG_ERR_STATE, "coarse operator not built");
       if (prec != WCMG_F64) C.refresh(prec, c.stream);
       C.apply(prec, in, out, 0x1ff, 0, nrhs, nullptr, c.stream);
     }
@@ -674,8 +674,9 @@ int wcmg_coarse_set(wcmg_coarse* h, const void* blocks, int src_prec) {
     else
       launch_c64_to_c128((const cf32*)blocks, o.op.M64.as<cd64>(), n, o.stream);
     o.op.invalidate();
+    o.op.five = o.kernel == 3;
     o.op.refresh(o.store, o.stream);
-    if (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb)) o.op.refresh_mfma(o.store, o.stream);
+    if (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb) && o.kernel != 3) o.op.refresh_mfma(o.store, o.stream);
     WCMG_HIP(hipStreamSynchronize(o.stream));
     // the canonical master is only needed to build the device layout
     o.op.M64.release();
@@ -692,9 +693,14 @@ int wcmg_coarse_apply(wcmg_coarse* h, const void* in, void* out, int nrhs) {
 
 int wcmg_coarse_set_kernel(wcmg_coarse* h, int kernel) {
   return guarded_c(h, [&](wcmg_coarse& o) {
-    require(kernel >= 0 && kernel <= 2, WCMG_ERR_ARG, "kernel must be 0 (auto), 1 (vector) or 2 (matrix cores)");
+    require(kernel >= 0 && kernel <= 3, WCMG_ERR_ARG,
+            "kernel must be 0 (auto), 1 (vector), 2 (matrix cores) or 3 (five-point vector)");
     require(kernel != 2 || (o.store != WCMG_F64 && mfma_supported_nb(o.op.nb)), WCMG_ERR_ARG,
             "matrix-core kernel needs FP32/BF16 storage and Nb in {8,16,24,32,40}");
+    require(kernel != 3 || five_point_supported(o.op.nb), WCMG_ERR_ARG,
+            "five-point kernel needs Nb in {8,12,16,24,32}");
+    require((kernel == 3) == (o.kernel == 3) || !o.op.built(o.store), WCMG_ERR_STATE,
+            "switch to or from the five-point kernel before wcmg_coarse_set");
     o.kernel = kernel;
   });
 }

@@ -7,7 +7,7 @@
 //   3. the same for the second Gram-Schmidt pass (CGS2), partials of |w|^2;
 //   4. one workgroup reduces |w|^2 and applies the Givens rotations.
 // Scalars and control words stay on the device; state words as in blas.hip.
-#include "coarse_common.h"
+#include "coarse5.h"
 
 namespace wcmg {
 
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_cg_cycle_start(int* st, cd64* S, int m,
 }
 
 // Step 1: w = A u / |u|, v_j = u / |u|, partials of <v_i, w> for i <= j.
-template <int P, int NB, int S>
+template <int P, int NB, int S, bool FIVE>
 __global__ void __launch_bounds__(256) k_cg_apply(const Chunk16* __restrict__ blk, const int* __restrict__ nbr,
                                                    long Vc, const cplx<typename BlkTraits<P>::R>* __restrict__ u,
                                                    const cd64* __restrict__ unrm2,
@@ -117,12 +117,15 @@ __global__ void __launch_bounds__(256) k_cg_apply(const Chunk16* __restrict__ bl
   if (!*run) return;
   __shared__ cd64 lds[4 * kMaxM1];
   const long n = Vc * NB;
-  const long g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const long xb = xcd_block(blockIdx.x, gridDim.x);
+  const long g = xb * blockDim.x + threadIdx.x;
   const long t = g / S;
   const int sub = (int)(g % S);
   const bool valid = t < n;
   const double inv = 1.0 / sqrt(unrm2->re);
-  cplx<R> acc = coarse_row<P, NB, S>(blk, u, nbr, Vc, NB, t, sub, 0x1ff, valid);
+  cplx<R> acc;
+  if constexpr (FIVE) acc = coarse_row5<P, NB, S>(blk, u, nbr, Vc, xb * (blockDim.x / S), t, sub, valid);
+  else acc = coarse_row<P, NB, S>(blk, u, nbr, Vc, NB, t, sub, 0x1ff, valid);
   const bool own = valid && sub == 0;
   cplx<R> vj = mkc((R)0, (R)0), wv = mkc((R)0, (R)0);
   if (own) {
@@ -270,29 +273,34 @@ void launch_cg_cycle_start(int* stw, cd64* S, int m, const cd64* part, int G, in
 }
 
 template <int P, int NB, int S>
-static void cg_apply_t(const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2, void* V, int j,
-                       void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
+static void cg_apply_t(bool five, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
+                       void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
   typedef typename BlkTraits<P>::R R;
-  WCMG_LAUNCH((k_cg_apply<P, NB, S>), dim3(nblocks(Vc * NB * S)), dim3(kBlock), 0, st, (const Chunk16*)blk, nbr, Vc,
-              (const cplx<R>*)u, unrm2, (cplx<R>*)V, j, (cplx<R>*)wout, part, m1, run);
+  if (five)
+    WCMG_LAUNCH((k_cg_apply<P, NB, S, true>), dim3(nblocks(Vc * NB * S)), dim3(kBlock), 0, st, (const Chunk16*)blk,
+                nbr, Vc, (const cplx<R>*)u, unrm2, (cplx<R>*)V, j, (cplx<R>*)wout, part, m1, run);
+  else
+    WCMG_LAUNCH((k_cg_apply<P, NB, S, false>), dim3(nblocks(Vc * NB * S)), dim3(kBlock), 0, st, (const Chunk16*)blk,
+                nbr, Vc, (const cplx<R>*)u, unrm2, (cplx<R>*)V, j, (cplx<R>*)wout, part, m1, run);
 }
 template <int P, int NB>
-static void cg_apply_s(int S, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2, void* V,
-                       int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
-  if (S == 1) cg_apply_t<P, NB, 1>(blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
-  else if (S == 2) cg_apply_t<P, NB, 2>(blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
-  else if (S == 4) cg_apply_t<P, NB, 4>(blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
-  else cg_apply_t<P, NB, 8>(blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+static void cg_apply_s(int S, bool five, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
+                       void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
+  if (S == 1) cg_apply_t<P, NB, 1>(five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  else if (S == 2) cg_apply_t<P, NB, 2>(five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  else if (S == 4) cg_apply_t<P, NB, 4>(five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  else cg_apply_t<P, NB, 8>(five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
 }
 template <int P>
-static void cg_apply_nb(int nb, int S, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
-                        void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
+static void cg_apply_nb(int nb, int S, bool five, const void* blk, const int* nbr, long Vc, const void* u,
+                        const cd64* unrm2, void* V, int j, void* wout, cd64* part, int m1, const int* run,
+                        hipStream_t st) {
   switch (nb) {
-    case 8: cg_apply_s<P, 8>(S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
-    case 12: cg_apply_s<P, 12>(S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
-    case 16: cg_apply_s<P, 16>(S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
-    case 24: cg_apply_s<P, 24>(S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
-    case 32: cg_apply_s<P, 32>(S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
+    case 8: cg_apply_s<P, 8>(S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
+    case 12: cg_apply_s<P, 12>(S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
+    case 16: cg_apply_s<P, 16>(S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
+    case 24: cg_apply_s<P, 24>(S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
+    case 32: cg_apply_s<P, 32>(S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st); break;
     default: throw Error(WCMG_ERR_ARG, "fused coarse GMRES: unsupported Nb");
   }
 }
@@ -301,11 +309,11 @@ bool cg_fused_supported(int nb) { return nb == 8 || nb == 12 || nb == 16 || nb =
 
 // Returns the number of workgroups of the apply step (the partial count).
 int launch_cg_apply(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
-                    void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st) {
+                    void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st, bool five) {
   const int S = coarse_split(Vc * nb);
-  if (prec == WCMG_F64) cg_apply_nb<WCMG_F64>(nb, S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
-  else if (prec == WCMG_F32) cg_apply_nb<WCMG_F32>(nb, S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
-  else cg_apply_nb<WCMG_BF16>(nb, S, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  if (prec == WCMG_F64) cg_apply_nb<WCMG_F64>(nb, S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  else if (prec == WCMG_F32) cg_apply_nb<WCMG_F32>(nb, S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
+  else cg_apply_nb<WCMG_BF16>(nb, S, five, blk, nbr, Vc, u, unrm2, V, j, wout, part, m1, run, st);
   WCMG_CHECK_LAUNCH();
   return (int)nblocks(Vc * nb * S);
 }

@@ -69,11 +69,20 @@ struct CoarseOp {
   bool fresh[3] = {false, false, false};
   DevBuf mfma[3];  // fragment-ordered blocks for the matrix-core kernel (F32, BF16)
   bool mfma_fresh[3] = {false, false, false};
+  // five-point storage (Mdiag and the forward blocks): full applies read it,
+  // the nine-block layout is then built only for single-term applies
+  bool five = false;
+  DevBuf dev5[3];
+  bool fresh5[3] = {false, false, false};
+  DevBuf tmp5;  // backward contributions of the owner-computes five-point apply
   void init_geometry(const int Lc[4], int nb_, hipStream_t st);
   void refresh(int prec, hipStream_t st);  // canonical -> device layout of prec
+  void refresh9(int prec, hipStream_t st);
   void refresh_mfma(int prec, hipStream_t st);
+  bool built(int prec) const { return fresh[prec] || fresh5[prec]; }
+  bool uses_five() const { return five && five_point_supported(nb); }
   void invalidate() {
-    for (int q = 0; q < 3; ++q) fresh[q] = mfma_fresh[q] = false;
+    for (int q = 0; q < 3; ++q) fresh[q] = mfma_fresh[q] = fresh5[q] = false;
   }
   // nrhs right-hand sides (RHS-major); kernel: 0 auto, 1 per-row vector kernel, 2 matrix cores
   void apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,

@@ -107,6 +107,17 @@ void CoarseOp::init_geometry(const int Lc[4], int nb_, hipStream_t) {
 }
 
 void CoarseOp::refresh(int prec, hipStream_t st) {
+  if (!uses_five()) {
+    refresh9(prec, st);
+    return;
+  }
+  if (fresh5[prec]) return;
+  dev5[prec].alloc(device_block5_bytes(V, nb, prec));
+  launch_blocks_to_device5(M64.as<cd64>(), V, nb, prec, dev5[prec].p, st);
+  fresh5[prec] = true;
+}
+
+void CoarseOp::refresh9(int prec, hipStream_t st) {
   if (fresh[prec]) return;
   dev[prec].alloc(device_block_bytes(V, nb, prec));
   launch_blocks_to_device(M64.as<cd64>(), V, nb, prec, dev[prec].p, st);
@@ -140,7 +151,20 @@ void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int ke
 
 void CoarseOp::apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run,
                      hipStream_t st, int run_stride) {
-  require(fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  require(built(prec), WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  if (fresh5[prec] && dmask == 0x1ff) {
+    void* tmp = nullptr;
+    if (coarse5_uses_owner(V, nb, nrhs)) {
+      // grown only (a captured apply reuses what its eager warm-up allocated)
+      const size_t need = 4 * (size_t)nrhs * V * nb * cbytes(prec);
+      if (tmp5.bytes < need) tmp5.alloc(need);
+      tmp = tmp5.p;
+    }
+    launch_coarse_apply5(prec, dev5[prec].p, in, out, tmp, nbr.as<int>(), V, nb, accumulate, nrhs, run, st,
+                         run_stride);
+    return;
+  }
+  refresh9(prec, st);
   launch_coarse_apply(prec, dev[prec].p, in, out, nbr.as<int>(), V, nb, dmask, accumulate, nrhs, run, st,
                       run_stride);
 }
@@ -153,6 +177,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   require(p.cycle_prec == WCMG_F64 || p.cycle_prec == WCMG_F32, WCMG_ERR_ARG, "cycle_prec must be F64 or F32");
   require(p.setup_prec == WCMG_F64 || p.setup_prec == WCMG_F32, WCMG_ERR_ARG, "setup_prec must be F64 or F32");
   require(p.coarse_store_prec >= 0 && p.coarse_store_prec <= 2, WCMG_ERR_ARG, "bad coarse_store_prec");
+  require(p.coarse_points == 0 || p.coarse_points == 5 || p.coarse_points == 9, WCMG_ERR_ARG,
+          "coarse_points must be 5 or 9");
   require(p.outer_restart >= 1 && p.outer_restart <= 40 && p.coarse_restart >= 1 && p.coarse_restart <= 40 &&
               p.kcycle_maxit >= 1 && p.kcycle_maxit <= 40,
           WCMG_ERR_ARG, "restart lengths must lie in 1..40");
@@ -217,6 +243,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
     for (long s = 0; s < G.V; ++s) G.perm[s] = (int)s;
     cop.emplace_back(new CoarseOp());
     cop.back()->init_geometry(G.L, G.ns, stream);
+    cop.back()->five = p.coarse_points == 5;
     // coarse level vectors and operator share the lexicographic neighbour table
   }
   // transfers
@@ -541,8 +568,9 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
   int* st = G.st.as<int>();
   int* run = st;
   int* live = st + 1;
-  const void* blk = C.dev[prec].p;
-  require(C.fresh[prec], WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  require(C.built(prec), WCMG_ERR_STATE, "coarse operator not built in the requested precision");
+  const bool five = C.fresh5[prec];
+  const void* blk = five ? C.dev5[prec].p : C.dev[prec].p;
   const int fixed = p.coarse_fixed_iters;
   const int limit = fixed > 0 ? fixed : p.coarse_maxit;
   const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
@@ -568,7 +596,8 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
       const cd64* unrm2 = j == 0 ? misc + 1 : misc + 3;
       cplx<R>* w = wb[(j + 1) & 1];
       prof.begin_kernel(fam);
-      const int G1 = launch_cg_apply(prec, nb, blk, C.nbr.as<int>(), C.V, u, unrm2, V, j, w, partA, m1, run, stream);
+      const int G1 =
+          launch_cg_apply(prec, nb, blk, C.nbr.as<int>(), C.V, u, unrm2, V, j, w, partA, m1, run, stream, five);
       prof.end(fam, stream);
       launch_cg_orth<R>(V, j, w, nn, partA, G1, S, m, 0, partB, run, stream);
       launch_cg_orth<R>(V, j, w, nn, partB, (int)G2, S, m, 1, partC, run, stream);
@@ -664,9 +693,11 @@ void Context::rebuild(int l) {
   T.built = true;
 }
 
-// Galerkin coarse operator (Sec. 2.1 CoarsenOperator): for each term of the
-// level operator (Mdiag and the eight Mdir) apply it to every column of P and
-// project on P aggregate by aggregate.
+// Galerkin coarse operator (Sec. 2.1 CoarsenOperator): Mdiag and the four
+// forward terms Mdir_{+mu} of the level operator are applied to every column
+// of P and projected on P aggregate by aggregate; the four backward terms
+// follow from gamma5-hermiticity (Sec. 4: five of the nine stencil points are
+// independent), which halves the hop work.
 void Context::galerkin(int l) {
   auto t0 = std::chrono::steady_clock::now();
   Transfer& T = tr[l];
@@ -677,20 +708,22 @@ void Context::galerkin(int l) {
   if (l == 0) {
     // fine level: the images of P's columns under each term are formed inside
     // the projection (no intermediate fields)
-    for (int d = 0; d <= 8; ++d)
+    for (int d = 0; d <= 7; d += d == 0 ? 1 : 2)
       launch_galerkin_fused(T.P64.as<cd64>(), U64.as<cd64>(), clov64.as<double>(), G.nbr.as<int>(), G.V,
-                            T.agg_sites.as<int>(), T.coarse_of.as<int>(), T.A, T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+                            T.agg_sites.as<int>(), T.coarse_of.as<int>(), T.A, T.Vc, T.nb, d, d == 0 ? 0 : d + 1,
+                            C.M64.as<cd64>(), stream);
   } else {
     cd64* cols = buf<cd64>("gal_cols" + std::to_string(l), (long)T.nb * nn);
     cd64* W = buf<cd64>("gal_W" + std::to_string(l), (long)T.nb * nn);
     launch_prolongator_columns(T.P64.as<cd64>(), G.lay, T.nv, cols, stream);
-    for (int d = 0; d <= 8; ++d) {
+    for (int d = 0; d <= 7; d += d == 0 ? 1 : 2) {
       apply_op<double>(l, cols, W, T.nb, nullptr, 1 << d);
       const int* nbr_d = d == 0 ? nullptr : G.nbr.as<int>() + (long)(d - 1) * G.V;
       launch_galerkin_project(W, T.P64.as<cd64>(), G.lay, T.agg_sites.as<int>(), T.coarse_of.as<int>(), nbr_d, T.A,
-                              T.Vc, T.nb, d, C.M64.as<cd64>(), stream);
+                              T.Vc, T.nb, d, d == 0 ? 0 : d + 1, C.M64.as<cd64>(), stream);
     }
   }
+  launch_galerkin_mirror(C.M64.as<cd64>(), C.nbr.as<int>(), T.Vc, T.nb, stream);
   C.invalidate();
   C.refresh(WCMG_F64, stream);
   if (p.cycle_prec == WCMG_F32 || p.setup_prec == WCMG_F32) C.refresh(store_prec_for(l + 1, true), stream);

@@ -36,6 +36,17 @@ void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st);
 void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
                          int dmask, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
 
+// ---- coarse operator from five-point storage (coarse5.hip): Mdiag and the
+// forward blocks only, the backward hops from sigma3-hermiticity
+bool five_point_supported(int nb);
+size_t device_block5_bytes(long Vc, int nb, int prec);
+void launch_blocks_to_device5(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
+// tmp: 4 * nrhs * Vc * Nb complex of the vector precision, used when
+// coarse5_uses_owner(Vc, nb, nrhs) (may be null otherwise)
+bool coarse5_uses_owner(long Vc, int nb, int nrhs);
+void launch_coarse_apply5(int prec, const void* blk, const void* in, void* out, void* tmp, const int* nbr, long Vc,
+                          int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
+
 // ---- batched coarse apply on the matrix cores (coarse_mfma.hip)
 bool mfma_supported_nb(int nb);
 size_t mfma_block_bytes(long Vc, int nb, int prec);
@@ -56,12 +67,17 @@ void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sit
 void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st);
 // level 0 Galerkin term d with the images of P's columns formed on the fly
 // (U, clov: packed FP64 links and (4 + m0) + C; nbr [8][V])
+// (dint: the block slot that contributions of hops inside an aggregate go to;
+// 0 = Mdiag)
 void launch_galerkin_fused(const cd64* P, const cd64* U, const double* clov, const int* nbr, long V,
-                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, cd64* M,
-                           hipStream_t st);
+                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, int dint,
+                           cd64* M, hipStream_t st);
 void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
-                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
-                             hipStream_t st);
+                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, int dint,
+                             cd64* M, hipStream_t st);
+// backward terms from the forward ones (and the -mu slots' inside-aggregate
+// parts folded into Mdiag); nbr_c: coarse neighbour table [8][Vc]
+void launch_galerkin_mirror(cd64* M, const int* nbr_c, long Vc, int nb, hipStream_t st);
 
 // ---- vector algebra and solver control (blas.hip)
 template <typename R>
@@ -106,8 +122,9 @@ template <typename R>
 void launch_cg_norm_partial(const cplx<R>* r, long n, cd64* part, int m1, const int* run, hipStream_t st);
 void launch_cg_cycle_start(int* stw, cd64* S, int m, const cd64* part, int G, int first, double tol, int limit,
                            int fixed, hipStream_t st);
+// five: blk holds five-point storage
 int launch_cg_apply(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* u, const cd64* unrm2,
-                    void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st);
+                    void* V, int j, void* wout, cd64* part, int m1, const int* run, hipStream_t st, bool five = false);
 template <typename R>
 void launch_cg_orth(cplx<R>* V, int j, cplx<R>* w, long n, const cd64* part_in, int G_in, cd64* S, int m, int pass,
                     cd64* part_out, const int* run, hipStream_t st);

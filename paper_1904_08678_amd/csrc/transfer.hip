@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) k_galerkin_project(const cd64* __restrict
                                                            FieldLayout lay, const int* __restrict__ agg_sites,
                                                            const int* __restrict__ coarse_of,
                                                            const int* __restrict__ nbr_d, int A, long Vc, int d,
-                                                           cd64* __restrict__ M) {
+                                                           int dint, cd64* __restrict__ M) {
   constexpr int nv = NB / 2;
   constexpr int T = 32;  // rows per tile
   constexpr int TPG = (nv / AB) * (NB / BB);  // threads per row group
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(256) k_galerkin_project(const cd64* __restrict
     for (int e = tid; e < 2 * nv * NB; e += blockDim.x) {
       const int t = e / (nv * NB), ab = e - t * nv * NB, a = ab / NB, b = ab - a * NB;
       if (t == 1 && d == 0) continue;
-      const int dd = t == 0 ? 0 : d;
+      const int dd = t == 0 ? dint : d;
       cd64* m = M + ((c * 9 + dd) * NB + chi * nv + a) * NB + b;
       *m = cadd(*m, res[t][a][b]);
     }
@@ -442,7 +442,7 @@ template <int NB, int AB, int BB>
 __global__ void __launch_bounds__(256) k_galerkin_fused(const cd64* __restrict__ P, const cd64* __restrict__ U,
                                                          const double* __restrict__ clov, const int* __restrict__ nbr,
                                                          long V, const int* __restrict__ agg_sites,
-                                                         const int* __restrict__ coarse_of, int A, int d,
+                                                         const int* __restrict__ coarse_of, int A, int d, int dint,
                                                          cd64* __restrict__ M) {
   constexpr int nv = NB / 2;
   constexpr int TS = 8, T = TS * 6;  // sites and rows per tile
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(256) k_galerkin_fused(const cd64* __restrict__
     for (int e = tid; e < 2 * nv * NB; e += blockDim.x) {
       const int t = e / (nv * NB), ab = e - t * nv * NB, a = ab / NB, b = ab - a * NB;
       if (t == 1 && d == 0) continue;
-      const int dd = t == 0 ? 0 : d;
+      const int dd = t == 0 ? dint : d;
       cd64* m = M + ((c * 9 + dd) * NB + chi * nv + a) * NB + b;
       *m = cadd(*m, res[t][a][b]);
     }
@@ -627,19 +627,68 @@ void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* ou
 }
 
 void launch_galerkin_fused(const cd64* P, const cd64* U, const double* clov, const int* nbr, long V,
-                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, cd64* M,
-                           hipStream_t st) {
+                           const int* agg_sites, const int* coarse_of, int A, long Vc, int nb, int d, int dint,
+                           cd64* M, hipStream_t st) {
   NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_fused<NBc, (NBc / 2) % 2 == 0 ? 2 : 1, NBc % 4 == 0 ? 4 : 2>),
-                                    dim3(Vc), dim3(kBlock), 0, st, P, U, clov, nbr, V, agg_sites, coarse_of, A, d, M));
+                                    dim3(Vc), dim3(kBlock), 0, st, P, U, clov, nbr, V, agg_sites, coarse_of, A, d,
+                                    dint, M));
   WCMG_CHECK_LAUNCH();
 }
 
 void launch_galerkin_project(const cd64* W, const cd64* P, FieldLayout lay, const int* agg_sites,
-                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, cd64* M,
-                             hipStream_t st) {
+                             const int* coarse_of, const int* nbr_d, int A, long Vc, int nb, int d, int dint,
+                             cd64* M, hipStream_t st) {
   NB_SWITCH(nb, hipLaunchKernelGGL((k_galerkin_project<NBc, (NBc / 2) % 2 == 0 ? 2 : 1, NBc % 4 == 0 ? 4 : 2>),
                                     dim3(Vc), dim3(kBlock), 0, st, W, P, lay, agg_sites, coarse_of, nbr_d, A, Vc, d,
-                                    M));
+                                    dint, M));
+  WCMG_CHECK_LAUNCH();
+}
+
+// The backward terms from the forward ones.  The level operator is
+// gamma5-hermitian term by term (the -mu hop is the gamma5-conjugated adjoint
+// of the +mu hop) and P preserves chirality, so with s = sigma3 = +1 on the
+// first Nb/2 coarse components and -1 on the rest (Sec. 2.2),
+//   Mdir_{-mu}(c) = s Mdir_{+mu}(c - mu)^dag s,
+// and the part of Mdiag that -mu hops inside an aggregate contribute is
+// s X_mu^dag s, X_mu being the part from the +mu hops inside it.  On entry the
+// -mu slot of site c holds X_mu; the first kernel adds X_mu + s X_mu^dag s to
+// Mdiag (mu in order), the second overwrites the -mu slots.  FP64.
+__global__ void k_mirror_diag(cd64* __restrict__ M, long Vc, int nb) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long per = (long)nb * nb;
+  if (e >= Vc * per) return;
+  const long c = e / per;
+  const int i = (int)((e % per) / nb), j = (int)(e % nb);
+  const double sij = ((i < nb / 2) == (j < nb / 2)) ? 1.0 : -1.0;
+  cd64* Mc = M + c * 9 * per;
+  cd64 acc = Mc[(long)i * nb + j];
+  for (int mu = 0; mu < 4; ++mu) {
+    const cd64* X = Mc + (2 * mu + 2) * per;
+    const cd64 a = X[(long)i * nb + j], b = X[(long)j * nb + i];
+    acc = cadd(acc, a);
+    acc = cadd(acc, mkc(sij * b.re, -sij * b.im));
+  }
+  Mc[(long)i * nb + j] = acc;
+}
+
+__global__ void k_mirror_hops(cd64* __restrict__ M, const int* __restrict__ nbr, long Vc, int nb) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long per = (long)nb * nb;
+  if (e >= 4 * Vc * per) return;
+  const int mu = (int)(e / (Vc * per));
+  const long r = e % (Vc * per);
+  const long c = r / per;
+  const int i = (int)((r % per) / nb), j = (int)(r % nb);
+  const double sij = ((i < nb / 2) == (j < nb / 2)) ? 1.0 : -1.0;
+  const long cm = nbr[(long)(2 * mu + 1) * Vc + c];  // c - mu
+  const cd64 b = M[(cm * 9 + 2 * mu + 1) * per + (long)j * nb + i];
+  M[(c * 9 + 2 * mu + 2) * per + (long)i * nb + j] = mkc(sij * b.re, -sij * b.im);
+}
+
+void launch_galerkin_mirror(cd64* M, const int* nbr_c, long Vc, int nb, hipStream_t st) {
+  const long per = (long)nb * nb;
+  hipLaunchKernelGGL(k_mirror_diag, dim3(nblocks(Vc * per)), dim3(kBlock), 0, st, M, Vc, nb);
+  hipLaunchKernelGGL(k_mirror_hops, dim3(nblocks(4 * Vc * per)), dim3(kBlock), 0, st, M, nbr_c, Vc, nb);
   WCMG_CHECK_LAUNCH();
 }
 

@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("coarse_tol", C.c_double), ("kcycle", C.c_int32), ("kcycle_maxit", C.c_int32), ("kcycle_tol", C.c_double),
         ("outer_restart", C.c_int32), ("outer_maxit", C.c_int32), ("outer_tol", C.c_double),
         ("cycle_prec", C.c_int32), ("coarse_store_prec", C.c_int32), ("setup_prec", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("coarse_points", C.c_int32), ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -404,7 +404,9 @@ class CoarseOperator:
         self._chk(lib().wcmg_coarse_set(self.h, _ptr(blocks), prec))
 
     def set_kernel(self, kernel: int):
-        """0 automatic, 1 per-row vector kernel, 2 matrix cores."""
+        """0 automatic, 1 per-row vector kernel, 2 matrix cores, 3 per-row
+        kernel on five-point storage (set before `set`; the blocks must be
+        sigma3-hermitian, as every Galerkin coarse operator is)."""
         self._chk(lib().wcmg_coarse_set_kernel(self.h, int(kernel)))
 
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -57,6 +57,24 @@ def dense_from_blocks(Lc, blocks):
     return M
 
 
+def sigma3(nb):
+    """Coarse chirality grading: +1 on the first Nb/2 components, -1 on the rest."""
+    return np.where(np.arange(nb) < nb // 2, 1.0, -1.0)
+
+
+def sigma3_mirror(Lc, blocks):
+    """Blocks [Vc][9][Nb][Nb] with every backward hop replaced by the
+    sigma3-conjugated adjoint of the neighbour's forward hop:
+    M_{-mu}(c) = s M_{+mu}(c - mu)^dag s."""
+    out = np.array(blocks, copy=True)
+    s = sigma3(blocks.shape[-1])
+    S = s[:, None] * s[None, :]
+    for mu in range(4):
+        back = neighbour(Lc, 2 * mu + 2)
+        out[:, 2 * mu + 2] = S * np.conj(np.swapaxes(blocks[back, 2 * mu + 1], -1, -2))
+    return out
+
+
 def dense_prolongator(L, block, ns, Pv):
     """Dense P: rows (x, k), columns (c, b); column b reads vector b mod nv on
     chirality half b // nv, restricted to aggregate c."""

@@ -292,6 +292,30 @@ def test_coarse_operator_sigma3_hermitian():
     assert np.max(np.abs(s3 @ Dc @ s3 - Dc.conj().T)) < 1e-12
 
 
+@pytest.mark.parametrize("L,block,Lc", [((4, 4, 4, 4), (2, 2, 2, 2), (2, 2, 2, 2)),
+                                         ((6, 4, 4, 6), (2, 2, 2, 3), (3, 2, 2, 2)),
+                                         ((6, 4, 4, 4), (3, 2, 2, 2), (2, 2, 2, 2))])
+def test_coarse_backward_hops_mirror_forward_hops(L, block, Lc):
+    """Term by term, the oracle's directly coarsened backward hop equals the
+    sigma3-conjugated adjoint of the neighbour's forward hop (the relation the
+    five-point storage and the five-term coarsening rely on), also where the
+    coarse extent is 2 (c + mu = c - mu) and for odd aggregate extents."""
+    nv = 4
+    V = int(np.prod(L))
+    H, _ = _hierarchy(L, 0.3, 81, blocks=(block,), nv=(nv,))
+    H.set_start(0, syn.complex_gaussian((nv, V, 12), 82))
+    H.setup()
+    blocks = H.coarse(1)
+    assert np.max(np.abs(bf.sigma3_mirror(Lc, blocks) - blocks)) < 1e-12 * np.max(np.abs(blocks))
+    s = bf.sigma3(2 * nv)
+    M0 = blocks[:, 0]
+    assert np.max(np.abs(s[:, None] * s[None, :] * np.conj(np.swapaxes(M0, -1, -2)) - M0)) < 1e-12
+    # a planted error in one forward block breaks the relation
+    bad = blocks.copy()
+    bad[0, 1, 0, 1] += 1e-3
+    assert np.max(np.abs(bf.sigma3_mirror(Lc, bad) - bad)) > 1e-4
+
+
 def test_coarse_operator_gauge_invariant():
     L, block, nv = (4, 4, 4, 4), (2, 2, 2, 2), 4
     U = syn.gauge_field(L, 0.3, 77)
