@@ -153,9 +153,13 @@ def make_inputs(wl):
     return U, start, b
 
 
+COARSE_POINTS = 9  # blocks stored per coarse site (set by --coarse-points)
+
+
 def make_context(w, wl, mixed: bool):
     kw = dict(dims=wl["L"], m0=wl["m0"], c_sw=wl["csw"], n_levels=2, block=(wl["block"],), n_vec=(wl["nv"],),
-              relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000)
+              relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000,
+              coarse_points=COARSE_POINTS)
     if mixed:
         kw.update(cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32)
     return w.Context(**kw)
@@ -530,6 +534,8 @@ def main():
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, three_level")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
+    ap.add_argument("--coarse-points", type=int, default=9, choices=(5, 9),
+                    help="coarse blocks stored per site: 9, or 5 (Mdiag and forward hops)")
     ap.add_argument("--lattice", default="24,24,24,48", help="learned_setup kernel mode: lattice")
     ap.add_argument("--ntrain", type=int, default=48)
     ap.add_argument("--ntest", type=int, default=16)
@@ -537,6 +543,8 @@ def main():
     ap.add_argument("--mib", type=int, default=1024)
     ap.add_argument("--nrhs", type=int, default=0, help="right-hand sides for the batched coarse-apply kernel mode")
     args = ap.parse_args()
+    global COARSE_POINTS
+    COARSE_POINTS = args.coarse_points
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; N=%d is not supported (the path would shard by 4D domain "
               "decomposition, see DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -657,7 +665,7 @@ def main():
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": wl["name"], "lattice": list(L), "aggregates": list(wl["block"]), "Nb": nb,
                    "m0": wl["m0"], "c_sw": wl["csw"], "eps": wl["eps"], "tol": 1e-10, "precision":
-                   "FP32 cycle and coarse blocks, FP64 outer FGMRES"},
+                   "FP32 cycle and coarse blocks, FP64 outer FGMRES", "coarse_points": COARSE_POINTS},
         "converged": ok, "setup_s": float(np.mean(setups)), "outer_iters": infos[-1]["outer_iters"],
         "coarse_iters": infos[-1]["coarse_iters"], "true_rel_res": infos[-1]["true_rel_res"],
         "roofline": roofline, "kernels": kernel_table, "cpu_baseline": cpu,
