@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("coarse_tol", C.c_double),
         ("kcycle", C.c_int), ("kcycle_maxit", C.c_int), ("kcycle_tol", C.c_double),
         ("outer_restart", C.c_int), ("outer_maxit", C.c_int), ("outer_tol", C.c_double),
+        ("smoother", C.c_int), ("sap_block_iters", C.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ def lib():
         l.or_prolong.argtypes = [ip, ip, C.c_int, C.c_int, dp, dp, dp, C.c_int]
         l.or_coarse_gmres.argtypes = [ip, C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, dp]
         l.or_coarse_mr.argtypes = [ip, C.c_int, dp, dp, dp, C.c_int]
+        l.or_sap.argtypes = [ip, ip, C.c_double, C.c_int, dp, dp, dp, dp, C.c_int, C.c_int, C.c_int]
         l.or_gamma.argtypes = [dp, dp]
         l.or_num_threads.restype = C.c_int
         _lib = l
@@ -201,6 +203,19 @@ def coarse_gmres(Lc, blocks, b, restart=20, maxit=100, tol=0.05, fixed=0):
     return x, it, est.value
 
 
+def sap(L, block, U, clover, b, x0, cycles, block_iters, m0=-0.05, antiperiodic=True, colours=2):
+    """SAP cycles on the fine operator (domains: the aggregates of `block`,
+    red-black by coarse-coordinate parity); x0 is the initial guess.
+    colours=1 runs only the colour-0 half of one cycle."""
+    U, clover, b = _c(U), _c(clover), _c(b)
+    x = _c(x0).copy()
+    st = lib().or_sap(_ip(L), _ip(block), float(m0), int(antiperiodic), _dp(U), _dp(clover), _dp(b), _dp(x),
+                      int(cycles), int(block_iters), int(colours))
+    if st:
+        raise ValueError("SAP needs even coarse extents")
+    return x
+
+
 def coarse_mr(Lc, blocks, b, x0, steps):
     blocks, b = _c(blocks), _c(b)
     x = _c(x0).copy()
@@ -212,6 +227,7 @@ DEFAULTS = dict(
     m0=-0.05, csw=1.0, antiperiodic=1, n_levels=2, blocks=((2, 2, 2, 2),), nv=(8,), relax_sweeps=20,
     refine_iters=0, post_smooth=4, coarse_restart=20, coarse_maxit=100, coarse_fixed_iters=0, coarse_tol=0.05,
     kcycle=0, kcycle_maxit=5, kcycle_tol=0.1, outer_restart=16, outer_maxit=500, outer_tol=1e-10,
+    smoother=0, sap_block_iters=4,
 )
 
 
@@ -234,7 +250,8 @@ class Hierarchy:
         for l, n in enumerate(cfg["nv"]):
             p.nv[l] = int(n)
         for k in ("relax_sweeps", "refine_iters", "post_smooth", "coarse_restart", "coarse_maxit",
-                  "coarse_fixed_iters", "kcycle", "kcycle_maxit", "outer_restart", "outer_maxit"):
+                  "coarse_fixed_iters", "kcycle", "kcycle_maxit", "outer_restart", "outer_maxit", "smoother",
+                  "sap_block_iters"):
             setattr(p, k, int(cfg[k]))
         for k in ("coarse_tol", "kcycle_tol", "outer_tol"):
             setattr(p, k, float(cfg[k]))

@@ -186,11 +186,17 @@ struct WilsonClover : LevelOp {
   }
 
   void mdir_add(int d, const cd* in, cd* out) const override {
+#pragma omp parallel for
+    for (long x = 0; x < lat.V; ++x) hop_add(x, d, &in[lat.neighbour(x, d) * 12], &out[x * 12]);
+  }
+
+  // out (12 components at site x) += Mdir_d at x applied to psi, the spinor at
+  // the neighbour of x in direction d.
+  void hop_add(long x, int d, const cd* psi, cd* out) const {
     const Gammas& G = gammas();
     const int mu = (d - 1) / 2;
     const bool fwd = ((d - 1) % 2 == 0);
-#pragma omp parallel for
-    for (long x = 0; x < lat.V; ++x) {
+    {
       long y = lat.neighbour(x, d);
       int xc[4];
       lat.coords(x, xc);
@@ -208,7 +214,7 @@ struct WilsonClover : LevelOp {
       for (int s = 0; s < 4; ++s)
         for (int a = 0; a < 3; ++a) {
           cd t = 0.0;
-          for (int b = 0; b < 3; ++b) t += u[a][b] * in[y * 12 + s * 3 + b];
+          for (int b = 0; b < 3; ++b) t += u[a][b] * psi[s * 3 + b];
           chi[s][a] = t;
         }
       // spin structure -(1/2)(1 -+ gamma_mu)
@@ -219,7 +225,7 @@ struct WilsonClover : LevelOp {
             cd p = (s == r ? cd(1.0) : cd(0.0)) + (fwd ? -G.g[mu][s][r] : G.g[mu][s][r]);
             t += p * chi[r][a];
           }
-          out[x * 12 + s * 3 + a] += -0.5 * sign * t;
+          out[s * 3 + a] += -0.5 * sign * t;
         }
     }
   }
@@ -527,6 +533,75 @@ void mr(const LinOp& A, long n, const cd* b, cd* x, int steps) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// Schwarz alternating procedure (SAP).  The paper names SAP as the smoother
+// DDalphaAMG normally uses and as a feature the Grid implementation does not
+// have yet (Sec. 2.1, Sec. 4); it gives no definition.  Reading, the
+// multiplicative Schwarz method on a red-black colouring of domains: the
+// domains are the level-0 aggregates, coloured by the parity of their coarse
+// coordinates (so every coarse extent must be even).  One SAP cycle visits
+// colour 0 and then colour 1; for each colour it forms r = b - D x with the
+// current x, and for every domain B of that colour solves D_B e = r_B by
+// block_iters MR steps from e = 0 (D_B: D with every coupling that leaves B
+// dropped, a Dirichlet boundary), then sets x_B += e.  Domains of one colour
+// do not couple, so they are independent of each other.
+// ----------------------------------------------------------------------------
+
+// out = D_B v on domain c; v and out are indexed by in-block offset.
+void block_apply(const WilsonClover& D, const Aggregation& ag, long c, const cd* v, cd* out) {
+  for (long o = 0; o < ag.A; ++o) {
+    const long x = ag.site_of[c * ag.A + o];
+    const cd* cl = &D.C[x * 144];
+    for (int i = 0; i < 12; ++i) {
+      cd s = (4.0 + D.m0) * v[o * 12 + i];
+      for (int j = 0; j < 12; ++j) s += cl[i * 12 + j] * v[o * 12 + j];
+      out[o * 12 + i] = s;
+    }
+    for (int d = 1; d <= 8; ++d) {
+      const long y = D.lat.neighbour(x, d);
+      if (ag.agg[y] != c) continue;  // the coupling leaves the domain
+      D.hop_add(x, d, &v[ag.off[y] * 12], &out[o * 12]);
+    }
+  }
+}
+
+// colours = 2: full cycles; colours = 1: the colour-0 half of one cycle.
+int sap(const WilsonClover& D, const Aggregation& ag, const cd* b, cd* x, int cycles, int block_iters,
+        int colours = 2) {
+  for (int mu = 0; mu < 4; ++mu)
+    if (ag.coarse.L[mu] % 2) return 2;
+  const long V = D.lat.V, A = ag.A;
+  cvec Dx(V * 12);
+  for (int cyc = 0; cyc < cycles; ++cyc)
+    for (int colour = 0; colour < colours; ++colour) {
+      D.apply(x, Dx.data());
+#pragma omp parallel for
+      for (long c = 0; c < ag.coarse.V; ++c) {
+        int cx[4];
+        ag.coarse.coords(c, cx);
+        if ((cx[0] + cx[1] + cx[2] + cx[3]) % 2 != colour) continue;
+        cvec r(A * 12), e(A * 12, cd(0.0)), p(A * 12);
+        for (long o = 0; o < A; ++o) {
+          const long xs = ag.site_of[c * A + o];
+          for (int k = 0; k < 12; ++k) r[o * 12 + k] = b[xs * 12 + k] - Dx[xs * 12 + k];
+        }
+        for (int it = 0; it < block_iters; ++it) {
+          block_apply(D, ag, c, r.data(), p.data());
+          const double pp = std::real(dot(A * 12, p.data(), p.data()));
+          if (pp == 0.0) break;
+          const cd alpha = dot(A * 12, p.data(), r.data()) / pp;
+          axpy(A * 12, alpha, r.data(), e.data());
+          axpy(A * 12, -alpha, p.data(), r.data());
+        }
+        for (long o = 0; o < A; ++o) {
+          const long xs = ag.site_of[c * A + o];
+          for (int k = 0; k < 12; ++k) x[xs * 12 + k] += e[o * 12 + k];
+        }
+      }
+    }
+  return 0;
+}
+
 struct KrylovResult {
   int iters = 0;
   double est = 0.0;
@@ -629,6 +704,8 @@ struct Params {
   double kcycle_tol;
   int outer_restart, outer_maxit;
   double outer_tol;
+  int smoother;         // 0: MR, 1: SAP on level 0 (post_smooth cycles)
+  int sap_block_iters;  // MR steps per domain solve
 };
 
 struct Level {
@@ -680,6 +757,10 @@ void cycle(const Hierarchy& H, int l, const cd* r, cd* x) {
     cycle(H, l + 1, rc.data(), ec.data());
   }
   prolong_vec(L.ag, D.ns, L.nv, L.Pv, ec.data(), x);
+  if (l == 0 && H.p.smoother == 1) {
+    sap(H.fine, L.ag, r, x, H.p.post_smooth, H.p.sap_block_iters);
+    return;
+  }
   LinOp A = [&](const cd* i, cd* o) { D.apply(i, o); };
   mr(A, D.size(), r, x, H.p.post_smooth);
 }
@@ -877,6 +958,22 @@ int or_coarse_gmres(const int* Lc, int nb, const double* M, const double* b, dou
 }
 
 // MR steps on a caller-given coarse operator: x holds x0 on entry.
+// SAP on the fine operator with the aggregates of `block` as domains; x holds
+// the initial guess.  Returns 2 when a coarse extent is odd.
+int or_sap(const int* L, const int* block, double m0, int antiperiodic, const double* U, const double* C,
+           const double* b, double* x, int cycles, int block_iters, int colours) {
+  WilsonClover D;
+  D.lat = Lattice(L);
+  D.ns = 12;
+  D.m0 = m0;
+  D.antiperiodic = antiperiodic != 0;
+  D.U.assign((const cd*)U, (const cd*)U + D.lat.V * 36);
+  D.C.assign((const cd*)C, (const cd*)C + D.lat.V * 144);
+  Aggregation ag;
+  if (make_aggregation(D.lat, block, ag)) return 2;
+  return sap(D, ag, (const cd*)b, (cd*)x, cycles, block_iters, colours);
+}
+
 void or_coarse_mr(const int* Lc, int nb, const double* M, const double* b, double* x, int steps) {
   CoarseOp op;
   op.lat = Lattice(Lc);
@@ -905,6 +1002,9 @@ void* or_mg_create(const or_params* p, const double* U, const double* C /* [V][1
     H->lv[l].nv = p->nv[l];
     lat = H->lv[l].ag.coarse;
   }
+  if (p->smoother == 1 && !H->lv.empty())
+    for (int mu = 0; mu < 4; ++mu)
+      if (H->lv[0].ag.coarse.L[mu] % 2) { delete H; return nullptr; }  // SAP needs two colours
   return H;
 }
 
