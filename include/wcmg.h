@@ -94,7 +94,12 @@ typedef struct {
                               the forward hops, the backward hops applied as sigma3-conjugated adjoints of the
                               neighbours' forward blocks (Sec. 4: five independent stencil points; needs
                               Nb in {8, 12, 16, 24, 32}, else nine are stored) */
-  int32_t reserved[4];
+  int32_t smoother;        /* level-0 post-smoother: 0 = MR (post_smooth steps); 1 = SAP (post_smooth cycles of the
+                              Schwarz alternating procedure, Sec. 2.1 and Sec. 4, on the level-0 aggregates as
+                              domains; needs an even number of aggregates in every direction and at most 256
+                              sites per aggregate).  Coarser levels always use MR. */
+  int32_t sap_block_iters; /* MR steps per SAP domain solve (default 4) */
+  int32_t reserved[2];
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;
@@ -281,6 +286,19 @@ int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
  * and their total duration in milliseconds, then reset. */
 int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable);
 int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms);
+
+/* SAP on the fine operator (Sec. 2.1 and Sec. 4 name SAP, the smoother
+ * DDalphaAMG normally uses, without defining it).  Reading: the domains are the
+ * level-0 aggregates, coloured by the parity of their coarse coordinates; one
+ * cycle visits colour 0 then colour 1, and for every domain B of the colour
+ * forms r_B = b_B - (D x)_B with the current x, runs sap_block_iters MR steps
+ * on D_B e = r_B from e = 0 (D_B: D with every coupling that leaves B dropped)
+ * and sets x_B += e.  b and x: nrhs device fields [nrhs][V][4][3], complex128
+ * (prec WCMG_F64) or complex64 (WCMG_F32), canonical layout; x holds the
+ * initial guess and receives the result.  Needs the gauge field, n_levels >= 2,
+ * even aggregate counts in every direction and aggregates of at most 256
+ * sites (WCMG_ERR_DIMS / WCMG_ERR_ARG otherwise).  Synchronises the stream. */
+int wcmg_sap(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int cycles, int prec);
 
 /* ---- standalone coarse operator (CoarsenedMatrix without a hierarchy) ---- */
 typedef struct wcmg_coarse wcmg_coarse;

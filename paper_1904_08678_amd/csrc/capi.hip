@@ -71,6 +71,7 @@ void wcmg_default_params(wcmg_params* p) {
   p->outer_restart = 20;
   p->outer_maxit = 1000;
   p->outer_tol = 1e-10;
+  p->sap_block_iters = 4;
   p->cycle_prec = WCMG_F64;
   p->coarse_store_prec = WCMG_F64;
   p->setup_prec = WCMG_F64;
@@ -218,6 +219,32 @@ int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks) {
     C.refresh(WCMG_F32, c.stream);
     if (C.nb % 4 == 0) C.refresh(WCMG_BF16, c.stream);
     c.sync();
+  });
+}
+
+int wcmg_sap(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int cycles, int prec) {
+  return guarded(ctx, [&](Context& c) {
+    check_prec(prec, false);
+    require(b && x && nrhs >= 1 && cycles >= 0, WCMG_ERR_ARG, "bad fields or cycle count");
+    require(c.gauge_set, WCMG_ERR_STATE, "gauge field not set");
+    c.sap_prepare();
+    const long V = c.geo[0].V, nn = c.n(0);
+    if (prec == WCMG_F64) {
+      cd64* bb = c.buf<cd64>("abi_a64", nn * nrhs);
+      cd64* xx = c.buf<cd64>("abi_b64", nn * nrhs);
+      launch_pack_fermion<double, double>((const cd64*)b, c.perm0.as<int>(), V, nrhs, bb, c.stream);
+      launch_pack_fermion<double, double>((const cd64*)x, c.perm0.as<int>(), V, nrhs, xx, c.stream);
+      c.sap<double>(bb, xx, cycles, nrhs, nullptr, 0);
+      launch_unpack_fermion<double, double>(xx, c.perm0.as<int>(), V, nrhs, (cd64*)x, c.stream);
+    } else {
+      cf32* bb = c.buf<cf32>("abi_a32", nn * nrhs);
+      cf32* xx = c.buf<cf32>("abi_b32", nn * nrhs);
+      launch_pack_fermion<float, float>((const cf32*)b, c.perm0.as<int>(), V, nrhs, bb, c.stream);
+      launch_pack_fermion<float, float>((const cf32*)x, c.perm0.as<int>(), V, nrhs, xx, c.stream);
+      c.sap<float>(bb, xx, cycles, nrhs, nullptr, 0);
+      launch_unpack_fermion<float, float>(xx, c.perm0.as<int>(), V, nrhs, (cf32*)x, c.stream);
+    }
+    WCMG_HIP(hipStreamSynchronize(c.stream));
   });
 }
 

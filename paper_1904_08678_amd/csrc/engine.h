@@ -183,6 +183,9 @@ struct Context {
   DevBuf U_lex, clover_lex;     // canonical copies (FP64)
   DevBuf U64, U32, clov64, clov32;
   bool gauge_set = false, setup_done = false;
+  // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
+  DevBuf sap_doms;
+  long sap_ndoms = 0;
   // workspaces
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::map<std::string, std::unique_ptr<GmresState>> gm;
@@ -234,6 +237,11 @@ struct Context {
 
   template <typename R>
   void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run);
+  // `cycles` SAP cycles on D x = b at level 0 for nrhs fields (run flags with
+  // stride rs; run may be null)
+  void sap_prepare();
+  template <typename R>
+  void sap(const cplx<R>* b, cplx<R>* x, int cycles, int nrhs, const int* run, int rs);
   template <typename R>
   void cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run);
   void precondition64(int l, const cd64* r, cd64* x, const int* run);

@@ -179,6 +179,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   require(p.coarse_store_prec >= 0 && p.coarse_store_prec <= 2, WCMG_ERR_ARG, "bad coarse_store_prec");
   require(p.coarse_points == 0 || p.coarse_points == 5 || p.coarse_points == 9, WCMG_ERR_ARG,
           "coarse_points must be 5 or 9");
+  require(p.smoother == 0 || p.smoother == 1, WCMG_ERR_ARG, "smoother must be 0 (MR) or 1 (SAP)");
+  require(p.smoother == 0 || p.sap_block_iters >= 1, WCMG_ERR_ARG, "sap_block_iters must be >= 1");
   require(p.outer_restart >= 1 && p.outer_restart <= 40 && p.coarse_restart >= 1 && p.coarse_restart <= 40 &&
               p.kcycle_maxit >= 1 && p.kcycle_maxit <= 40,
           WCMG_ERR_ARG, "restart lengths must lie in 1..40");
@@ -656,9 +658,50 @@ void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
     cycle<R>(lc, rc, ec, run);
   }
   prolong_<R>(l, ec, x, 0, 1, run);
-  mr<R>(l, r, x, false, p.post_smooth, run);
+  if (l == 0 && p.smoother == 1) sap<R>(r, x, p.post_smooth, 1, run, 0);
+  else mr<R>(l, r, x, false, p.post_smooth, run);
   cycles++;
 }
+
+// SAP domains: the level-0 aggregates, coloured by the parity of their coarse
+// coordinates (two colours need every coarse extent even; a domain is one
+// aggregate of at most 256 sites, contiguous in the device site order).
+void Context::sap_prepare() {
+  if (sap_ndoms > 0) return;
+  require(nlev >= 2, WCMG_ERR_ARG, "SAP uses the level-0 aggregates as domains: n_levels >= 2");
+  const LevelGeom& Gc = geo[1];
+  for (int m = 0; m < 4; ++m)
+    require(Gc.L[m] % 2 == 0, WCMG_ERR_DIMS, "SAP needs an even number of aggregates in every direction");
+  require(tr[0].A <= 256, WCMG_ERR_ARG, "SAP domains (aggregates) hold at most 256 sites");
+  std::vector<int> lists[2];
+  for (long c = 0; c < Gc.V; ++c) {
+    int x[4];
+    lex_coords(c, Gc.L, x);
+    lists[(x[0] + x[1] + x[2] + x[3]) & 1].push_back((int)c);
+  }
+  std::vector<int> both(lists[0]);
+  both.insert(both.end(), lists[1].begin(), lists[1].end());
+  upload(sap_doms, both);
+  sap_ndoms = (long)lists[0].size();
+}
+
+template <typename R>
+void Context::sap(const cplx<R>* b, cplx<R>* x, int cycles, int nrhs, const int* run, int rs) {
+  sap_prepare();
+  const bool single = sizeof(R) == 4;
+  const cplx<R>* U = single ? (const cplx<R>*)U32.as<cf32>() : (const cplx<R>*)U64.as<cd64>();
+  const R* clov = single ? (const R*)clov32.as<float>() : (const R*)clov64.as<double>();
+  const char* fam = single ? "sap_f32" : "sap_f64";
+  for (int c = 0; c < cycles; ++c)
+    for (int colour = 0; colour < 2; ++colour) {
+      prof.begin_kernel(fam);
+      launch_sap<R>(x, b, U, clov, geo[0].nbr.as<int>(), geo[0].V, tr[0].A, sap_doms.as<int>() + colour * sap_ndoms,
+                    (int)sap_ndoms, p.sap_block_iters, nrhs, run, rs, stream);
+      prof.end(fam, stream);
+    }
+}
+template void Context::sap<double>(const cd64*, cd64*, int, int, const int*, int);
+template void Context::sap<float>(const cf32*, cf32*, int, int, const int*, int);
 
 void Context::precondition64(int l, const cd64* r, cd64* x, const int* run) {
   if (p.cycle_prec == WCMG_F64) {

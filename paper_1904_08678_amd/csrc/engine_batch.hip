@@ -357,7 +357,8 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
     launch_prolong<R>(ec, x, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, 0, B, run, stream, rs);
     if (!capturing) prof.end(fam, stream);
   }
-  mrB<R>(l, r, x, B, p.post_smooth, run, rs);
+  if (l == 0 && p.smoother == 1) sap<R>(r, x, p.post_smooth, B, run, rs);
+  else mrB<R>(l, r, x, B, p.post_smooth, run, rs);
   cycles += B;
 }
 

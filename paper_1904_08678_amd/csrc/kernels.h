@@ -29,6 +29,12 @@ int wilson_blocks(long V);
 void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* clov, const int* nbr, long V, int nrhs,
                         const int* run, int rs, cd64* dots, hipStream_t st);
 
+// ---- SAP smoother (sap.hip): one colour of domains; x, b [nrhs][12][V];
+// doms: aggregate indices of the colour; A: sites per domain (<= 256)
+template <typename R>
+void launch_sap(cplx<R>* x, const cplx<R>* b, const cplx<R>* U, const R* clov, const int* nbr, long V, int A,
+                const int* doms, int ndoms, int iters, int nrhs, const int* run, int rs, hipStream_t st);
+
 // ---- coarse operator (coarse.hip)
 size_t device_block_bytes(long Vc, int nb, int prec);
 void launch_blocks_to_device(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);

@@ -37,7 +37,8 @@ class Params(C.Structure):
         ("coarse_tol", C.c_double), ("kcycle", C.c_int32), ("kcycle_maxit", C.c_int32), ("kcycle_tol", C.c_double),
         ("outer_restart", C.c_int32), ("outer_maxit", C.c_int32), ("outer_tol", C.c_double),
         ("cycle_prec", C.c_int32), ("coarse_store_prec", C.c_int32), ("setup_prec", C.c_int32),
-        ("coarse_points", C.c_int32), ("reserved", C.c_int32 * 4),
+        ("coarse_points", C.c_int32), ("smoother", C.c_int32), ("sap_block_iters", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -251,6 +252,14 @@ class Context:
         out = torch.empty((nrhs, self.sites(level), self.ns[level]), dtype=coarse.dtype, device="cuda")
         self._chk(lib().wcmg_prolong(self.h, level, _ptr(coarse), _ptr(out), nrhs, prec))
         return out
+
+    def sap(self, b: torch.Tensor, x: torch.Tensor, cycles: int, prec=None) -> torch.Tensor:
+        """wcmg_sap: `cycles` SAP cycles on D x = b (x updated in place)."""
+        nrhs = b.numel() // (self.V * 12)
+        if prec is None:
+            prec = F64 if b.dtype == torch.complex128 else F32
+        self._chk(lib().wcmg_sap(self.h, _ptr(b), _ptr(x), nrhs, int(cycles), int(prec)))
+        return x
 
     def cycle(self, r: torch.Tensor) -> torch.Tensor:
         out = torch.empty_like(r)
