@@ -229,6 +229,43 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
             "batched": batched}
 
 
+def sap_smoother(w, torch, wl, Ud, startd, bd, iters=4):
+    """The benchmark solve with SAP (1 and 2 cycles, `iters` MR steps per
+    domain) as the level-0 post-smoother instead of MR(4), and the SAP
+    launches' duration.  Algorithmic bytes of one colour's launch: on its half
+    of the sites, links, clover, b and x read and x written once, plus x of the
+    other half read once (960 B per active site in FP32); flops: the residual
+    (1872 per site) and, per MR step, the domain operator (1872) and the
+    updates (96)."""
+    import numpy as np
+    V = int(np.prod(wl["L"]))
+    out = {"domains": "level-0 aggregates %s, red-black" % "x".join(map(str, wl["block"])), "block_iters": iters}
+    for cycles in (1, 2):
+        kw = dict(dims=wl["L"], m0=wl["m0"], c_sw=wl["csw"], n_levels=2, block=(wl["block"],), n_vec=(wl["nv"],),
+                  relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000,
+                  cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32, smoother=1, sap_block_iters=iters,
+                  post_smooth=cycles)
+        ctx = w.Context(**kw)
+        ctx.set_gauge(Ud)
+        ctx.set_null_vectors(0, startd)
+        ctx.setup()
+        ctx.solve(bd)
+        ctx.profile("sap_f32", True)
+        x, info, st = ctx.solve(bd)
+        n, ms = ctx.profile_stats("sap_f32")
+        ctx.profile("sap_f32", False)
+        x, info2, st2 = ctx.solve(bd)
+        avg = ms / max(n, 1)
+        byts = V / 2 * 960.0
+        flops = V / 2 * (1872.0 + iters * (1872.0 + 96.0))
+        out["cycles_%d" % cycles] = {
+            "solve_s": min(info[0]["t_solve_s"], info2[0]["t_solve_s"]), "outer_iters": info[0]["outer_iters"],
+            "true_rel_res": info[0]["true_rel_res"], "converged": st == 0,
+            "sap_launch_ms": avg, "sap_launches": n, "sap_GB_s": byts / avg / 1e6, "sap_TFLOP_s": flops / avg / 1e9}
+        del ctx
+    return out
+
+
 def batched_point_sources(w, torch, wl, fp64=True):
     """Twelve point sources on the 24^3 x 48 lattice: one batched solve (matrix-core
     coarse apply; with and without the HIP-graph cycle; per-row coarse kernel for
@@ -529,6 +566,7 @@ def main():
     ap.add_argument("--no-mk", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-sap", action="store_true")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, three_level")
@@ -638,6 +676,9 @@ def main():
                          "true_rel_res": inf64[0]["true_rel_res"]}
         extra["speedup_mixed_vs_fp64"] = extra["fp64"]["solve_s"] / solve_s
         del c64
+    if not args.no_sap:
+        print("[bench] SAP smoother", file=sys.stderr, flush=True)
+        extra["sap_smoother"] = sap_smoother(w, torch, wl, Ud, startd, bd)
     if not args.no_mk:
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)

@@ -120,11 +120,84 @@ __device__ inline void sap_group(int g, cplx<R> (&acc)[12], const cplx<R>* __res
     }
   }
 }
+
+// One thread's operator data for direction group G of NG = 2 (directions 2G
+// and 2G+1, clover chirality G): its four links (forward U_mu(s), backward
+// U_mu(s - mu)), the four neighbour sites and the 36 reals of its clover
+// block, loaded once and kept in registers for the residual and every MR step.
+template <typename R>
+struct SapOps {
+  cplx<R> u[4][9];
+  long y[4];
+  R cl[36];
+};
+
+template <typename R, int G>
+__device__ inline void sap_load_ops(SapOps<R>& op, const cplx<R>* __restrict__ U, const R* __restrict__ clov,
+                                    const int* __restrict__ nbr, long V, long s) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int mu = 2 * G + j / 2, f = j % 2;
+    op.y[j] = nbr[(long)(2 * mu + f) * V + s];
+    const long ls = f == 0 ? s : op.y[j];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) op.u[j][e] = U[(long)(mu * 9 + e) * V + ls];
+  }
+  constexpr int RC = 16 / sizeof(R);
+  typedef typename std::conditional<sizeof(R) == 4, float4, double2>::type V16;
+  const V16* cb = (const V16*)(clov + (long)G * 36 * V);
+#pragma unroll
+  for (int q = 0; q < 36 / RC; ++q) {
+    const V16 c = cb[(long)q * V + s];
+    if constexpr (RC == 4) {
+      op.cl[q * 4 + 0] = c.x;
+      op.cl[q * 4 + 1] = c.y;
+      op.cl[q * 4 + 2] = c.z;
+      op.cl[q * 4 + 3] = c.w;
+    } else {
+      op.cl[q * 2 + 0] = c.x;
+      op.cl[q * 2 + 1] = c.y;
+    }
+  }
+}
+
+template <typename R, int G, int J, bool FROM_LDS>
+__device__ inline void sap_hop_j(cplx<R> (&acc)[12], const SapOps<R>& op, const cplx<R>* __restrict__ x, long V,
+                                 long base, int A, const cplx<R> (*rho)[kSapMaxA]) {
+  constexpr int MU = 2 * G + J / 2;
+  constexpr bool FWD = J % 2 == 0;
+  cplx<R> p[12];
+  if (FROM_LDS) {
+    const long oy = op.y[J] - base;
+    if (oy < 0 || oy >= A) return;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = rho[k][oy];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = x[(long)k * V + op.y[J]];
+  }
+  hop_core<R, MU, FWD>(acc, p, op.u[J]);
+}
+
+template <typename R, int G, bool FROM_LDS>
+__device__ inline void sap_apply_ops(cplx<R> (&acc)[12], const SapOps<R>& op, const cplx<R>* __restrict__ x,
+                                     long V, long s, long base, int A, int o, const cplx<R> (*rho)[kSapMaxA]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mkc((R)0, (R)0);
+  cplx<R> p[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = FROM_LDS ? rho[G * 6 + k][o] : x[(long)(G * 6 + k) * V + s];
+  clover_block_apply<R, G>(acc, op.cl, p);
+  sap_hop_j<R, G, 0, FROM_LDS>(acc, op, x, V, base, A, rho);
+  sap_hop_j<R, G, 1, FROM_LDS>(acc, op, x, V, base, A, rho);
+  sap_hop_j<R, G, 2, FROM_LDS>(acc, op, x, V, base, A, rho);
+  sap_hop_j<R, G, 3, FROM_LDS>(acc, op, x, V, base, A, rho);
+}
 }  // namespace
 
 // x and b: [nrhs][12][V] (right-hand side r at offset r * 12 * V); doms: the
 // aggregate indices of this colour (one workgroup each, blockIdx.y = rhs).
-template <typename R, int NG>
+template <typename R, int NG, bool CACHE>
 __global__ void __launch_bounds__(NG * 256) k_sap(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ b,
                                               const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                               const int* __restrict__ nbr, long V, int A,
@@ -145,9 +218,17 @@ __global__ void __launch_bounds__(NG * 256) k_sap(cplx<R>* __restrict__ x, const
   b += r * 12 * V;
   const cplx<R>(*rho)[kSapMaxA] = sh.rho;
   cplx<R> acc[12];
+  static_assert(!CACHE || NG == 2, "register-resident operators need two direction groups");
+  SapOps<R> op;
+  if (CACHE && valid) {
+    if (g == 0) sap_load_ops<R, 0>(op, U, clov, nbr, V, s);
+    else sap_load_ops<R, 1>(op, U, clov, nbr, V, s);
+  }
   // residual r_B = b - D x at the domain's sites (full operator, global x)
   if (valid) {
-    sap_group<R, NG, false>(g, acc, x, U, clov, nbr, V, s, base, A, o, rho);
+    if (!CACHE) sap_group<R, NG, false>(g, acc, x, U, clov, nbr, V, s, base, A, o, rho);
+    else if (g == 0) sap_apply_ops<R, 0, false>(acc, op, x, V, s, base, A, o, rho);
+    else sap_apply_ops<R, 1, false>(acc, op, x, V, s, base, A, o, rho);
 #pragma unroll
     for (int k = 0; k < 12; ++k) sh.part[g][k][o] = acc[k];
   }
@@ -170,7 +251,9 @@ __global__ void __launch_bounds__(NG * 256) k_sap(cplx<R>* __restrict__ x, const
   for (int it = 0; it < iters; ++it) {
     __syncthreads();  // rho complete
     if (valid) {
-      sap_group<R, NG, true>(g, acc, x, U, clov, nbr, V, s, base, A, o, rho);
+      if (!CACHE) sap_group<R, NG, true>(g, acc, x, U, clov, nbr, V, s, base, A, o, rho);
+      else if (g == 0) sap_apply_ops<R, 0, true>(acc, op, x, V, s, base, A, o, rho);
+      else sap_apply_ops<R, 1, true>(acc, op, x, V, s, base, A, o, rho);
 #pragma unroll
       for (int k = 0; k < 12; ++k) sh.part[g][k][o] = acc[k];
     }
@@ -237,10 +320,13 @@ template <typename R>
 void launch_sap(cplx<R>* x, const cplx<R>* b, const cplx<R>* U, const R* clov, const int* nbr, long V, int A,
                 const int* doms, int ndoms, int iters, int nrhs, const int* run, int rs, hipStream_t st) {
   require(A >= 1 && A <= kSapMaxA, WCMG_ERR_ARG, "SAP domains hold at most 256 sites");
+  // FP32 keeps each thread's links and clover block in registers across the
+  // MR steps; FP64 (twice the registers) reloads them from the caches
   constexpr int NG = 2;
+  constexpr bool CACHE = sizeof(R) == 4;
   const int NQ = (A + 63) / 64;
-  WCMG_LAUNCH((k_sap<R, NG>), dim3(ndoms, nrhs), dim3(NG * NQ * 64), 0, st, x, b, U, clov, nbr, V, A, doms, iters,
-              run, rs);
+  WCMG_LAUNCH((k_sap<R, NG, CACHE>), dim3(ndoms, nrhs), dim3(NG * NQ * 64), 0, st, x, b, U, clov, nbr, V, A, doms,
+              iters, run, rs);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_sap<float>(cf32*, const cf32*, const cf32*, const float*, const int*, long, int, const int*, int,
