@@ -281,9 +281,13 @@ int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
  * bracketed by HIP events on the context stream.  Families:
  * "dslash_f64", "dslash_f32" (full fine operator), "wilson_term" (single
  * terms, coarsening), "coarse_apply_f64", "coarse_apply_f32",
- * "coarse_apply_bf16", "coarse_term", "restrict_f64", "restrict_f32",
- * "prolong_f64", "prolong_f32".  Stats return the number of timed launches
- * and their total duration in milliseconds, then reset. */
+ * "coarse_apply_bf16", "coarse_term", "coarse_mfma_f32", "coarse_mfma_bf16"
+ * (batched coarse apply on the matrix cores), "coarse_gmres_step_f64",
+ * "coarse_gmres_step_f32", "coarse_gmres_step_bf16" (apply step of the fused
+ * coarsest GMRES), "restrict_f64", "restrict_f32", "prolong_f64",
+ * "prolong_f32", "sap_f64", "sap_f32" (one SAP colour), "nn_forward",
+ * "nn_backward" (network, on its own context).  Stats return the number of
+ * timed launches and their total duration in milliseconds, then reset. */
 int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable);
 int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms);
 
