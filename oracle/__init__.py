@@ -81,6 +81,9 @@ def lib():
         l.or_coarse_gmres.argtypes = [ip, C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, dp]
         l.or_coarse_mr.argtypes = [ip, C.c_int, dp, dp, dp, C.c_int]
         l.or_sap.argtypes = [ip, ip, C.c_double, C.c_int, dp, dp, dp, dp, C.c_int, C.c_int, C.c_int]
+        l.or_schur_apply.argtypes = [ip, C.c_double, C.c_int, dp, dp, dp, dp]
+        l.or_clover_inverse.argtypes = [ip, C.c_double, dp, dp]
+        l.or_mg_solve_eo.argtypes = [vp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         l.or_gamma.argtypes = [dp, dp]
         l.or_num_threads.restype = C.c_int
         _lib = l
@@ -216,6 +219,34 @@ def sap(L, block, U, clover, b, x0, cycles, block_iters, m0=-0.05, antiperiodic=
     return x
 
 
+def schur_apply(L, m0, antiperiodic, U, Cl, psi) -> np.ndarray:
+    """Even-odd Schur complement Dhat = A_oo - H_oe A_ee^{-1} H_eo applied to the
+    odd part of psi [V][4][3]; the even part of the result is zero."""
+    psi = _c(psi)
+    out = np.zeros_like(psi)
+    st = lib().or_schur_apply(_ip(L), float(m0), int(antiperiodic), _dp(_c(U)), _dp(_c(Cl)), _dp(psi), _dp(out))
+    if st:
+        raise ValueError("singular clover block")
+    return out
+
+
+def clover_inverse(L, m0, Cl) -> np.ndarray:
+    """((4 + m0) + C(x))^{-1} per site, [V][12][12]."""
+    out = np.zeros((vol(L), 12, 12), np.complex128)
+    st = lib().or_clover_inverse(_ip(L), float(m0), _dp(_c(Cl)), _dp(out))
+    if st:
+        raise ValueError("singular clover block")
+    return out
+
+
+def parity(L) -> np.ndarray:
+    """Site parity (x + y + z + t) mod 2 of the lexicographic sites."""
+    V = vol(L)
+    i = np.arange(V)
+    c = [i % L[0], i // L[0] % L[1], i // (L[0] * L[1]) % L[2], i // (L[0] * L[1] * L[2])]
+    return (c[0] + c[1] + c[2] + c[3]) % 2
+
+
 def coarse_mr(Lc, blocks, b, x0, steps):
     blocks, b = _c(blocks), _c(b)
     x = _c(x0).copy()
@@ -331,6 +362,15 @@ class Hierarchy:
         out = np.zeros_like(r)
         lib().or_mg_cycle(self.h, l, _dp(r), _dp(out))
         return out
+
+    def solve_eo(self, b, x0=None):
+        """Even-odd preconditioned outer solve (Schur complement on the odd sites)."""
+        b = _c(b).reshape(-1)
+        x = np.zeros_like(b) if x0 is None else _c(x0).reshape(-1).copy()
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        st = lib().or_mg_solve_eo(self.h, _dp(b), _dp(x), C.byref(it), C.byref(rr))
+        return x, it.value, rr.value, st
 
     def solve(self, b, x0=None):
         b = _c(b).reshape(-1)

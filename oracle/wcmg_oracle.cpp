@@ -534,6 +534,112 @@ void mr(const LinOp& A, long n, const cd* b, cd* x, int steps) {
 }
 
 // ----------------------------------------------------------------------------
+// Even-odd (red-black) preconditioning.  The paper names red-black
+// preconditioning as a feature the Grid implementation lacks and DDalphaAMG
+// uses (Sec. 2.1, Sec. 4) without writing it down.  Reading: sites are even or
+// odd by the parity of x+y+z+t; with A = (4 + m0) + C (site-diagonal) and the
+// hopping terms H_eo, H_oe connecting the two parities,
+//   D = [[A_ee, H_eo], [H_oe, A_oo]],   Dhat = A_oo - H_oe A_ee^{-1} H_eo,
+// and D x = b becomes Dhat x_o = b_o - H_oe A_ee^{-1} b_e,
+// x_e = A_ee^{-1} (b_e - H_eo x_o).  Fields keep their full length with the
+// even part zero.
+// ----------------------------------------------------------------------------
+int site_parity(const Lattice& lat, long x) {
+  int c[4];
+  lat.coords(x, c);
+  return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+// Inverse of a dense n x n complex matrix by Gauss-Jordan elimination with
+// partial pivoting (rows); returns 1 when singular.
+int invert_dense(int n, const cd* a, cd* inv) {
+  std::vector<cd> m(a, a + n * n);
+  for (int i = 0; i < n * n; ++i) inv[i] = 0.0;
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(m[i * n + k]) > std::abs(m[piv * n + k])) piv = i;
+    if (std::abs(m[piv * n + k]) == 0.0) return 1;
+    for (int j = 0; j < n; ++j) {
+      std::swap(m[k * n + j], m[piv * n + j]);
+      std::swap(inv[k * n + j], inv[piv * n + j]);
+    }
+    const cd d = 1.0 / m[k * n + k];
+    for (int j = 0; j < n; ++j) {
+      m[k * n + j] *= d;
+      inv[k * n + j] *= d;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const cd f = m[i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        m[i * n + j] -= f * m[k * n + j];
+        inv[i * n + j] -= f * inv[k * n + j];
+      }
+    }
+  }
+  return 0;
+}
+
+// A(x)^{-1} for every site, [V][12][12]: A = (4 + m0) + C is block diagonal in
+// chirality (C commutes with gamma5), so each 6 x 6 block is inverted alone.
+int clover_inverse(const WilsonClover& D, cvec& Ainv) {
+  const long V = D.lat.V;
+  Ainv.assign(V * 144, cd(0.0));
+  int bad = 0;
+#pragma omp parallel for reduction(| : bad)
+  for (long x = 0; x < V; ++x) {
+    for (int chi = 0; chi < 2; ++chi) {
+      cd blk[36], inv[36];
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j)
+          blk[i * 6 + j] = D.C[x * 144 + (chi * 6 + i) * 12 + chi * 6 + j] + (i == j ? cd(4.0 + D.m0) : cd(0.0));
+      bad |= invert_dense(6, blk, inv);
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) Ainv[x * 144 + (chi * 6 + i) * 12 + chi * 6 + j] = inv[i * 6 + j];
+    }
+  }
+  return bad;
+}
+
+// out = (parity of x == keep) ? M(x) in(x) : 0 for site matrices M [V][12][12].
+void site_apply_masked(const WilsonClover& D, const cvec& M, int keep, const cd* in, cd* out) {
+#pragma omp parallel for
+  for (long x = 0; x < D.lat.V; ++x) {
+    const bool on = site_parity(D.lat, x) == keep;
+    for (int i = 0; i < 12; ++i) {
+      cd s = 0.0;
+      if (on)
+        for (int j = 0; j < 12; ++j) s += M[x * 144 + i * 12 + j] * in[x * 12 + j];
+      out[x * 12 + i] = s;
+    }
+  }
+}
+
+// out = the hopping part of D applied to in (all eight Mdir terms).
+void hopping(const WilsonClover& D, const cd* in, cd* out) {
+  std::fill(out, out + D.size(), cd(0.0));
+  for (int d = 1; d <= 8; ++d) D.mdir_add(d, in, out);
+}
+
+// y = Dhat x on the odd sites (x: odd part used, even part ignored), y even = 0.
+void schur_apply(const WilsonClover& D, const cvec& Ainv, const cd* x, cd* y) {
+  const long n = D.size();
+  cvec xo(n), t(n), u(n), w(n), ax(n);
+  for (long s = 0; s < D.lat.V; ++s)
+    for (int k = 0; k < 12; ++k) xo[s * 12 + k] = site_parity(D.lat, s) == 1 ? x[s * 12 + k] : cd(0.0);
+  hopping(D, xo.data(), t.data());               // even sites: H_eo x_o
+  site_apply_masked(D, Ainv, 0, t.data(), u.data());  // A_ee^{-1} H_eo x_o
+  hopping(D, u.data(), w.data());                // odd sites: H_oe A_ee^{-1} H_eo x_o
+  D.mdiag(xo.data(), ax.data());                 // A x_o
+  for (long s = 0; s < D.lat.V; ++s)
+    for (int k = 0; k < 12; ++k)
+      y[s * 12 + k] = site_parity(D.lat, s) == 1 ? ax[s * 12 + k] - w[s * 12 + k] : cd(0.0);
+}
+
+// ----------------------------------------------------------------------------
 // Schwarz alternating procedure (SAP).  The paper names SAP as the smoother
 // DDalphaAMG normally uses and as a feature the Grid implementation does not
 // have yet (Sec. 2.1, Sec. 4); it gives no definition.  Reading, the
@@ -1084,6 +1190,98 @@ void or_mg_apply(void* h, int l, const double* in, double* out) {
 void or_mg_cycle(void* h, int l, const double* r, double* x) {
   Hierarchy* H = (Hierarchy*)h;
   cycle(*H, l, (const cd*)r, (cd*)x);
+}
+
+// x = Dhat x_o for the fine operator of a field [V][12] (even part ignored).
+int or_schur_apply(const int* L, double m0, int antiperiodic, const double* U, const double* C, const double* in,
+                   double* out) {
+  WilsonClover D;
+  D.lat = Lattice(L);
+  D.ns = 12;
+  D.m0 = m0;
+  D.antiperiodic = antiperiodic != 0;
+  D.U.assign((const cd*)U, (const cd*)U + D.lat.V * 36);
+  D.C.assign((const cd*)C, (const cd*)C + D.lat.V * 144);
+  cvec Ainv;
+  if (clover_inverse(D, Ainv)) return 1;
+  schur_apply(D, Ainv, (const cd*)in, (cd*)out);
+  return 0;
+}
+
+// A(x)^{-1} per site, [V][12][12].
+int or_clover_inverse(const int* L, double m0, const double* C, double* out) {
+  WilsonClover D;
+  D.lat = Lattice(L);
+  D.ns = 12;
+  D.m0 = m0;
+  D.C.assign((const cd*)C, (const cd*)C + D.lat.V * 144);
+  cvec Ainv;
+  const int st = clover_inverse(D, Ainv);
+  std::copy(Ainv.begin(), Ainv.end(), (cd*)out);
+  return st;
+}
+
+// Even-odd preconditioned outer solve: FGMRES(outer_restart) on Dhat with the
+// MG cycle embedded as its preconditioner (Mhat r_o = odd part of
+// M (0_e, r_o), since the odd part of D^{-1} (0_e, r_o) is Dhat^{-1} r_o),
+// converged when |bhat - Dhat x_o| <= outer_tol |b|, which is the full true
+// residual once x_e is reconstructed.  x holds the initial guess (its odd part
+// is used).
+int or_mg_solve_eo(void* h, const double* b, double* x, int* iters, double* relres) {
+  Hierarchy* H = (Hierarchy*)h;
+  const WilsonClover& D = H->fine;
+  const long n = D.size(), V = D.lat.V;
+  cvec Ainv;
+  if (clover_inverse(D, Ainv)) return 1;
+  const cd* bb = (const cd*)b;
+  cd* xx = (cd*)x;
+  auto mask_odd = [&](cd* v) {
+    for (long s = 0; s < V; ++s)
+      if (site_parity(D.lat, s) == 0)
+        for (int k = 0; k < 12; ++k) v[s * 12 + k] = 0.0;
+  };
+  // bhat = b_o - H_oe A_ee^{-1} b_e
+  cvec t(n), w(n), bh(n), xo(xx, xx + n);
+  site_apply_masked(D, Ainv, 0, bb, t.data());
+  hopping(D, t.data(), w.data());
+  for (long i = 0; i < n; ++i) bh[i] = bb[i] - w[i];
+  mask_odd(bh.data());
+  mask_odd(xo.data());
+  LinOp A = [&](const cd* i, cd* o) { schur_apply(D, Ainv, i, o); };
+  LinOp M = [&](const cd* i, cd* o) {
+    cvec in(i, i + n);
+    mask_odd(in.data());
+    if (H->lv.empty()) std::copy(in.begin(), in.end(), o);
+    else cycle(*H, 0, in.data(), o);
+    mask_odd(o);
+  };
+  const double bn = norm(n, bb), bhn = norm(n, bh.data());
+  int total = 0;
+  double rel = 0.0;
+  cvec r(n);
+  for (;;) {
+    schur_apply(D, Ainv, xo.data(), r.data());
+    for (long i = 0; i < n; ++i) r[i] = bh[i] - r[i];
+    rel = bn > 0 ? norm(n, r.data()) / bn : 0.0;
+    if (rel <= H->p.outer_tol || total >= H->p.outer_maxit) break;
+    const int budget = H->p.outer_maxit - total;
+    KrylovResult kr = gmres_core(A, &M, n, bh.data(), xo.data(), H->p.outer_restart,
+                                 std::min(budget, H->p.outer_restart), H->p.outer_tol * bn / bhn, 0, false);
+    total += kr.iters;
+    if (kr.iters == 0) break;
+  }
+  // x_e = A_ee^{-1} (b_e - H_eo x_o)
+  hopping(D, xo.data(), t.data());
+  for (long i = 0; i < n; ++i) w[i] = bb[i] - t[i];
+  site_apply_masked(D, Ainv, 0, w.data(), t.data());
+  for (long i = 0; i < n; ++i) xx[i] = xo[i] + t[i];
+  // the full true residual
+  D.apply(xx, r.data());
+  for (long i = 0; i < n; ++i) r[i] = bb[i] - r[i];
+  rel = bn > 0 ? norm(n, r.data()) / bn : 0.0;
+  if (iters) *iters = total;
+  if (relres) *relres = rel;
+  return rel <= H->p.outer_tol ? 0 : 7;
 }
 
 // Outer solve (Sec. 2.1): flexible GMRES(outer_restart) on D, preconditioned by
