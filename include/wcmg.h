@@ -99,7 +99,11 @@ typedef struct {
                               domains; needs an even number of aggregates in every direction and at most 256
                               sites per aggregate).  Coarser levels always use MR. */
   int32_t sap_block_iters; /* MR steps per SAP domain solve (default 4) */
-  int32_t reserved[2];
+  int32_t even_odd;        /* 1: wcmg_solve runs the outer FGMRES on the even-odd Schur complement
+                              Dhat = A_oo - H_oe A_ee^{-1} H_eo (Sec. 2.1 and Sec. 4 name red-black
+                              preconditioning; see wcmg_apply_schur) with the MG cycle embedded as its
+                              preconditioner, then reconstructs the even sites */
+  int32_t reserved[1];
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;
@@ -290,6 +294,16 @@ int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
  * timed launches and their total duration in milliseconds, then reset. */
 int wcmg_profile_enable(wcmg_ctx* ctx, const char* family, int enable);
 int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, double* total_ms);
+
+/* Even-odd Schur complement of the fine operator (Sec. 2.1 and Sec. 4 name
+ * red-black preconditioning without writing it down).  Reading: sites are
+ * even or odd by the parity of x+y+z+t; with A = (4 + m0) + C and the hopping
+ * terms H_eo, H_oe between the parities, out = Dhat in with
+ * Dhat = A_oo - H_oe A_ee^{-1} H_eo acting on the odd sites: the even part of
+ * `in` is ignored and that of `out` set to zero.  FP64 fields [nrhs][V][4][3]
+ * (complex128, canonical layout, device pointers).  WCMG_ERR_BREAKDOWN when a
+ * chirality block of A is singular.  Synchronises the stream. */
+int wcmg_apply_schur(wcmg_ctx* ctx, const void* in, void* out, int nrhs);
 
 /* SAP on the fine operator (Sec. 2.1 and Sec. 4 name SAP, the smoother
  * DDalphaAMG normally uses, without defining it).  Reading: the domains are the

@@ -222,6 +222,24 @@ int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks) {
   });
 }
 
+int wcmg_apply_schur(wcmg_ctx* ctx, const void* in, void* out, int nrhs) {
+  return guarded(ctx, [&](Context& c) {
+    require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    c.eo_prepare();
+    const long V = c.geo[0].V, nn = c.n(0);
+    cd64* a = c.buf<cd64>("abi_a64", nn);
+    cd64* bb = c.buf<cd64>("abi_b64", nn);
+    const unsigned char* par = (const unsigned char*)c.par0.p;
+    for (int k = 0; k < nrhs; ++k) {
+      launch_pack_fermion<double, double>((const cd64*)in + k * nn, c.perm0.as<int>(), V, 1, a, c.stream);
+      launch_eo_local<double>(a, nullptr, a, nullptr, par, 1, 2, V, c.stream);  // even part dropped
+      c.schur64(a, bb, nullptr);
+      launch_unpack_fermion<double, double>(bb, c.perm0.as<int>(), V, 1, (cd64*)out + k * nn, c.stream);
+    }
+    WCMG_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
 int wcmg_sap(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int cycles, int prec) {
   return guarded(ctx, [&](Context& c) {
     check_prec(prec, false);
@@ -369,8 +387,37 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
       launch_pack_fermion<double, double>((const cd64*)b + k * nn, c.perm0.as<int>(), V, 1, b64, c.stream);
       launch_pack_fermion<double, double>((const cd64*)x + k * nn, c.perm0.as<int>(), V, 1, x64, c.stream);
       GmresState& G = c.gmres_state("outer", c.p.outer_restart, nn, 0, true);
-      int its = c.gmres<double>(G, A, &M, b64, x64, false, c.p.outer_restart, c.p.outer_maxit, c.p.outer_tol, 0,
-                                false, nullptr, 1);
+      int its = 0;
+      if (c.p.even_odd) {
+        // Schur complement on the odd sites: bhat = b_o - H_oe A_ee^{-1} b_e,
+        // FGMRES on Dhat from the odd part of x (tolerance scaled so that the
+        // residual is measured against |b|), then x_e = A_ee^{-1} (b_e - H_eo x_o)
+        c.eo_prepare();
+        const unsigned char* par = (const unsigned char*)c.par0.p;
+        cd64* bh = c.buf<cd64>("eo_bhat", nn);
+        cd64* t = c.buf<cd64>("eo_s", nn);
+        launch_eo_local<double>(b64, nullptr, t, c.clovinv64.as<double>(), par, 0, 0, V, c.stream);
+        c.apply_op<double>(0, t, r64, 1, nullptr, 0x1fe);
+        launch_eo_local<double>(b64, r64, bh, nullptr, par, 1, 4, V, c.stream);
+        launch_eo_local<double>(x64, nullptr, x64, nullptr, par, 1, 2, V, c.stream);
+        std::function<void(const cd64*, cd64*, const int*)> Ah = [&c](const cd64* i, cd64* o, const int* rn) {
+          c.schur64(i, o, rn);
+        };
+        std::function<void(const cd64*, cd64*, const int*)> Mh = [&c, &M, V, par](const cd64* i, cd64* o,
+                                                                                 const int* rn) {
+          M(i, o, rn);
+          launch_eo_local<double>(o, nullptr, o, nullptr, par, 1, 2, V, c.stream);
+        };
+        const double bn = std::sqrt(c.norm2_host<double>(b64, nn)), bhn = std::sqrt(c.norm2_host<double>(bh, nn));
+        const double tol = bhn > 0 ? c.p.outer_tol * bn / bhn : c.p.outer_tol;
+        its = c.gmres<double>(G, Ah, &Mh, bh, x64, false, c.p.outer_restart, c.p.outer_maxit, tol, 0, false, nullptr,
+                              1);
+        c.apply_op<double>(0, x64, t, 1, nullptr, 0x1fe);
+        launch_eo_local<double>(b64, t, x64, c.clovinv64.as<double>(), par, 0, 3, V, c.stream);
+      } else {
+        its = c.gmres<double>(G, A, &M, b64, x64, false, c.p.outer_restart, c.p.outer_maxit, c.p.outer_tol, 0,
+                              false, nullptr, 1);
+      }
       // true residual in FP64
       c.apply_op<double>(0, x64, r64, 1, nullptr);
       launch_sub<double>(r64, b64, r64, nn, nullptr, c.stream);

@@ -183,6 +183,9 @@ struct Context {
   DevBuf U_lex, clover_lex;     // canonical copies (FP64)
   DevBuf U64, U32, clov64, clov32;
   bool gauge_set = false, setup_done = false;
+  // even-odd preconditioning: site parity (device order) and A^{-1} (packed)
+  DevBuf par0, clovinv64, clovinv32;
+  bool eo_ready = false;
   // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
   DevBuf sap_doms;
   long sap_ndoms = 0;
@@ -240,6 +243,10 @@ struct Context {
   // `cycles` SAP cycles on D x = b at level 0 for nrhs fields (run flags with
   // stride rs; run may be null)
   void sap_prepare();
+  // even-odd: parity table and A^{-1}; y = Dhat x on the odd sites (FP64,
+  // x's even part must be zero, y's even part is set to zero)
+  void eo_prepare();
+  void schur64(const cd64* x, cd64* y, const int* run);
   template <typename R>
   void sap(const cplx<R>* b, cplx<R>* x, int cycles, int nrhs, const int* run, int rs);
   template <typename R>

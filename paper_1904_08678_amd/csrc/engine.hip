@@ -180,6 +180,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   require(p.coarse_points == 0 || p.coarse_points == 5 || p.coarse_points == 9, WCMG_ERR_ARG,
           "coarse_points must be 5 or 9");
   require(p.smoother == 0 || p.smoother == 1, WCMG_ERR_ARG, "smoother must be 0 (MR) or 1 (SAP)");
+  require(p.even_odd == 0 || p.even_odd == 1, WCMG_ERR_ARG, "even_odd must be 0 or 1");
   require(p.smoother == 0 || p.sap_block_iters >= 1, WCMG_ERR_ARG, "sap_block_iters must be >= 1");
   require(p.outer_restart >= 1 && p.outer_restart <= 40 && p.coarse_restart >= 1 && p.coarse_restart <= 40 &&
               p.kcycle_maxit >= 1 && p.kcycle_maxit <= 40,
@@ -396,6 +397,7 @@ void Context::set_clover(const cd64* blocks) {
 }
 
 void Context::pack_clover() {
+  eo_ready = false;  // A^{-1} follows the clover term
   launch_pack_clover<double>(clover_lex.as<cd64>(), perm0.as<int>(), geo[0].V, p.m0, clov64.as<double>(), stream);
   launch_pack_clover<float>(clover_lex.as<cd64>(), perm0.as<int>(), geo[0].V, p.m0, clov32.as<float>(), stream);
 }
@@ -661,6 +663,44 @@ void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
   if (l == 0 && p.smoother == 1) sap<R>(r, x, p.post_smooth, 1, run, 0);
   else mr<R>(l, r, x, false, p.post_smooth, run);
   cycles++;
+}
+
+// Even-odd preconditioning (Sec. 2.1, Sec. 4: red-black preconditioning):
+// the site parity table in device order and A^{-1} per site.
+void Context::eo_prepare() {
+  if (eo_ready) return;
+  require(gauge_set, WCMG_ERR_STATE, "gauge field not set");
+  const LevelGeom& G = geo[0];
+  std::vector<unsigned char> par(G.V);
+  for (long s = 0; s < G.V; ++s) {
+    int x[4];
+    lex_coords(G.perm[s], G.L, x);
+    par[s] = (unsigned char)((x[0] + x[1] + x[2] + x[3]) & 1);
+  }
+  par0.alloc(G.V);
+  WCMG_HIP(hipMemcpy(par0.p, par.data(), G.V, hipMemcpyHostToDevice));
+  clovinv64.alloc(clov64.bytes);
+  clovinv32.alloc(clov32.bytes);
+  int* bad = (int*)(scratch64.as<cd64>() + 32);
+  WCMG_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+  launch_clover_invert(clov64.as<double>(), G.V, clovinv64.as<double>(), clovinv32.as<float>(), bad, stream);
+  WCMG_HIP(hipMemcpyAsync(pinned + 8, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  sync();
+  require(pinned[8] == 0, WCMG_ERR_BREAKDOWN, "singular clover block: (4 + m0) + C has no inverse");
+  eo_ready = true;
+}
+
+// y = A_oo x_o - H_oe A_ee^{-1} H_eo x_o: the hopping-only Dslash twice, with
+// A^{-1} on the even sites between them and A on the odd sites at the end.
+void Context::schur64(const cd64* x, cd64* y, const int* run) {
+  const long V = geo[0].V, nn = n(0);
+  cd64* t = buf<cd64>("eo_t", nn);
+  cd64* u = buf<cd64>("eo_u", nn);
+  const unsigned char* par = (const unsigned char*)par0.p;
+  apply_op<double>(0, x, t, 1, run, 0x1fe);
+  launch_eo_local<double>(t, nullptr, u, clovinv64.as<double>(), par, 0, 0, V, stream);
+  apply_op<double>(0, u, t, 1, run, 0x1fe);
+  launch_eo_local<double>(x, t, y, clov64.as<double>(), par, 1, 1, V, stream);
 }
 
 // SAP domains: the level-0 aggregates, coloured by the parity of their coarse

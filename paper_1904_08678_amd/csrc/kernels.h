@@ -29,6 +29,14 @@ int wilson_blocks(long V);
 void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* clov, const int* nbr, long V, int nrhs,
                         const int* run, int rs, cd64* dots, hipStream_t st);
 
+// ---- even-odd preconditioning (evenodd.hip): A^{-1} per site (packed like A,
+// FP64 and FP32 copies; bad set on a vanishing pivot) and parity-masked
+// site-local operations (modes in evenodd.hip)
+void launch_clover_invert(const double* A, long V, double* inv64, float* inv32, int* bad, hipStream_t st);
+template <typename R>
+void launch_eo_local(const cplx<R>* in, const cplx<R>* aux, cplx<R>* out, const R* B, const unsigned char* par,
+                     int keep, int mode, long V, hipStream_t st);
+
 // ---- SAP smoother (sap.hip): one colour of domains; x, b [nrhs][12][V];
 // doms: aggregate indices of the colour; A: sites per domain (<= 256)
 template <typename R>

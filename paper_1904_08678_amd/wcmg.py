@@ -38,7 +38,7 @@ class Params(C.Structure):
         ("outer_restart", C.c_int32), ("outer_maxit", C.c_int32), ("outer_tol", C.c_double),
         ("cycle_prec", C.c_int32), ("coarse_store_prec", C.c_int32), ("setup_prec", C.c_int32),
         ("coarse_points", C.c_int32), ("smoother", C.c_int32), ("sap_block_iters", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("even_odd", C.c_int32), ("reserved", C.c_int32 * 1),
     ]
 
 
@@ -251,6 +251,13 @@ class Context:
         nrhs = coarse.numel() // (self.sites(level + 1) * self.ns[level + 1])
         out = torch.empty((nrhs, self.sites(level), self.ns[level]), dtype=coarse.dtype, device="cuda")
         self._chk(lib().wcmg_prolong(self.h, level, _ptr(coarse), _ptr(out), nrhs, prec))
+        return out
+
+    def apply_schur(self, x: torch.Tensor) -> torch.Tensor:
+        """wcmg_apply_schur: the even-odd Schur complement on the odd sites (FP64)."""
+        nrhs = x.numel() // (self.V * 12)
+        out = torch.empty_like(x)
+        self._chk(lib().wcmg_apply_schur(self.h, _ptr(x), _ptr(out), nrhs))
         return out
 
     def sap(self, b: torch.Tensor, x: torch.Tensor, cycles: int, prec=None) -> torch.Tensor:
