@@ -266,6 +266,27 @@ def sap_smoother(w, torch, wl, Ud, startd, bd, iters=4):
     return out
 
 
+def even_odd(w, torch, wl, Ud, startd, bd):
+    """The benchmark solve with the outer FGMRES on the even-odd Schur
+    complement (MR(4) and SAP(2 cycles) post-smoothing), FP64 outer and FP32
+    cycle as in the main line."""
+    out = {}
+    for name, extra in (("mr4", {}), ("sap2", dict(smoother=1, sap_block_iters=4, post_smooth=2))):
+        kw = dict(dims=wl["L"], m0=wl["m0"], c_sw=wl["csw"], n_levels=2, block=(wl["block"],), n_vec=(wl["nv"],),
+                  relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000,
+                  cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32, even_odd=1, **extra)
+        ctx = w.Context(**kw)
+        ctx.set_gauge(Ud)
+        ctx.set_null_vectors(0, startd)
+        ctx.setup()
+        x, i1, st = ctx.solve(bd)
+        x, i2, st2 = ctx.solve(bd)
+        out[name] = {"solve_s": min(i1[0]["t_solve_s"], i2[0]["t_solve_s"]), "outer_iters": i1[0]["outer_iters"],
+                     "true_rel_res": i1[0]["true_rel_res"], "converged": st == 0 and st2 == 0}
+        del ctx
+    return out
+
+
 def batched_point_sources(w, torch, wl, fp64=True):
     """Twelve point sources on the 24^3 x 48 lattice: one batched solve (matrix-core
     coarse apply; with and without the HIP-graph cycle; per-row coarse kernel for
@@ -679,6 +700,8 @@ def main():
     if not args.no_sap:
         print("[bench] SAP smoother", file=sys.stderr, flush=True)
         extra["sap_smoother"] = sap_smoother(w, torch, wl, Ud, startd, bd)
+        print("[bench] even-odd outer solve", file=sys.stderr, flush=True)
+        extra["even_odd"] = even_odd(w, torch, wl, Ud, startd, bd)
     if not args.no_mk:
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)

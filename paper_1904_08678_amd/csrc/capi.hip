@@ -386,35 +386,51 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
       c.cycles = 0;
       launch_pack_fermion<double, double>((const cd64*)b + k * nn, c.perm0.as<int>(), V, 1, b64, c.stream);
       launch_pack_fermion<double, double>((const cd64*)x + k * nn, c.perm0.as<int>(), V, 1, x64, c.stream);
-      GmresState& G = c.gmres_state("outer", c.p.outer_restart, nn, 0, true);
       int its = 0;
       if (c.p.even_odd) {
         // Schur complement on the odd sites: bhat = b_o - H_oe A_ee^{-1} b_e,
-        // FGMRES on Dhat from the odd part of x (tolerance scaled so that the
-        // residual is measured against |b|), then x_e = A_ee^{-1} (b_e - H_eo x_o)
+        // FGMRES on Dhat over the odd sites only (compact vectors, half the
+        // outer vector traffic; the operator and the preconditioner scatter to
+        // and gather from full-length fields), tolerance scaled so that the
+        // residual is measured against |b|, then x_e = A_ee^{-1} (b_e - H_eo x_o)
         c.eo_prepare();
         const unsigned char* par = (const unsigned char*)c.par0.p;
+        const long Vh = c.eo_half, nh = 12 * Vh;
+        const int* odd = c.eo_odd.as<int>();
+        const int* pos = c.eo_pos.as<int>();
         cd64* bh = c.buf<cd64>("eo_bhat", nn);
         cd64* t = c.buf<cd64>("eo_s", nn);
+        cd64* fi = c.buf<cd64>("eo_fin", nn);
+        cd64* fo = c.buf<cd64>("eo_fout", nn);
+        cd64* bc = c.buf<cd64>("eo_bc", nh);
+        cd64* xc = c.buf<cd64>("eo_xc", nh);
         launch_eo_local<double>(b64, nullptr, t, c.clovinv64.as<double>(), par, 0, 0, V, c.stream);
         c.apply_op<double>(0, t, r64, 1, nullptr, 0x1fe);
         launch_eo_local<double>(b64, r64, bh, nullptr, par, 1, 4, V, c.stream);
-        launch_eo_local<double>(x64, nullptr, x64, nullptr, par, 1, 2, V, c.stream);
-        std::function<void(const cd64*, cd64*, const int*)> Ah = [&c](const cd64* i, cd64* o, const int* rn) {
-          c.schur64(i, o, rn);
+        launch_eo_gather<double>(bh, bc, odd, V, Vh, c.stream);
+        launch_eo_gather<double>(x64, xc, odd, V, Vh, c.stream);
+        std::function<void(const cd64*, cd64*, const int*)> Ah = [&c, fi, fo, odd, pos, par, V, Vh](
+                                                                      const cd64* i, cd64* o, const int* rn) {
+          launch_eo_scatter<double>(i, fi, pos, par, V, Vh, c.stream);
+          c.schur64(fi, fo, rn);
+          launch_eo_gather<double>(fo, o, odd, V, Vh, c.stream);
         };
-        std::function<void(const cd64*, cd64*, const int*)> Mh = [&c, &M, V, par](const cd64* i, cd64* o,
-                                                                                 const int* rn) {
-          M(i, o, rn);
-          launch_eo_local<double>(o, nullptr, o, nullptr, par, 1, 2, V, c.stream);
+        std::function<void(const cd64*, cd64*, const int*)> Mh = [&c, &M, fi, fo, odd, pos, par, V, Vh](
+                                                                      const cd64* i, cd64* o, const int* rn) {
+          launch_eo_scatter<double>(i, fi, pos, par, V, Vh, c.stream);
+          M(fi, fo, rn);
+          launch_eo_gather<double>(fo, o, odd, V, Vh, c.stream);
         };
-        const double bn = std::sqrt(c.norm2_host<double>(b64, nn)), bhn = std::sqrt(c.norm2_host<double>(bh, nn));
+        const double bn = std::sqrt(c.norm2_host<double>(b64, nn)), bhn = std::sqrt(c.norm2_host<double>(bc, nh));
         const double tol = bhn > 0 ? c.p.outer_tol * bn / bhn : c.p.outer_tol;
-        its = c.gmres<double>(G, Ah, &Mh, bh, x64, false, c.p.outer_restart, c.p.outer_maxit, tol, 0, false, nullptr,
+        GmresState& G = c.gmres_state("outer_eo", c.p.outer_restart, nh, 0, true);
+        its = c.gmres<double>(G, Ah, &Mh, bc, xc, false, c.p.outer_restart, c.p.outer_maxit, tol, 0, false, nullptr,
                               1);
+        launch_eo_scatter<double>(xc, x64, pos, par, V, Vh, c.stream);
         c.apply_op<double>(0, x64, t, 1, nullptr, 0x1fe);
         launch_eo_local<double>(b64, t, x64, c.clovinv64.as<double>(), par, 0, 3, V, c.stream);
       } else {
+        GmresState& G = c.gmres_state("outer", c.p.outer_restart, nn, 0, true);
         its = c.gmres<double>(G, A, &M, b64, x64, false, c.p.outer_restart, c.p.outer_maxit, c.p.outer_tol, 0,
                               false, nullptr, 1);
       }

@@ -185,6 +185,8 @@ struct Context {
   bool gauge_set = false, setup_done = false;
   // even-odd preconditioning: site parity (device order) and A^{-1} (packed)
   DevBuf par0, clovinv64, clovinv32;
+  DevBuf eo_odd, eo_pos;  // odd sites in device order and their compact positions
+  long eo_half = 0;       // number of odd sites
   bool eo_ready = false;
   // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
   DevBuf sap_doms;

@@ -679,6 +679,16 @@ void Context::eo_prepare() {
   }
   par0.alloc(G.V);
   WCMG_HIP(hipMemcpy(par0.p, par.data(), G.V, hipMemcpyHostToDevice));
+  std::vector<int> odd, pos(G.V, 0);
+  for (long s = 0; s < G.V; ++s)
+    if (par[s]) {
+      pos[s] = (int)odd.size();
+      odd.push_back((int)s);
+    }
+  require(2 * (long)odd.size() == G.V, WCMG_ERR_DIMS, "even-odd preconditioning needs as many odd as even sites");
+  upload(eo_odd, odd);
+  upload(eo_pos, pos);
+  eo_half = (long)odd.size();
   clovinv64.alloc(clov64.bytes);
   clovinv32.alloc(clov32.bytes);
   int* bad = (int*)(scratch64.as<cd64>() + 32);

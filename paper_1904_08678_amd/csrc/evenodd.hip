@@ -200,6 +200,45 @@ __global__ void __launch_bounds__(256) k_eo_local(const cplx<R>* in, const cplx<
   }
 }
 
+// Odd-site compaction: compact[k][j] = full[k][odd[j]] (gather), and
+// full[k][s] = compact[k][pos[s]] on odd sites, 0 on even ones (scatter).
+template <typename R>
+__global__ void __launch_bounds__(256) k_eo_gather(const cplx<R>* __restrict__ full, cplx<R>* __restrict__ compact,
+                                                    const int* __restrict__ odd, long V, long Vh) {
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= Vh) return;
+  const long s = odd[j];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) compact[(long)k * Vh + j] = full[(long)k * V + s];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_eo_scatter(const cplx<R>* __restrict__ compact, cplx<R>* __restrict__ full,
+                                                     const int* __restrict__ pos, const unsigned char* __restrict__ par,
+                                                     long V, long Vh) {
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  const bool odd = par[s] == 1;
+  const long j = odd ? pos[s] : 0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) full[(long)k * V + s] = odd ? compact[(long)k * Vh + j] : mkc((R)0, (R)0);
+}
+
+template <typename R>
+void launch_eo_gather(const cplx<R>* full, cplx<R>* compact, const int* odd, long V, long Vh, hipStream_t st) {
+  hipLaunchKernelGGL(k_eo_gather<R>, dim3(nblocks(Vh)), dim3(kBlock), 0, st, full, compact, odd, V, Vh);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_eo_scatter(const cplx<R>* compact, cplx<R>* full, const int* pos, const unsigned char* par, long V,
+                       long Vh, hipStream_t st) {
+  hipLaunchKernelGGL(k_eo_scatter<R>, dim3(nblocks(V)), dim3(kBlock), 0, st, compact, full, pos, par, V, Vh);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_eo_gather<double>(const cd64*, cd64*, const int*, long, long, hipStream_t);
+template void launch_eo_scatter<double>(const cd64*, cd64*, const int*, const unsigned char*, long, long,
+                                        hipStream_t);
+
 void launch_clover_invert(const double* A, long V, double* inv64, float* inv32, int* bad, hipStream_t st) {
   hipLaunchKernelGGL(k_clover_invert, dim3(nblocks(2 * V, 128)), dim3(128), 0, st, A, V, inv64, inv32, bad);
   WCMG_CHECK_LAUNCH();

@@ -36,6 +36,13 @@ void launch_clover_invert(const double* A, long V, double* inv64, float* inv32, 
 template <typename R>
 void launch_eo_local(const cplx<R>* in, const cplx<R>* aux, cplx<R>* out, const R* B, const unsigned char* par,
                      int keep, int mode, long V, hipStream_t st);
+// odd-site compaction ([12][Vh] with Vh = V/2; odd: device index of the j-th
+// odd site; pos: the inverse on odd sites)
+template <typename R>
+void launch_eo_gather(const cplx<R>* full, cplx<R>* compact, const int* odd, long V, long Vh, hipStream_t st);
+template <typename R>
+void launch_eo_scatter(const cplx<R>* compact, cplx<R>* full, const int* pos, const unsigned char* par, long V,
+                       long Vh, hipStream_t st);
 
 // ---- SAP smoother (sap.hip): one colour of domains; x, b [nrhs][12][V];
 // doms: aggregate indices of the colour; A: sites per domain (<= 256)
