@@ -44,7 +44,9 @@
  * of coarse-operator blocks only; vectors and accumulation stay FP32).
  *
  * Errors: every call returns a wcmg_status; nothing throws or aborts.
- * wcmg_last_error() gives a message for the last failing call on a context.
+ * wcmg_last_error() gives a message for the last failing call on a context
+ * (when no call has failed: the report of the last coarsest-GMRES solve that
+ * was redone after a grid-barrier timeout, see wcmg_timers, or "").
  */
 #ifndef WCMG_H
 #define WCMG_H
@@ -278,7 +280,10 @@ int wcmg_tune_table(wcmg_ctx* ctx, char* buf, int len, int* needed);
 int wcmg_tune_load(wcmg_ctx* ctx, const char* json);
 
 /* Per-phase timers in seconds: [0] setup total, [1] relaxation, [2] Gram-Schmidt,
- * [3] coarsening, [4] refinement, [5] last solve.  n entries are written. */
+ * [3] coarsening, [4] refinement, [5] last solve; [6] is a count: coarsest
+ * GMRES solves that the single-launch form handed back to the multi-kernel
+ * form after a grid-barrier timeout (0 in a healthy run).  n entries (<= 8)
+ * are written. */
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
 
 /* Kernel timing: when enabled, launches of the named kernel family are

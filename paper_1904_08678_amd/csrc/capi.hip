@@ -99,7 +99,11 @@ int wcmg_destroy(wcmg_ctx* ctx) {
   return WCMG_OK;
 }
 
-const char* wcmg_last_error(const wcmg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+const char* wcmg_last_error(const wcmg_ctx* ctx) {
+  if (!ctx) return g_create_error.c_str();
+  if (ctx->err.empty() && ctx->c && !ctx->c->cgp_last_report.empty()) return ctx->c->cgp_last_report.c_str();
+  return ctx->err.c_str();
+}
 
 int wcmg_set_gauge(wcmg_ctx* ctx, const void* U) {
   return guarded(ctx, [&](Context& c) {
@@ -679,7 +683,7 @@ int wcmg_tune_load(wcmg_ctx* ctx, const char* json) {
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n) {
   return guarded(ctx, [&](Context& c) {
     require(out_host != nullptr && n >= 0, WCMG_ERR_ARG, "bad output");
-    for (int i = 0; i < n && i < 8; ++i) out_host[i] = c.timers[i];
+    for (int i = 0; i < n && i < 8; ++i) out_host[i] = i == 6 ? (double)c.cgp_fallbacks : c.timers[i];
   });
 }
 

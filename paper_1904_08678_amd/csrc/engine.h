@@ -191,6 +191,10 @@ struct Context {
   // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
   DevBuf sap_doms;
   long sap_ndoms = 0;
+  // cooperative coarsest GMRES: solves redone by the multi-kernel form after a
+  // grid-barrier timeout, and the last timeout's report
+  long cgp_fallbacks = 0;
+  std::string cgp_last_report;
   // workspaces
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::map<std::string, std::unique_ptr<GmresState>> gm;

@@ -325,9 +325,11 @@ class Context:
         self._chk(lib().wcmg_tune_load(self.h, json.dumps(table).encode()))
 
     def timers(self):
-        out = (C.c_double * 6)()
-        self._chk(lib().wcmg_timers(self.h, out, 6))
-        return dict(zip(["setup", "relax", "gram_schmidt", "coarsen", "refine", "solve"], list(out)))
+        out = (C.c_double * 7)()
+        self._chk(lib().wcmg_timers(self.h, out, 7))
+        d = dict(zip(["setup", "relax", "gram_schmidt", "coarsen", "refine", "solve"], list(out)[:6]))
+        d["coarse_solve_fallbacks"] = int(out[6])
+        return d
 
     def profile(self, family, enable=True):
         self._chk(lib().wcmg_profile_enable(self.h, family.encode(), int(enable)))

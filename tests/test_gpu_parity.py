@@ -379,6 +379,48 @@ def test_fused_coarse_gmres_matches_generic_path(fixed):
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
 
 
+@pytest.mark.parametrize("L,block,store", [((8, 8, 8, 8), (4, 4, 4, 4), "f32"), ((8, 8, 8, 8), (4, 4, 4, 4), "bf16"),
+                                           ((16, 16, 16, 16), (4, 4, 4, 4), "f32"),
+                                           ((16, 16, 16, 32), (4, 4, 4, 4), "f32"), ((8, 8, 6, 6), (2, 2, 2, 2), "f32")])
+def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store):
+    """The coarsest GMRES as one cooperative launch (blocks resident in LDS,
+    grid barriers) against the multi-kernel form (reserved[0] flag 4): the
+    FP32 cycle with 10 fixed coarse iterations agrees to FP32 rounding and
+    repeats bit for bit (every grid reduction is summed in a fixed order, so
+    a repeat that differs means a workgroup read data of the wrong phase),
+    and mixed solves agree in outer and coarse iteration counts (within one
+    step).  Coarse lattices of 16, 256, 512 and 324 sites (the last with a
+    partly filled final workgroup)."""
+    w = wc()
+    nv = 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 821)
+    start = syn.complex_gaussian((nv, V, 12), 822)
+    r = syn.complex_gaussian((V, 4, 3), 823)
+    sp = w.F32 if store == "f32" else w.BF16
+    outs, infos = [], []
+    for flags in (0, 4):
+        kw = dict(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), cycle_prec=w.F32, coarse_store_prec=sp,
+                  setup_prec=w.F32, reserved=(flags,))
+        ctx = w.Context(coarse_fixed_iters=10, **kw)
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        outs.append(host(ctx.cycle(dev(r.astype(np.complex128)))))
+        assert np.array_equal(host(ctx.cycle(dev(r.astype(np.complex128)))), outs[-1])
+        ctx = w.Context(**kw)
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        x, info, st = ctx.solve(dev(r))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        assert ctx.timers()["coarse_solve_fallbacks"] == 0, w.lib().wcmg_last_error(ctx.h)
+        infos.append(info[0])
+    assert rel(outs[0], outs[1]) < 2e-5
+    assert abs(infos[0]["outer_iters"] - infos[1]["outer_iters"]) <= 1
+    assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
+
+
 @pytest.mark.parametrize("Lc,nb,nrhs", [((2, 2, 2, 2), 8, 12), ((3, 2, 2, 4), 16, 5), ((4, 4, 4, 8), 24, 12),
                                          ((2, 3, 2, 2), 24, 16), ((3, 3, 2, 2), 32, 12), ((2, 2, 2, 2), 40, 17)])
 def test_coarse_apply_matrix_cores_parity(Lc, nb, nrhs):
