@@ -1,136 +1,173 @@
 // The coarsest-level GMRES (Sec. 2.1: GMRES is the coarse-grid solver) as one
 // cooperative launch for a whole solve, when the coarse operator fits the
 // chip's LDS: each workgroup owns at most two coarse sites, loads their nine
-// blocks into LDS once, and keeps them there for every matrix-vector product
-// of every Arnoldi step and restart.  The steps are those of the fused
-// four-kernel form (coarse_gmres.hip): w = A u / |u| with v_j = u / |u|,
-// classical Gram-Schmidt applied twice, |w|^2, Givens rotation; the kernel
-// boundaries between them become grid barriers, and every workgroup reduces
-// the per-workgroup partials (double-buffered by phase) itself in a fixed
-// order, so every control decision (convergence, iteration limit, breakdown)
-// is taken identically by all workgroups.  Workgroup 0 keeps the Hessenberg matrix, solves for y at
-// the end of a restart cycle and writes the state words.
+// blocks into LDS once and keeps them there for every matrix-vector product
+// of every Arnoldi step and restart.  The Krylov basis V and its image
+// Z = A V stay in LDS too, for the workgroup's own rows.
 //
-// Grid barrier: a counter and a generation word in device memory, with
-// agent-scope release/acquire fences around them; a waiting workgroup gives
-// up after a wall-clock timeout (the error word is set, every later barrier
-// passes at once and the host redoes the solve with the multi-kernel form),
-// so a fault in the launch configuration cannot hang the device.
+// Each Arnoldi step takes one grid-wide reduction, of h1 = V^H p_j and
+// |p_j|^2 together, where p_j = A v_j - s v_j with the shift s = Re h_00 of
+// the restart cycle (s = 0 for the first step): the coarse operator is
+// dominated by its diagonal, so A v_j lies mostly along v_j, and projecting
+// p_j instead spans the same Krylov space with far less cancellation.  Then
+// w1 = p_j - V h1 with |w1|^2 = |p_j|^2 - |h1|^2 (V orthonormal), and
+// A w1 = A p_j - Z h1 (Z = A V at the own rows), where A p_j needs p_j at the
+// neighbouring sites, which that reduction's barrier has made visible.
+// Gram-Schmidt is repeated (a second reduction, of h2 = V^H w1 and |w1|^2)
+// only when |w1|^2 < |p_j|^2 / 2, i.e. when the first pass cancelled more
+// than half of p_j's norm (the criterion of Daniel, Gragg, Kaufman and
+// Stewart); A w2 = A w1 - Z h2.  The Hessenberg column of A is
+// h1 + s e_j (+ h2), and v_{j+1} = w / |w|, z_{j+1} = A w / |w|.
+// Every workgroup sums the per-workgroup partials itself in a fixed order,
+// so every workgroup holds bit-identical reductions, Givens rotations,
+// control decisions (convergence, iteration limit, breakdown,
+// reorthogonalisation) and, at the end of a restart cycle, the same
+// least-squares solution y.
+//
+// Grid barrier: every workgroup waits for every other's flag (a phase number
+// in its own 128-byte line), with one agent-scope release fence before the
+// flag is raised and one acquire fence after the wait, both taken by one
+// thread for the whole workgroup after every wave's stores have completed
+// (on this chip each fence is a whole-L2 write-back or invalidate).  After
+// the barrier, data that other workgroups wrote (partials, the vectors the
+// stencil reads) is read with plain loads: the invalidate has dropped stale
+// lines from this XCD's L2, and the first workgroup of an XCD to read a line
+// brings it in for the others (agent-scope loads would bypass L2 and send
+// every workgroup's reads of the same partials to memory).  A
+// waiting thread gives up after a wall-clock timeout: the error word is set,
+// every workgroup leaves, and the host redoes the solve with the
+// multi-kernel form, so a fault in the launch configuration cannot hang the
+// device.
 #include "coarse_common.h"
 
 namespace wcmg {
-
 namespace {
-constexpr int kPMaxM1 = 41;  // restart + 1 (restart <= 40)
-constexpr int kPSpw = 2;     // coarse sites per workgroup, at most
+constexpr int kPMaxM1 = 41;     // restart + 1 (restart <= 40)
+constexpr int kPSpw = 2;        // coarse sites per workgroup, at most
+constexpr int kPStride = 48;    // partial slots (cd64) per workgroup and phase buffer
+constexpr int kBarWords = 64;   // bar[2]: error word, bar[3..6]: report; flags follow
+constexpr int kFlagWords = 32;  // one 128-byte line per workgroup flag
+constexpr int kPRtri = kPMaxM1 * (kPMaxM1 - 1) / 2;  // packed upper triangle, 40 columns
 
-// bar: [0] arrival counter, [1] generation, [2] error word, [3..6] the first
-// timed-out workgroup's report (workgroup, barriers it had passed, counter
-// and generation it saw).  nb_passed: this workgroup's barrier count (LDS).
-__device__ inline bool pbarrier(unsigned* bar, unsigned nblocks, int* nb_passed, long long tick_limit) {
-  __shared__ int failed;
-  unsigned* err = bar + 2;
-  // every wave releases its own global writes (L2 write-back) before arriving
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    if (!bad) {
-      const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == nblocks - 1) {
-        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        const long long t0 = wall_clock64();
-        while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          const bool other = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-          if (other || wall_clock64() - t0 > tick_limit) {
-            if (!other && __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-              bar[3] = blockIdx.x;
-              bar[4] = (unsigned)*nb_passed;
-              bar[5] = __hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              bar[6] = gen;
-            }
-            bad = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-    }
-    failed = bad;
-    ++*nb_passed;
-  }
-  __syncthreads();
-  // every wave acquires for itself: one wave's cache invalidation is not
-  // ordered before the other waves' later loads, which could then read the
-  // previous phase's partials from this XCD's L2
-  __threadfence();
-  return failed == 0;
-}
-
-// Loads of data that other workgroups (possibly on other XCDs) wrote during
-// this launch: agent-scope atomic loads, which read the coherent copy instead
-// of a line this XCD's L2 may still hold from an earlier phase.
-__device__ inline cd64 ld_shared(const cd64* p) {
-  const unsigned long long* q = (const unsigned long long*)p;
-  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return mkc(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b));
-}
-__device__ inline cf32 ld_shared(const cf32* p) {
-  const unsigned long long a =
-      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return mkc(__builtin_bit_cast(float, (unsigned)a), __builtin_bit_cast(float, (unsigned)(a >> 32)));
-}
-
-__device__ inline cd64 pwsum(cd64 v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v.re += __shfl_xor(v.re, off, 64);
-    v.im += __shfl_xor(v.im, off, 64);
-  }
-  return v;
-}
-
-// Device scalars of one solve, in the layout of the fused path's (H, cs, sn,
-// g, y, misc): H [(m+1) x m] row-major, then m, m, m+1, m entries, then misc.
-struct PScalars {
-  cd64 *H, *y, *misc;
-  __device__ PScalars(cd64* S, int m) {
-    H = S;
-    y = S + (m + 1) * m + 2 * m + (m + 1);
-    misc = y + m;
-  }
-};
-
-template <int NB>
+template <int P, int NB>
 struct PShape {
+  typedef typename BlkTraits<P>::R R;
+  static constexpr int K = BlkTraits<P>::K, NCH = NB / K, NQ = 9 * NCH;
   static constexpr int rows = kPSpw * NB;  // LDS rows per workgroup
   static constexpr int s0 = 256 / rows;
   // lanes per row: the largest power of two that fits, at most 16
   static constexpr int S = s0 >= 16 ? 16 : s0 >= 8 ? 8 : s0 >= 4 ? 4 : s0 >= 2 ? 2 : 1;
+  static constexpr size_t lds = (size_t)NQ * rows * 16 + 2 * (size_t)kPMaxM1 * rows * sizeof(cplx<R>) +
+                                (size_t)kPSpw * 9 * NB * sizeof(cplx<R>) + (size_t)kPRtri * 16 +
+                                (size_t)(4 * (kPMaxM1 + 1) + 4 * (kPMaxM1 + 1) + 2 * kPMaxM1) * 16 + 128;
+  static constexpr bool fits = lds <= 160 * 1024;
 };
+
+// Returns false when a wait timed out, here or in another workgroup.
+__device__ inline bool pbarrier(unsigned* bar, unsigned G, unsigned phase, int* fail, long long tick_limit) {
+  unsigned* err = bar + 2;
+  unsigned* flags = bar + kBarWords;
+  // the workgroup barrier does not wait for stores: every wave first waits
+  // until its own stores have reached this XCD's L2, so that the one
+  // write-back below covers the whole workgroup's writes of this phase
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flags + (size_t)kFlagWords * blockIdx.x, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  int bad = 0;
+  const long long t0 = wall_clock64();
+  for (unsigned g = threadIdx.x; g < G && !bad; g += blockDim.x) {
+    unsigned seen;
+    while ((seen = __hip_atomic_load(flags + (size_t)kFlagWords * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
+           phase) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        bad = 1;
+        break;
+      }
+      if (wall_clock64() - t0 > tick_limit) {
+        if (__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          bar[3] = blockIdx.x;
+          bar[4] = phase;
+          bar[5] = g;
+          bar[6] = seen;
+        }
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (bad) *fail = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  return *fail == 0;
+}
+
+__device__ inline cd64 shfl_xor_c(cd64 v, int off) {
+  return mkc(__shfl_xor(v.re, off, 64), __shfl_xor(v.im, off, 64));
+}
+
+// Wave sums of eight entries at once: at offsets 32, 16 and 8 each lane
+// keeps half of its remaining entries and receives its partner's share of
+// them, then a butterfly over the last three lane bits; lane l ends with the
+// sum of entry 4 b5 + 2 b4 + b3 (the bits of l), in a fixed order.
+__device__ inline cd64 wred8(cd64 (&a)[8], int lane) {
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const cd64 send = h5 ? a[k] : a[k + 4], keep = h5 ? a[k + 4] : a[k];
+    a[k] = cadd(keep, shfl_xor_c(send, 32));
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const cd64 send = h4 ? a[k] : a[k + 2], keep = h4 ? a[k + 2] : a[k];
+    a[k] = cadd(keep, shfl_xor_c(send, 16));
+  }
+  cd64 v;
+  {
+    const cd64 send = h3 ? a[0] : a[1], keep = h3 ? a[1] : a[0];
+    v = cadd(keep, shfl_xor_c(send, 8));
+  }
+  v = cadd(v, shfl_xor_c(v, 4));
+  v = cadd(v, shfl_xor_c(v, 2));
+  v = cadd(v, shfl_xor_c(v, 1));
+  return v;
+}
+__device__ inline int wred8_entry(int lane) { return ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1); }
+
+// conj(a) b in FP64 (products of FP32 values are exact in FP64)
+__device__ inline cd64 cdotd(cf32 a, cf32 b) {
+  return mkc((double)a.re * b.re + (double)a.im * b.im, (double)a.re * b.im - (double)a.im * b.re);
+}
 }  // namespace
 
 template <int P, int NB>
 __global__ void __launch_bounds__(256) k_cg_persistent(
     const Chunk16* __restrict__ blk, const int* __restrict__ nbr, long Vc, const cplx<typename BlkTraits<P>::R>* b,
-    cplx<typename BlkTraits<P>::R>* x, cplx<typename BlkTraits<P>::R>* V, cplx<typename BlkTraits<P>::R>* w,
-    cplx<typename BlkTraits<P>::R>* r, cd64* part, cd64* S, int* st, const int* parent, int m, double tol,
-    int limit, int fixed, unsigned* bar, long long tick_limit) {
-  typedef typename BlkTraits<P>::R R;
-  constexpr int K = BlkTraits<P>::K, NCH = NB / K, NQ = 9 * NCH;
-  constexpr int ROWS = PShape<NB>::rows, SL = PShape<NB>::S;
+    cplx<typename BlkTraits<P>::R>* x, cplx<typename BlkTraits<P>::R>* zg, cplx<typename BlkTraits<P>::R>* r,
+    cd64* part, cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
+    long long tick_limit) {
+  typedef PShape<P, NB> Sh;
+  typedef typename Sh::R R;
+  constexpr int K = Sh::K, NCH = Sh::NCH, NQ = Sh::NQ, ROWS = Sh::rows, SL = Sh::S;
   __shared__ Chunk16 tile[NQ][ROWS];
-  __shared__ cd64 red[4][kPMaxM1];
-  __shared__ cd64 hs[kPMaxM1];  // reduced entries of the current phase
-  __shared__ cd64 hcol[kPMaxM1], csv[kPMaxM1], snv[kPMaxM1], gv[kPMaxM1];
-  __shared__ double scal[4];    // 0: |u|^2 of the vector being applied, 1: |b|^2 of the first cycle
-  __shared__ int ctl[4];        // 0: continue the cycle, 1: live, 2: jdone, 3: total
-  __shared__ int nbar;          // barriers passed (diagnostics)
+  __shared__ cplx<R> vl[kPMaxM1][ROWS];  // v_i at the own rows
+  __shared__ cplx<R> zl[kPMaxM1][ROWS];  // A v_i at the own rows
   __shared__ cplx<R> ust[kPSpw][9][NB];  // the applied vector at the sites' stencil points
+  __shared__ cd64 rtri[kPRtri];          // rotated Hessenberg R, column j at j (j + 1) / 2
+  __shared__ cd64 red[4][kPMaxM1 + 1];
+  __shared__ cd64 hs[kPMaxM1 + 1];       // reduced entries of the current phase
+  __shared__ cd64 hcol[kPMaxM1 + 1], gv[kPMaxM1 + 1], csv[kPMaxM1], snv[kPMaxM1];
+  __shared__ cd64 yv[kPMaxM1];
+  __shared__ double scal[3];             // 0: |u|^2 of the next basis vector, 1: |b|^2 of the first cycle, 2: shift
+  __shared__ int ctl[5];                 // 0: continue the cycle, 1: live, 2: jdone, 3: total, 4: reorthogonalise
+  __shared__ int fail;
   const unsigned G = gridDim.x;
   const long n = Vc * NB;
   const long row0 = (long)blockIdx.x * ROWS;
@@ -139,11 +176,10 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   const int lr = tid / SL, sub = tid - lr * SL;
   const bool own = lr < nrow && sub == 0;  // this thread holds row row0 + lr of every vector
   const long t = row0 + lr;
-  PScalars c(S, m);
+  const int lrc = min(lr, ROWS - 1);       // LDS row for unconditional reads (used only when own)
 
-  // live flag of this solve (the caller's run flag)
   if (tid == 0) {
-    nbar = 0;
+    fail = 0;
     ctl[1] = parent ? *parent : 1;
     ctl[2] = 0;
     ctl[3] = 0;
@@ -159,24 +195,54 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   if (!ctl[1]) return;  // uniform: every workgroup reads the same flag
 
   // this workgroup's rows of the nine blocks, resident for the whole solve
-  for (int idx = tid; idx < NQ * nrow; idx += blockDim.x) {
-    const int q = idx / nrow, rr = idx - q * nrow;
-    tile[q][rr] = blk[(long)q * n + row0 + rr];
+  {
+    // eight loads in flight per thread (indices past the end re-read the
+    // last chunk and are not stored)
+    const int total = NQ * nrow;
+    for (int base = tid; base < total; base += 8 * 256) {
+      Chunk16 c[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int idx = min(base + 256 * k, total - 1);
+        const int q = idx / nrow, rr = idx - q * nrow;
+        c[k] = blk[(long)q * n + row0 + rr];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int idx = base + 256 * k;
+        if (idx < total) {
+          const int q = idx / nrow, rr = idx - q * nrow;
+          tile[q][rr] = c[k];
+        }
+      }
+    }
   }
   __syncthreads();
 
-  // (A u)_t for this thread's row: the vector at the nine stencil points of
-  // the workgroup's sites is staged in LDS (coherent loads), then SL lanes
-  // split the row's chunks
+  // (A u) at this thread's row (every lane of the row gets the sum): the
+  // vector at the nine stencil points of the workgroup's sites is staged in
+  // LDS (ust, flat index e = k + NB (d + 9 site); the source rows are fixed
+  // for the whole solve and kept in registers), then SL lanes split the
+  // row's chunks
   const int nsites = nrow / NB;
-  auto apply_row = [&](const cplx<R>* u) -> cplx<R> {
-    __syncthreads();  // the previous apply's readers are done with ust
-    for (int e = tid; e < nsites * 9 * NB; e += blockDim.x) {
+  constexpr int kStage = (kPSpw * 9 * NB + 255) / 256;
+  long srcrow[kStage];
+#pragma unroll
+  for (int kk = 0; kk < kStage; ++kk) {
+    const int e = tid + 256 * kk;
+    srcrow[kk] = -1;
+    if (e < nsites * 9 * NB) {
       const int k = e % NB, dd = (e / NB) % 9, ls = e / (9 * NB);
       const long site = row0 / NB + ls;
-      const long src = dd == 0 ? site : (long)nbr[(long)(dd - 1) * Vc + site];
-      ust[ls][dd][k] = ld_shared(u + src * NB + k);
+      srcrow[kk] = (dd == 0 ? site : (long)nbr[(long)(dd - 1) * Vc + site]) * NB + k;
     }
+  }
+  cplx<R>* ustf = &ust[0][0][0];
+  auto apply_row = [&](const cplx<R>* u) -> cplx<R> {
+    __syncthreads();  // the previous apply's readers are done with ust
+#pragma unroll
+    for (int kk = 0; kk < kStage; ++kk)
+      if (srcrow[kk] >= 0) ustf[tid + 256 * kk] = u[srcrow[kk]];
     __syncthreads();
     cplx<R> acc = mkc((R)0, (R)0), acc2 = mkc((R)0, (R)0);
     if (lr < nrow) {
@@ -205,59 +271,76 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     }
     return acc;
   };
-  // per-workgroup partials of cnt entries (entry-major: part[i * G + block]).
-  // Two buffers, alternating by phase: a workgroup that has finished reducing
-  // one phase may write the next phase's partials while a slower one still
-  // reads the previous phase's; it can only come back to a buffer after the
-  // next barrier, which every reader of that buffer has reached.
+
+  // Grid-wide sums of cnt entries: this workgroup's partials go to
+  // part[pb][block][i]; after the barrier every workgroup adds the G
+  // partials of each entry in the same order into hs.  Two partial buffers,
+  // alternating by phase: a workgroup that has finished reading one phase may
+  // write the next phase's partials while a slower one still reads the
+  // previous phase's, and it can only come back to a buffer after the next
+  // barrier, which every reader of that buffer has reached.
+  unsigned phase = 0;
   int pb = 0;
-  auto block_partials = [&](int cnt, auto contrib) {
-    for (int i = 0; i < cnt; ++i) {
-      const cd64 s = pwsum(own ? contrib(i) : mkc(0.0, 0.0));
-      if (lane == 0) red[wave][i] = s;
+  const int ent = wred8_entry(lane);
+  auto reduce = [&](int cnt, auto contrib) -> bool {
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      cd64 a[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const cd64 v = contrib(min(i0 + k, cnt - 1));
+        a[k] = own && i0 + k < cnt ? v : mkc(0.0, 0.0);
+      }
+      const cd64 s = wred8(a, lane);
+      if ((lane & 7) == 0 && i0 + ent < cnt) red[wave][i0 + ent] = s;
     }
     __syncthreads();
-    if (tid < cnt) {
-      cd64 s = mkc(0.0, 0.0);
-      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s = cadd(s, red[q][tid]);
-      part[(long)(pb * kPMaxM1 + tid) * G + blockIdx.x] = s;
+    if (tid < cnt)
+      part[((size_t)pb * G + blockIdx.x) * kPStride + tid] =
+          cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
+    if (!pbarrier(bar, G, ++phase, &fail, tick_limit)) return false;
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+      cd64 a[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] = mkc(0.0, 0.0);
+      for (unsigned g = tid; g < G; g += blockDim.x) {
+        const cd64* pg = part + ((size_t)pb * G + g) * kPStride + i0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          // every slot is in bounds (i0 + k < kPStride); only the first cnt count
+          const cd64 v = pg[k];
+          if (i0 + k < cnt) a[k] = cadd(a[k], v);
+        }
+      }
+      const cd64 s = wred8(a, lane);
+      if ((lane & 7) == 0 && i0 + ent < cnt) red[wave][i0 + ent] = s;
     }
-  };
-  // every workgroup: hs[i] = sum over the G partials of entry i (fixed order)
-  auto grid_reduce = [&](int cnt) {
-    for (int i = wave; i < cnt; i += (int)(blockDim.x >> 6)) {
-      cd64 s = mkc(0.0, 0.0);
-      for (unsigned g = lane; g < G; g += 64) s = cadd(s, ld_shared(part + (long)(pb * kPMaxM1 + i) * G + g));
-      s = pwsum(s);
-      if (lane == 0) hs[i] = s;
-    }
+    __syncthreads();
+    if (tid < cnt) hs[tid] = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
     __syncthreads();
     pb ^= 1;
+    return true;
   };
 
   const int max_cycles = (limit + m - 1) / m;
   cplx<R> xv = mkc((R)0, (R)0);
+  cplx<R> pj = mkc((R)0, (R)0);  // p_j at the own row, as stored in zg
   if (own) x[t] = xv;
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     // residual of the current x (zero on the first cycle: u0 = b)
     const cplx<R>* u0 = b;
     if (cyc > 0) {
-      if (!pbarrier(bar, G, &nbar, tick_limit)) return;  // x complete
+      if (!pbarrier(bar, G, ++phase, &fail, tick_limit)) return;  // x complete
       const cplx<R> ax = apply_row(x);
       if (own) r[t] = csub(b[t], ax);
       u0 = r;
     }
-    {
-      const cplx<R> uv = own ? u0[t] : mkc((R)0, (R)0);
-      const double q = (double)uv.re * uv.re + (double)uv.im * uv.im;
-      block_partials(1, [&](int) { return mkc(q, 0.0); });
-    }
-    if (!pbarrier(bar, G, &nbar, tick_limit)) return;
-    grid_reduce(1);
+    const cplx<R> uo = own ? u0[t] : mkc((R)0, (R)0);
+    // |u0|^2 (the barrier also completes u0 everywhere)
+    if (!reduce(1, [&](int) { return mkc((double)uo.re * uo.re + (double)uo.im * uo.im, 0.0); })) return;
     if (tid == 0) {
       const double b2 = hs[0].re;
-      scal[0] = b2;
       if (cyc == 0) scal[1] = b2;
+      scal[0] = b2;
       const double bn = sqrt(scal[1]), beta = sqrt(b2);
       ctl[2] = 0;
       ctl[0] = 1;
@@ -266,59 +349,84 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         ctl[1] = 0;
         if (blockIdx.x == 0) st[4] = !(beta == beta) ? 3 : 1;
       } else {
-        for (int i = 0; i < kPMaxM1; ++i) gv[i] = mkc(0.0, 0.0);
+        for (int i = 0; i <= kPMaxM1; ++i) gv[i] = mkc(0.0, 0.0);
         gv[0] = mkc(beta, 0.0);
       }
       if (blockIdx.x == 0) {
-        c.misc[1] = mkc(b2, 0.0);
-        if (cyc == 0) c.misc[0] = mkc(b2, 0.0);
-        c.misc[2].re = bn > 0 ? beta / bn : 0.0;
+        misc[1] = mkc(b2, 0.0);
+        if (cyc == 0) misc[0] = mkc(b2, 0.0);
+        misc[2].re = bn > 0 ? beta / bn : 0.0;
       }
     }
     __syncthreads();
     if (!ctl[0]) break;
-
-    const cplx<R>* u = u0;
-    for (int j = 0; j < m; ++j) {
-      // 1. w = A u / |u|, v_j = u / |u|, partials of <v_i, w>
-      const double inv = 1.0 / sqrt(scal[0]);
-      const cplx<R> au = apply_row(u);
-      cplx<R> vj = mkc((R)0, (R)0), wv = mkc((R)0, (R)0);
+    {
+      // v_0 = u0 / beta, z_0 = A u0 / beta
+      const cplx<R> au = apply_row(u0);
+      const R inv = (R)(1.0 / sqrt(scal[0]));
       if (own) {
-        const cplx<R> ut = u[t];
-        vj = mkc((R)(ut.re * inv), (R)(ut.im * inv));
-        wv = mkc((R)(au.re * inv), (R)(au.im * inv));
-        V[(long)j * n + t] = vj;
+        vl[0][lr] = cscale(inv, uo);
+        zl[0][lr] = cscale(inv, au);
+        pj = zl[0][lr];
+        zg[t] = pj;
       }
-      auto dots = [&](int i) {
-        const cplx<R> vi = i == j ? vj : V[(long)i * n + t];
-        return mkc((double)vi.re * wv.re + (double)vi.im * wv.im, (double)vi.re * wv.im - (double)vi.im * wv.re);
-      };
-      block_partials(j + 1, dots);
-      if (!pbarrier(bar, G, &nbar, tick_limit)) return;
-      grid_reduce(j + 1);
-      // 2. and 3. two classical Gram-Schmidt passes
-      for (int pass = 0; pass < 2; ++pass) {
-        if (tid <= j) hcol[tid] = pass == 0 ? hs[tid] : cadd(hcol[tid], hs[tid]);
+    }
+
+    for (int j = 0; j < m; ++j) {
+      // h1 = V^H z_j and |z_j|^2 (the barrier also completes z_j, which the
+      // apply below reads at the neighbouring sites; z_j alternates between
+      // two global buffers, so a workgroup writing z_{j+1} cannot overwrite
+      // rows a slower one still reads)
+      const cplx<R> zj = pj;
+      if (!reduce(j + 2, [&](int i) {
+            return i <= j ? cdotd(vl[i][lrc], zj) : mkc((double)zj.re * zj.re + (double)zj.im * zj.im, 0.0);
+          }))
+        return;
+      cplx<R> aw = apply_row(zg + (long)(j & 1) * n);
+      cplx<R> wv = zj;
+      if (own)
+        for (int i = 0; i <= j; ++i) {
+          const cplx<R> h = cneg(mkc((R)hs[i].re, (R)hs[i].im));
+          cfma(wv, h, vl[i][lr]);
+          cfma(aw, h, zl[i][lr]);
+        }
+      if (tid == 0) {
+        double n1 = hs[j + 1].re;
+        for (int i = 0; i <= j; ++i) {
+          hcol[i] = hs[i];
+          n1 -= hs[i].re * hs[i].re + hs[i].im * hs[i].im;
+        }
+        if (j == 0) scal[2] = hs[0].re;  // the shift of the later steps
+        else hcol[j].re += scal[2];
+        scal[0] = n1;
+        ctl[4] = n1 < 0.25 * hs[j + 1].re;
+      }
+      __syncthreads();
+      if (ctl[4]) {
+        // h2 = V^H w1 and |w1|^2 (computed from w1 itself)
+        if (!reduce(j + 2, [&](int i) {
+              return i <= j ? cdotd(vl[i][lrc], wv) : mkc((double)wv.re * wv.re + (double)wv.im * wv.im, 0.0);
+            }))
+          return;
         if (own)
           for (int i = 0; i <= j; ++i) {
-            const cplx<R> hi = mkc((R)hs[i].re, (R)hs[i].im);
-            cfma(wv, cneg(hi), i == j ? vj : V[(long)i * n + t]);
+            const cplx<R> h = cneg(mkc((R)hs[i].re, (R)hs[i].im));
+            cfma(wv, h, vl[i][lr]);
+            cfma(aw, h, zl[i][lr]);
           }
-        __syncthreads();
-        if (pass == 0) {
-          block_partials(j + 1, dots);
-        } else {
-          if (own) w[t] = wv;
-          const double q = (double)wv.re * wv.re + (double)wv.im * wv.im;
-          block_partials(1, [&](int) { return mkc(q, 0.0); });
+        if (tid == 0) {
+          double n2 = hs[j + 1].re;
+          for (int i = 0; i <= j; ++i) {
+            hcol[i] = cadd(hcol[i], hs[i]);
+            n2 -= hs[i].re * hs[i].re + hs[i].im * hs[i].im;
+          }
+          scal[0] = n2;
         }
-        if (!pbarrier(bar, G, &nbar, tick_limit)) return;
-        grid_reduce(pass == 0 ? j + 1 : 1);
       }
-      // 4. |w|^2 and the Givens rotation of column j (every workgroup)
+      // |w|^2 and the Givens rotation of the Hessenberg column
       if (tid == 0) {
-        const double hn2 = hs[0].re, hn = sqrt(hn2);
+        const double hn2 = scal[0] > 0.0 ? scal[0] : 0.0;
+        const double hn = sqrt(hn2);
         scal[0] = hn2;
         for (int i = 0; i < j; ++i) {
           const cd64 a = hcol[i], bb = hcol[i + 1];
@@ -336,7 +444,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         csv[j] = cc;
         snv[j] = ss;
         hcol[j] = mkc(den, 0.0);
-        hcol[j + 1] = mkc(0.0, 0.0);
+        for (int i = 0; i <= j; ++i) rtri[j * (j + 1) / 2 + i] = hcol[i];
         const cd64 gj = gv[j];
         gv[j + 1] = cmul(cneg(cconj(ss)), gj);
         gv[j] = cmul(cc, gj);
@@ -361,35 +469,36 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         if (stop) ctl[1] = 0;
         ctl[0] = (stop || j + 1 == m) ? 0 : 1;
         if (blockIdx.x == 0) {
-          for (int i = 0; i <= j + 1 && i < m + 1; ++i)
-            if (i * m + j < (m + 1) * m) c.H[i * m + j] = hcol[i];
-          c.misc[3] = mkc(hn2, 0.0);
-          c.misc[2].re = est;
+          misc[3] = mkc(hn2, 0.0);
+          misc[2].re = est;
           if (stop) st[4] = reason;
         }
       }
       __syncthreads();
-      u = w;
       if (!ctl[0]) break;
-      // the next step reads w at neighbouring rows: written before the last barrier
+      const R inv = (R)(1.0 / sqrt(scal[0]));
+      if (own) {
+        const cplx<R> v1 = cscale(inv, wv), z1 = cscale(inv, aw);
+        vl[j + 1][lr] = v1;
+        zl[j + 1][lr] = z1;
+        pj = csub(z1, cscale((R)scal[2], v1));
+        zg[(long)((j + 1) & 1) * n + t] = pj;
+      }
     }
-    // y from the leading jdone x jdone triangle (every workgroup, its own copy)
+    // y from the leading jdone x jdone triangle (every workgroup its own,
+    // bit-identical copy), then x += V y at the own rows
     const int jd = ctl[2];
-    if (tid == 0 && blockIdx.x == 0) {
+    if (tid == 0)
       for (int i = jd - 1; i >= 0; --i) {
         cd64 s = gv[i];
-        for (int k = i + 1; k < jd; ++k) s = csub(s, cmul(c.H[i * m + k], c.y[k]));
-        const cd64 d = c.H[i * m + i];
+        for (int k = i + 1; k < jd; ++k) s = csub(s, cmul(rtri[k * (k + 1) / 2 + i], yv[k]));
+        const cd64 d = rtri[i * (i + 1) / 2 + i];
         const double dd = d.re * d.re + d.im * d.im;
-        c.y[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
+        yv[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
       }
-    }
-    if (!pbarrier(bar, G, &nbar, tick_limit)) return;  // y written by workgroup 0
+    __syncthreads();
     if (own) {
-      for (int k = 0; k < jd; ++k) {
-        const cd64 yk = ld_shared(c.y + k);
-        cfma(xv, mkc((R)yk.re, (R)yk.im), V[(long)k * n + t]);
-      }
+      for (int k = 0; k < jd; ++k) cfma(xv, mkc((R)yv[k].re, (R)yv[k].im), vl[k][lr]);
       x[t] = xv;
     }
     if (!ctl[1]) break;
@@ -402,50 +511,83 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   }
 }
 
-// Returns false (and launches nothing) when the operator does not fit: more
-// than 2 * (co-resident workgroups) coarse sites, an unsupported Nb, FP64
-// storage, or no cooperative launch.
+namespace {
 template <int P, int NB>
-static bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* V, void* w, void* r,
-                       cd64* part, cd64* S, int* st, const int* parent, int m, double tol, int limit, int fixed,
-                       unsigned* bar, long long tick_limit, hipStream_t stream) {
-  typedef typename BlkTraits<P>::R R;
-  auto kern = k_cg_persistent<P, NB>;
-  int dev = 0, cus = 0, coop = 0, per_cu = 0;
-  WCMG_HIP(hipGetDevice(&dev));
-  WCMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  WCMG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-  WCMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
-  const long G = (Vc + kPSpw - 1) / kPSpw;
-  if (!coop || per_cu < 1 || G > (long)cus * per_cu || m + 1 > kPMaxM1) return false;
-  const Chunk16* bk = (const Chunk16*)blk;
-  const cplx<R>* bc = (const cplx<R>*)b;
-  cplx<R>* xx = (cplx<R>*)x;
-  cplx<R>* vv = (cplx<R>*)V;
-  cplx<R>* ww = (cplx<R>*)w;
-  cplx<R>* rr = (cplx<R>*)r;
-  void* args[] = {(void*)&bk, (void*)&nbr, (void*)&Vc, (void*)&bc, (void*)&xx, (void*)&vv, (void*)&ww, (void*)&rr,
-                  (void*)&part, (void*)&S, (void*)&st, (void*)&parent, (void*)&m, (void*)&tol, (void*)&limit,
-                  (void*)&fixed, (void*)&bar, (void*)&tick_limit};
-  WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
-  return true;
+bool cgp_shape_fits() {
+  if constexpr (PShape<P, NB>::fits) return true;
+  else return false;
 }
+
+// Returns false (and launches nothing) when the workgroups cannot all be
+// co-resident or there is no cooperative launch.
+template <int P, int NB>
+bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* z, void* r, cd64* part,
+                cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
+                long long tick_limit, hipStream_t stream) {
+  if constexpr (!PShape<P, NB>::fits) {
+    return false;
+  } else {
+    typedef typename BlkTraits<P>::R R;
+    auto kern = k_cg_persistent<P, NB>;
+    int dev = 0, cus = 0, coop = 0, per_cu = 0;
+    WCMG_HIP(hipGetDevice(&dev));
+    WCMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    WCMG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    WCMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
+    const long G = (Vc + kPSpw - 1) / kPSpw;
+    if (!coop || per_cu < 1 || G > (long)cus * per_cu || m + 1 > kPMaxM1 || m < 1) return false;
+    const Chunk16* bk = (const Chunk16*)blk;
+    const cplx<R>* bc = (const cplx<R>*)b;
+    cplx<R>* xx = (cplx<R>*)x;
+    cplx<R>* zz = (cplx<R>*)z;
+    cplx<R>* rr = (cplx<R>*)r;
+    void* args[] = {(void*)&bk,   (void*)&nbr, (void*)&Vc,    (void*)&bc,    (void*)&xx,    (void*)&zz,
+                    (void*)&rr,   (void*)&part, (void*)&misc, (void*)&st,    (void*)&parent, (void*)&m,
+                    (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&tick_limit};
+    WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
+    return true;
+  }
+}
+}  // namespace
 
 bool cg_persistent_fits(int prec, int nb, long Vc) {
-  if (prec == WCMG_F64 || !(nb == 8 || nb == 12 || nb == 16 || nb == 24 || nb == 32)) return false;
-  return Vc >= 1 && Vc <= 2 * 256 * 4;  // refined by the occupancy check at launch
+  if (Vc < 1 || Vc > 2L * 256 * 4) return false;  // refined by the occupancy check at launch
+  if (prec == WCMG_F32) {
+    switch (nb) {
+      case 8: return cgp_shape_fits<WCMG_F32, 8>();
+      case 12: return cgp_shape_fits<WCMG_F32, 12>();
+      case 16: return cgp_shape_fits<WCMG_F32, 16>();
+      case 24: return cgp_shape_fits<WCMG_F32, 24>();
+      case 32: return cgp_shape_fits<WCMG_F32, 32>();
+      default: return false;
+    }
+  }
+  if (prec == WCMG_BF16) {
+    switch (nb) {
+      case 8: return cgp_shape_fits<WCMG_BF16, 8>();
+      case 12: return cgp_shape_fits<WCMG_BF16, 12>();
+      case 16: return cgp_shape_fits<WCMG_BF16, 16>();
+      case 24: return cgp_shape_fits<WCMG_BF16, 24>();
+      case 32: return cgp_shape_fits<WCMG_BF16, 32>();
+      default: return false;
+    }
+  }
+  return false;
 }
 
+size_t cg_persistent_part_elems(long Vc) { return (size_t)2 * kPStride * (size_t)((Vc + kPSpw - 1) / kPSpw); }
+size_t cg_persistent_bar_words(long Vc) { return (size_t)kBarWords + (size_t)kFlagWords * ((Vc + kPSpw - 1) / kPSpw); }
+
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
-                          void* V, void* w, void* r, cd64* part, cd64* S, int* st, const int* parent, int m,
-                          double tol, int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream) {
+                          void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
+                          int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream) {
   if (!cg_persistent_fits(prec, nb, Vc)) return false;
   int dev = 0, khz = 0;
   WCMG_HIP(hipGetDevice(&dev));
   WCMG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   const long long tick_limit = (long long)(timeout_s * 1000.0 * (khz > 0 ? khz : 100000));
 #define CGP(PP, NBc) \
-  return cgp_launch<PP, NBc>(blk, nbr, Vc, b, x, V, w, r, part, S, st, parent, m, tol, limit, fixed, bar, \
+  return cgp_launch<PP, NBc>(blk, nbr, Vc, b, x, z, r, part, misc, st, parent, m, tol, limit, fixed, bar, \
                              tick_limit, stream)
   if (prec == WCMG_F32) {
     switch (nb) {

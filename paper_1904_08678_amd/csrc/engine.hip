@@ -585,14 +585,17 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
   const char* fam = prec == WCMG_F64 ? "coarse_gmres_step_f64" : prec == WCMG_F32 ? "coarse_gmres_step_f32"
                                                                                      : "coarse_gmres_step_bf16";
   // one cooperative launch for the whole solve when the blocks fit the LDS
-  // (reserved[0] bit 2 turns it off); the state is read back to check the
-  // barrier word, so only with host checks
+  // (reserved[0] flag 4 turns it off); the state is read back to check the
+  // barrier words, so only with host checks
   if (!five && check_every > 0 && !(p.reserved[0] & 4) && cg_persistent_fits(prec, nb, C.V)) {
-    cd64* partP = buf<cd64>("cgp_part" + t, 2 * 41 * ((C.V + 1) / 2));  // two phase buffers
-    unsigned* bar = (unsigned*)(scratch64.as<cd64>() + 40);  // 8 words: cd64 40..43
-    WCMG_HIP(hipMemsetAsync(bar, 0, 8 * sizeof(unsigned), stream));
+    cd64* partP = buf<cd64>("cgp_part" + t, (long)cg_persistent_part_elems(C.V));
+    const long nbar = (long)cg_persistent_bar_words(C.V);
+    unsigned* bar = buf<unsigned>("cgp_bar" + t, nbar);
+    WCMG_HIP(hipMemsetAsync(bar, 0, nbar * sizeof(unsigned), stream));
+    cplx<R>* zP = buf<cplx<R>>("cgp_z" + t, 2 * nn);
+    cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
     prof.begin("coarse_gmres_persistent", stream);
-    const bool launched = launch_cg_persistent(prec, nb, blk, C.nbr.as<int>(), C.V, b, x, V, wb[0], r, partP, S, st,
+    const bool launched = launch_cg_persistent(prec, nb, blk, C.nbr.as<int>(), C.V, b, x, zP, r, partP, misc, st,
                                                parent, m, p.coarse_tol, limit, fixed, bar, 5.0, stream);
     prof.end("coarse_gmres_persistent", stream);
     if (launched) {
@@ -600,11 +603,11 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
       WCMG_HIP(hipMemcpyAsync(pinned + 8, bar, 8 * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
       sync();
       if (pinned[10] == 0) return pinned[3];
-      // a barrier timed out: keep the report and redo the solve below
+      // a barrier wait timed out: keep the report and redo the solve below
       cgp_fallbacks++;
       cgp_last_report = "workgroup " + std::to_string(pinned[11]) + " of " + std::to_string((C.V + 1) / 2) +
-                        " after " + std::to_string(pinned[12]) + " barriers; counter " + std::to_string(pinned[13]) +
-                        ", generation " + std::to_string(pinned[14]);
+                        " timed out at phase " + std::to_string(pinned[12]) + " waiting for workgroup " +
+                        std::to_string(pinned[13]) + " (its flag: " + std::to_string(pinned[14]) + ")";
     }
   }
   launch_gmres_init(st, parent, stream);

@@ -138,15 +138,19 @@ void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
 void launch_gmres_cycle_end(int* st_, hipStream_t st);
 
 // ---- the coarsest GMRES in one cooperative launch (coarse_persist.hip):
-// false (nothing launched) when the operator does not fit the LDS of the
-// co-resident workgroups; part: cd64 [2 * 41 * ceil(Vc / 2)]; bar: 8 zeroed
-// words (counter, generation, error word set on a barrier timeout, then the
-// first timed-out workgroup's report: workgroup, barriers passed, counter,
-// generation)
+// false (nothing launched) when the operator's blocks, basis and image do not
+// fit the LDS of co-resident workgroups; part: cd64 [cg_persistent_part_elems];
+// bar: cg_persistent_bar_words zeroed words (bar[2] is set when a barrier
+// wait timed out, bar[3..6] then hold the first timed-out workgroup, the
+// phase, the workgroup it waited for and the flag value it saw); misc: the
+// solve's residual words, as the multi-kernel form writes them; z: 2 Vc Nb
+// vector elements; r: Vc Nb
 bool cg_persistent_fits(int prec, int nb, long Vc);
+size_t cg_persistent_part_elems(long Vc);
+size_t cg_persistent_bar_words(long Vc);
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
-                          void* V, void* w, void* r, cd64* part, cd64* S, int* st, const int* parent, int m,
-                          double tol, int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream);
+                          void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
+                          int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream);
 
 // ---- fused coarse GMRES (coarse_gmres.hip)
 bool cg_fused_supported(int nb);

@@ -379,20 +379,22 @@ def test_fused_coarse_gmres_matches_generic_path(fixed):
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
 
 
-@pytest.mark.parametrize("L,block,store", [((8, 8, 8, 8), (4, 4, 4, 4), "f32"), ((8, 8, 8, 8), (4, 4, 4, 4), "bf16"),
-                                           ((16, 16, 16, 16), (4, 4, 4, 4), "f32"),
-                                           ((16, 16, 16, 32), (4, 4, 4, 4), "f32"), ((8, 8, 6, 6), (2, 2, 2, 2), "f32")])
-def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store):
+@pytest.mark.parametrize("L,block,store,nv", [((8, 8, 8, 8), (4, 4, 4, 4), "f32", 12),
+                                              ((8, 8, 8, 8), (4, 4, 4, 4), "bf16", 12),
+                                              ((8, 8, 8, 8), (4, 4, 4, 4), "bf16", 16),
+                                              ((16, 16, 16, 16), (4, 4, 4, 4), "f32", 12),
+                                              ((16, 16, 16, 32), (4, 4, 4, 4), "f32", 12),
+                                              ((6, 6, 6, 6), (2, 2, 2, 2), "f32", 12)])
+def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store, nv):
     """The coarsest GMRES as one cooperative launch (blocks resident in LDS,
     grid barriers) against the multi-kernel form (reserved[0] flag 4): the
     FP32 cycle with 10 fixed coarse iterations agrees to FP32 rounding and
     repeats bit for bit (every grid reduction is summed in a fixed order, so
     a repeat that differs means a workgroup read data of the wrong phase),
     and mixed solves agree in outer and coarse iteration counts (within one
-    step).  Coarse lattices of 16, 256, 512 and 324 sites (the last with a
-    partly filled final workgroup)."""
+    step).  Coarse lattices of 16 (Nb 24 and, with BF16 blocks, 32), 256,
+    512 and 81 sites (the last with a partly filled final workgroup)."""
     w = wc()
-    nv = 12
     V = int(np.prod(L))
     U = syn.gauge_field(L, 0.25, 821)
     start = syn.complex_gaussian((nv, V, 12), 822)
@@ -412,9 +414,12 @@ def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store):
         ctx.set_gauge(dev(U))
         ctx.set_null_vectors(0, dev(start))
         ctx.setup()
+        ctx.profile("coarse_gmres_persistent", True)
         x, info, st = ctx.solve(dev(r))
         assert st == 0 and info[0]["true_rel_res"] <= 1e-10
         assert ctx.timers()["coarse_solve_fallbacks"] == 0, w.lib().wcmg_last_error(ctx.h)
+        launches = ctx.profile_stats("coarse_gmres_persistent")[0]
+        assert (launches > 0) == (flags == 0), launches
         infos.append(info[0])
     assert rel(outs[0], outs[1]) < 2e-5
     assert abs(infos[0]["outer_iters"] - infos[1]["outer_iters"]) <= 1
