@@ -293,7 +293,8 @@ int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
  * "coarse_apply_bf16", "coarse_term", "coarse_mfma_f32", "coarse_mfma_bf16"
  * (batched coarse apply on the matrix cores), "coarse_gmres_step_f64",
  * "coarse_gmres_step_f32", "coarse_gmres_step_bf16" (apply step of the fused
- * coarsest GMRES), "restrict_f64", "restrict_f32", "prolong_f64",
+ * coarsest GMRES), "coarse_gmres_persistent" (a whole coarsest GMRES solve
+ * as one cooperative launch), "restrict_f64", "restrict_f32", "prolong_f64",
  * "prolong_f32", "sap_f64", "sap_f32" (one SAP colour), "nn_forward",
  * "nn_backward" (network, on its own context).  Stats return the number of
  * timed launches and their total duration in milliseconds, then reset. */
