@@ -739,6 +739,21 @@ def main():
                          "true_rel_res": inf64[0]["true_rel_res"]}
         extra["speedup_mixed_vs_fp64"] = extra["fp64"]["solve_s"] / solve_s
         del c64
+    # setup checkpoint: export the timed context's hierarchy, load it into a
+    # fresh context (rebuild from the vectors, no relaxation or refinement)
+    t_e = time.perf_counter()
+    blob = ctx.export_setup()
+    t_e = time.perf_counter() - t_e
+    c2 = make_context(w, wl, mixed=True)
+    c2.set_gauge(Ud)
+    t_i = time.perf_counter()
+    c2.import_setup(blob)
+    t_i = time.perf_counter() - t_i
+    x2, inf2, _ = c2.solve(bd)
+    extra["setup_checkpoint"] = {"bytes": len(blob), "export_s": t_e, "import_s": t_i,
+                                 "setup_s": float(np.mean(setups)), "solve_outer_iters": inf2[0]["outer_iters"],
+                                 "true_rel_res": inf2[0]["true_rel_res"]}
+    del c2, blob
     if not args.no_coarse_compare:
         print("[bench] coarse GMRES as separate kernels", file=sys.stderr, flush=True)
         extra["coarse_gmres_multi_kernel"] = coarse_multi_kernel(w, torch, wl, Ud, startd, bd)

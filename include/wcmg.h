@@ -150,6 +150,36 @@ int wcmg_refine(wcmg_ctx* ctx, int iterations);
  * rebuild P_l, D_{l+1} and the Galerkin products below. */
 int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v);
 
+/* Setup checkpoint (Sec. 2.1: a setup serves many solves, and more setup
+ * iterations buy faster solves): the hierarchy after wcmg_setup (or
+ * wcmg_setup_learned, wcmg_refine) as one host blob, to be loaded by a later
+ * context instead of running the setup again.  Layout (little-endian):
+ *   bytes   0..7    "WCMGSET1"
+ *           8..15   uint32 version (1), uint32 n_levels
+ *          16..31   int32 dims[4]
+ *          32..79   int32 block[3][4]
+ *          80..91   int32 n_vec[3]
+ *          92..95   int32 antiperiodic_t
+ *          96..111  double m0, double c_sw
+ *         112..127  uint64 payload bytes, uint64 checksum of the payload
+ *                   (64-bit FNV-1a over its 8-byte words)
+ *         128..     per level l = 0 .. n_levels-2 the near-null vectors
+ *                   complex128 [n_vec[l]][V_l][ns_l] (the layout of
+ *                   wcmg_get_null_vectors)
+ * Export: buf == NULL only reports the size in *bytes; otherwise buf (host,
+ * capacity bytes, owned by the caller) receives the blob (WCMG_ERR_ARG if it
+ * is too small; WCMG_ERR_STATE before the setup).  Import (host blob, read
+ * only): the gauge field must be set; the header must match the context
+ * (dims, levels, aggregates, n_vec, m0, c_sw, boundary) and the checksum the
+ * payload, else WCMG_ERR_ARG and the context is unchanged; then P_l and
+ * D_{l+1} are rebuilt level by level from the vectors (no relaxation, no
+ * refinement; the setup timer reports this rebuild).  With the gauge field of the exporting context
+ * the hierarchy, and every solve on it, is bit-identical to the exported one;
+ * the blob does not identify the gauge field, so pairing them is the caller's
+ * task. */
+int wcmg_setup_export(wcmg_ctx* ctx, void* buf, size_t capacity, size_t* bytes);
+int wcmg_setup_import(wcmg_ctx* ctx, const void* buf, size_t bytes);
+
 /* Aggregation map of level l -> l+1: per site of level l (lexicographic),
  * the coarse site and the offset inside its aggregate.  Host int32 arrays of V_l. */
 int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host);

@@ -194,6 +194,108 @@ int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v) {
   });
 }
 
+namespace {
+constexpr size_t kCkptHeader = 128;
+const char kCkptMagic[8] = {'W', 'C', 'M', 'G', 'S', 'E', 'T', '1'};
+
+uint64_t ckpt_hash(const unsigned char* p, size_t n) {  // 64-bit FNV-1a over 8-byte words
+  uint64_t h = 1469598103934665603ull;
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    std::memcpy(&w, p + i, 8);
+    h = (h ^ w) * 1099511628211ull;
+  }
+  for (; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+size_t ckpt_payload(const Context& c) {
+  size_t b = 0;
+  for (int l = 0; l + 1 < c.nlev; ++l) b += (size_t)c.tr[l].nv * c.geo[l].n() * sizeof(cd64);
+  return b;
+}
+
+void ckpt_header(const Context& c, unsigned char* h, uint64_t payload, uint64_t hash) {
+  std::memset(h, 0, kCkptHeader);
+  std::memcpy(h, kCkptMagic, 8);
+  const uint32_t ver = 1, nl = (uint32_t)c.nlev;
+  std::memcpy(h + 8, &ver, 4);
+  std::memcpy(h + 12, &nl, 4);
+  std::memcpy(h + 16, c.p.dims, 16);
+  for (int l = 0; l + 1 < c.nlev; ++l) {
+    std::memcpy(h + 32 + 16 * l, c.p.block[l], 16);
+    std::memcpy(h + 80 + 4 * l, &c.p.n_vec[l], 4);
+  }
+  std::memcpy(h + 92, &c.p.antiperiodic_t, 4);
+  std::memcpy(h + 96, &c.p.m0, 8);
+  std::memcpy(h + 104, &c.p.c_sw, 8);
+  std::memcpy(h + 112, &payload, 8);
+  std::memcpy(h + 120, &hash, 8);
+}
+}  // namespace
+
+int wcmg_setup_export(wcmg_ctx* ctx, void* buf, size_t capacity, size_t* bytes) {
+  return guarded(ctx, [&](Context& c) {
+    require(bytes != nullptr, WCMG_ERR_ARG, "null size output");
+    require(c.nlev >= 2, WCMG_ERR_STATE, "no multigrid hierarchy to export");
+    require(c.setup_done, WCMG_ERR_STATE, "run wcmg_setup first");
+    const size_t payload = ckpt_payload(c);
+    *bytes = kCkptHeader + payload;
+    if (!buf) return;
+    require(capacity >= kCkptHeader + payload, WCMG_ERR_ARG, "export buffer too small");
+    unsigned char* out = (unsigned char*)buf;
+    size_t off = kCkptHeader;
+    for (int l = 0; l + 1 < c.nlev; ++l) {
+      const int nv = c.tr[l].nv;
+      const size_t nb = (size_t)nv * c.geo[l].n() * sizeof(cd64);
+      cd64* tmp = c.buf<cd64>("ckpt", (long)nv * c.geo[l].n());
+      level_vectors_out(c, l, c.tr[l].vecs64.as<cd64>(), tmp, nv);
+      WCMG_HIP(hipMemcpyAsync(out + off, tmp, nb, hipMemcpyDeviceToHost, c.stream));
+      c.sync();
+      off += nb;
+    }
+    ckpt_header(c, out, payload, ckpt_hash(out + kCkptHeader, payload));
+  });
+}
+
+int wcmg_setup_import(wcmg_ctx* ctx, const void* buf, size_t bytes) {
+  return guarded(ctx, [&](Context& c) {
+    require(buf != nullptr, WCMG_ERR_ARG, "null checkpoint");
+    require(c.nlev >= 2, WCMG_ERR_STATE, "no multigrid hierarchy to import");
+    require(c.gauge_set, WCMG_ERR_STATE, "set the gauge field first");
+    require(bytes >= kCkptHeader, WCMG_ERR_ARG, "checkpoint truncated");
+    const unsigned char* in = (const unsigned char*)buf;
+    require(std::memcmp(in, kCkptMagic, 8) == 0, WCMG_ERR_ARG, "not a setup checkpoint");
+    const size_t payload = ckpt_payload(c);
+    unsigned char want[kCkptHeader];
+    uint64_t have_payload = 0, have_hash = 0;
+    std::memcpy(&have_payload, in + 112, 8);
+    std::memcpy(&have_hash, in + 120, 8);
+    ckpt_header(c, want, payload, have_hash);
+    require(std::memcmp(in, want, 112) == 0, WCMG_ERR_ARG,
+            "checkpoint was written for another lattice, hierarchy or operator");
+    require(have_payload == payload && bytes == kCkptHeader + payload, WCMG_ERR_ARG, "checkpoint size mismatch");
+    require(ckpt_hash(in + kCkptHeader, payload) == have_hash, WCMG_ERR_ARG, "checkpoint checksum mismatch");
+    auto t0 = std::chrono::steady_clock::now();
+    c.setup_done = false;
+    for (int q = 0; q < 5; ++q) c.timers[q] = 0.0;
+    size_t off = kCkptHeader;
+    for (int l = 0; l + 1 < c.nlev; ++l) {
+      const int nv = c.tr[l].nv;
+      const size_t nb = (size_t)nv * c.geo[l].n() * sizeof(cd64);
+      cd64* tmp = c.buf<cd64>("ckpt", (long)nv * c.geo[l].n());
+      WCMG_HIP(hipMemcpyAsync(tmp, in + off, nb, hipMemcpyHostToDevice, c.stream));
+      level_vectors_in(c, l, tmp, c.tr[l].vecs64.as<cd64>(), nv);
+      c.rebuild(l);
+      off += nb;
+    }
+    c.sync();
+    c.timers[0] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c.setup_done = true;
+  });
+}
+
 int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host) {
   return guarded(ctx, [&](Context& c) {
     check_level(c, level, true);

@@ -67,6 +67,8 @@ def lib():
                      "wcmg_get_coarse_op", "wcmg_set_coarse_op"):
             getattr(l, name).argtypes = [vp, ip, vp]
         l.wcmg_setup.argtypes = [vp]
+        l.wcmg_setup_export.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        l.wcmg_setup_import.argtypes = [vp, vp, C.c_size_t]
         l.wcmg_refine.argtypes = [vp, ip]
         l.wcmg_get_aggregate_map.argtypes = [vp, ip, vp, vp]
         for name in ("wcmg_apply_D", "wcmg_restrict", "wcmg_prolong"):
@@ -213,6 +215,23 @@ class Context:
 
     def refine(self, iters):
         self._chk(lib().wcmg_refine(self.h, int(iters)))
+
+    def export_setup(self):
+        """The hierarchy as a setup checkpoint (a bytearray; wcmg_setup_export)."""
+        n = C.c_size_t(0)
+        self._chk(lib().wcmg_setup_export(self.h, None, 0, C.byref(n)))
+        out = bytearray(n.value)
+        cbuf = (C.c_char * n.value).from_buffer(out)
+        self._chk(lib().wcmg_setup_export(self.h, cbuf, n.value, C.byref(n)))
+        return out
+
+    def import_setup(self, blob):
+        """Load a setup checkpoint (bytes or bytearray; wcmg_setup_import)."""
+        if isinstance(blob, bytearray):
+            ptr = (C.c_char * len(blob)).from_buffer(blob)
+        else:
+            ptr = C.c_char_p(bytes(blob))
+        self._chk(lib().wcmg_setup_import(self.h, ptr, len(blob)))
 
     def aggregate_map(self, level):
         import numpy as np
