@@ -105,7 +105,11 @@ typedef struct {
                               Dhat = A_oo - H_oe A_ee^{-1} H_eo (Sec. 2.1 and Sec. 4 name red-black
                               preconditioning; see wcmg_apply_schur) with the MG cycle embedded as its
                               preconditioner, then reconstructs the even sites */
-  int32_t reserved[1];
+  int32_t reserved[1];     /* reserved[0]: flags selecting reference forms, for comparisons (default 0):
+                              1 no host progress checks inside cycles; 2 the generic coarsest GMRES;
+                              4 the coarsest GMRES as four kernels per Arnoldi step instead of one
+                              cooperative launch; 8 the outer Arnoldi step as classical Gram-Schmidt applied
+                              twice instead of the single-reduction step */
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;

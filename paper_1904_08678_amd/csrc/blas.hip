@@ -147,6 +147,78 @@ __global__ void __launch_bounds__(256) k_multi_axpy_norm(cplx<R>* __restrict__ y
   }
 }
 
+// Single-reduction Arnoldi step, first sweep: y = V_{j+1} - s V_j written
+// back (s = *shift; no shift when shift is null), then per-workgroup partials
+// of <V_q, y> for q <= j and of |y|^2 (entry j + 1), mstride entries per
+// workgroup.  Columns are taken KT at a time; only the first tile forms y.
+template <typename R>
+__global__ void __launch_bounds__(256) k_arnoldi_dots(cplx<R>* __restrict__ V, long n, int j,
+                                                       const cd64* __restrict__ shift, cd64* __restrict__ partial,
+                                                       int mstride, const int* __restrict__ run) {
+  if (run && !*run) return;
+  constexpr int KT = 8;
+  __shared__ cd64 lds[4][KT];
+  const int m = j + 2;
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const R sh = shift ? (R)shift->re : (R)0;
+  cplx<R>* yv = V + (long)(j + 1) * n;
+  for (int k0 = 0; k0 < m; k0 += KT) {
+    cd64 s[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
+    for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      cplx<R> y = yv[i];
+      if (k0 == 0 && shift) {
+        y = csub(y, cscale(sh, V[(long)j * n + i]));
+        yv[i] = y;
+      }
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int k = k0 + q;
+        if (k < m) {
+          const cplx<R> x = k == j + 1 ? y : V[(long)k * n + i];
+          s[q].re += (double)x.re * y.re + (double)x.im * y.im;
+          s[q].im += (double)x.re * y.im - (double)x.im * y.re;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      s[q] = wave_sum(s[q]);
+      if (lane == 0) lds[wave][q] = s[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < KT && k0 + (int)threadIdx.x < m) {
+      cd64 t = mkc(0.0, 0.0);
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w][threadIdx.x]);
+      partial[(long)blockIdx.x * mstride + k0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Single-reduction Arnoldi step, last sweep: y = (y - sum_{k<m} coef[k] V_k)
+// / sqrt(*nrm2) (y = 0 when *nrm2 is 0).
+template <typename R>
+__global__ void __launch_bounds__(256) k_update_scale(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ V,
+                                                       long vstride, int m, const cd64* __restrict__ coef,
+                                                       const cd64* __restrict__ nrm2, long n,
+                                                       const int* __restrict__ run) {
+  if (run && !*run) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double q = nrm2->re;
+  const R inv = q > 0.0 ? (R)(1.0 / sqrt(q)) : (R)0;
+  cplx<R> acc = y[i];
+  for (int k = 0; k < m; ++k) {
+    const cd64 c = coef[k];
+    cfma(acc, mkc((R)-c.re, (R)-c.im), V[k * vstride + i]);
+  }
+  y[i] = cscale(inv, acc);
+}
+
 // y = a * x + b * y with real constants
 template <typename R>
 __global__ void k_axpby(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, R a, R b, long n,
@@ -281,6 +353,41 @@ __global__ void k_gmres_cycle_start(int* st, cd64* S, int m, double tol, int lim
   for (int i = 0; i <= m; ++i) g[i] = mkc(0.0, 0.0);
   g[0] = mkc(beta, 0.0);
   st[0] = 1;
+}
+
+// Single-reduction Arnoldi step, bookkeeping (one thread).  stage 0, with d
+// the first sweep's j + 2 sums (<v_i, w'> and |w'|^2 for w' = A z_j - s v_j):
+// column j of H = d (+ s on the diagonal; at j = 0 there is no shift and s is
+// set to Re d_0 for the later steps of the cycle), hn^2 = |w'|^2 - |d|^2, and
+// st[5] = 1 (repeat the projection) when that is below |w'|^2 / 4.
+// stage 1 (only when st[5]), with d2 the second sweep's sums: column j += d2,
+// hn^2 = |w1|^2 - |d2|^2, and d = d2 for the final update.
+__global__ void k_gmres_sr(int* st, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage) {
+  cd64* H = S;
+  cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+  if (stage == 0) {
+    st[5] = 0;
+    if (!st[0]) return;
+    const double n0 = d[j + 1].re;
+    double n1 = n0;
+    for (int i = 0; i <= j; ++i) {
+      H[i * m + j] = d[i];
+      n1 -= d[i].re * d[i].re + d[i].im * d[i].im;
+    }
+    if (j == 0) misc[4] = mkc(d[0].re, 0.0);
+    else H[j * m + j].re += misc[4].re;
+    misc[3] = mkc(n1 > 0.0 ? n1 : 0.0, 0.0);
+    st[5] = n1 < 0.25 * n0 ? 1 : 0;
+  } else {
+    if (!st[0] || !st[5]) return;
+    double n2 = d2[j + 1].re;
+    for (int i = 0; i <= j; ++i) {
+      H[i * m + j] = cadd(H[i * m + j], d2[i]);
+      n2 -= d2[i].re * d2[i].re + d2[i].im * d2[i].im;
+      d[i] = d2[i];
+    }
+    misc[3] = mkc(n2 > 0.0 ? n2 : 0.0, 0.0);
+  }
 }
 
 // Givens update for column j (after H[0..j][j] and hn^2 = misc[3]).
@@ -486,6 +593,29 @@ void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit,
   hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, st, st_, S, m, j, tol, limit, fixed, stop_on_est);
   WCMG_CHECK_LAUNCH();
 }
+void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_sr, dim3(1), dim3(1), 0, st, st_, S, m, j, d, d2, stage);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_dots<R>, dim3(red_blocks(n)), dim3(kBlock), 0, st, V, n, j, shift, partial, mstride,
+                     run);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_update_scale(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, const cd64* nrm2,
+                         long n, const int* run, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_scale<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, V, vstride, m, coef, nrm2, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_arnoldi_dots<double>(cd64*, long, int, const cd64*, cd64*, int, const int*, hipStream_t);
+template void launch_arnoldi_dots<float>(cf32*, long, int, const cd64*, cd64*, int, const int*, hipStream_t);
+template void launch_update_scale<double>(cd64*, const cd64*, long, int, const cd64*, const cd64*, long, const int*,
+                                          hipStream_t);
+template void launch_update_scale<float>(cf32*, const cf32*, long, int, const cd64*, const cd64*, long, const int*,
+                                         hipStream_t);
 void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_gmres_solve_y, dim3(1), dim3(1), 0, st, st_, S, m);
   WCMG_CHECK_LAUNCH();

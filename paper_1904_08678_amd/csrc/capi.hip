@@ -486,6 +486,7 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
       if (c.nlev >= 2) c.precondition64(0, i, o, rn);
       else launch_convert<double, double>(i, o, c.n(0), rn, c.stream);
     };
+    const bool sr = !(c.p.reserved[0] & 8);  // single-reduction Arnoldi step in the outer solve
     for (int k = 0; k < nrhs; ++k) {
       auto t0 = std::chrono::steady_clock::now();
       c.coarse_iters = 0;
@@ -531,14 +532,14 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
         const double tol = bhn > 0 ? c.p.outer_tol * bn / bhn : c.p.outer_tol;
         GmresState& G = c.gmres_state("outer_eo", c.p.outer_restart, nh, 0, true);
         its = c.gmres<double>(G, Ah, &Mh, bc, xc, false, c.p.outer_restart, c.p.outer_maxit, tol, 0, false, nullptr,
-                              1);
+                              1, sr);
         launch_eo_scatter<double>(xc, x64, pos, par, V, Vh, c.stream);
         c.apply_op<double>(0, x64, t, 1, nullptr, 0x1fe);
         launch_eo_local<double>(b64, t, x64, c.clovinv64.as<double>(), par, 0, 3, V, c.stream);
       } else {
         GmresState& G = c.gmres_state("outer", c.p.outer_restart, nn, 0, true);
         its = c.gmres<double>(G, A, &M, b64, x64, false, c.p.outer_restart, c.p.outer_maxit, c.p.outer_tol, 0,
-                              false, nullptr, 1);
+                              false, nullptr, 1, sr);
       }
       // true residual in FP64
       c.apply_op<double>(0, x64, r64, 1, nullptr);

@@ -264,7 +264,7 @@ struct Context {
   int gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<R>*, const int*)>& A,
             const std::function<void(const cplx<R>*, cplx<R>*, const int*)>* M, const cplx<R>* b, cplx<R>* x,
             bool x0_zero, int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent,
-            int check_every);
+            int check_every, bool single_reduction = false);
   template <typename R>
   void restrict_(int l, const cplx<R>* fine, cplx<R>* coarse, int nrhs, const int* run);
   template <typename R>

@@ -331,7 +331,7 @@ GmresState& Context::gmres_state(const std::string& tag, int m, long n, int prec
     G.V.alloc((size_t)(m + 1) * n * cb);
     if (flex) G.Z.alloc((size_t)m * n * cb);
     G.w.alloc((size_t)n * cb);
-    G.S.alloc((size_t)((m + 1) * m + 2 * m + (m + 1) + m + 8 + (m + 1)) * sizeof(cd64));
+    G.S.alloc((size_t)((m + 1) * m + 2 * m + (m + 1) + m + 8 + 2 * (m + 1)) * sizeof(cd64));
     G.st.alloc(8 * sizeof(int));
   }
   return G;
@@ -469,7 +469,7 @@ template <typename R>
 int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<R>*, const int*)>& A,
                    const std::function<void(const cplx<R>*, cplx<R>*, const int*)>* M, const cplx<R>* b, cplx<R>* x,
                    bool x0_zero, int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent,
-                   int check_every) {
+                   int check_every, bool single_reduction) {
   const long nn = G.n;
   const int m = restart;
   cplx<R>* V = G.V.as<cplx<R>>();
@@ -481,6 +481,7 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
   cd64* y = g + (m + 1);
   cd64* misc = y + m;
   cd64* tmp = misc + 8;
+  cd64* tmp2 = tmp + (m + 1);
   int* st = G.st.as<int>();
   int* run = st;
   int* live = st + 1;
@@ -509,6 +510,32 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
       cplx<R>* vj = V + (long)j * nn;
       cplx<R>* zj = M ? Z + (long)j * nn : vj;
       if (M) (*M)(vj, zj, run);
+      if (single_reduction) {
+        // One sweep gives the dots of w' = A z_j - s v_j (formed in place in
+        // the slot of v_{j+1}; s = Re h_00 of the cycle, none at j = 0) with
+        // the basis and |w'|^2; |w1|^2 = |w'|^2 - |h|^2 (V orthonormal), and
+        // the projection is repeated only when it removed more than 3/4 of
+        // |w'|^2 (st[5]); the last sweep subtracts and normalises.  A z_j is
+        // mostly along v_j when the preconditioner is good, so projecting w'
+        // instead of A z_j avoids that cancellation; the Hessenberg column of
+        // A Z is h + s e_j.
+        cplx<R>* wj = V + (long)(j + 1) * nn;
+        A(zj, wj, run);
+        launch_arnoldi_dots<R>(V, nn, j, j > 0 ? misc + 4 : nullptr, part, j + 2, run, stream);
+        launch_dot_finish(part, Gb, j + 2, j + 2, tmp, 1, 0, run, stream);
+        launch_gmres_sr(st, S, m, j, tmp, tmp2, 0, stream);
+        launch_multi_axpy<R>(wj, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, st + 5, stream);
+        launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream);
+        launch_dot_finish(part, Gb, j + 2, j + 2, tmp2, 1, 0, st + 5, stream);
+        launch_gmres_sr(st, S, m, j, tmp, tmp2, 1, stream);
+        launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
+        if (j + 1 < m) launch_update_scale<R>(wj, V, nn, j + 1, tmp, misc + 3, nn, run, stream);
+        if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
+          read_state();
+          if (!pinned[0]) break;
+        }
+        continue;
+      }
       A(zj, w, run);
       // classical Gram-Schmidt applied twice; |w|^2 comes out of the last update
       launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, H + j, m, 0, run, stream);
@@ -940,10 +967,10 @@ template int Context::coarse_gmres<float>(int, const cf32*, cf32*, const int*, i
 template void Context::cycle<float>(int, const cf32*, cf32*, const int*);
 template int Context::gmres<double>(GmresState&, const std::function<void(const cd64*, cd64*, const int*)>&,
                                     const std::function<void(const cd64*, cd64*, const int*)>*, const cd64*, cd64*,
-                                    bool, int, int, double, int, bool, const int*, int);
+                                    bool, int, int, double, int, bool, const int*, int, bool);
 template int Context::gmres<float>(GmresState&, const std::function<void(const cf32*, cf32*, const int*)>&,
                                    const std::function<void(const cf32*, cf32*, const int*)>*, const cf32*, cf32*,
-                                   bool, int, int, double, int, bool, const int*, int);
+                                   bool, int, int, double, int, bool, const int*, int, bool);
 template double Context::norm2_host<double>(const cd64*, long);
 template double Context::norm2_host<float>(const cf32*, long);
 template cd64* Context::buf<cd64>(const std::string&, long);

@@ -135,6 +135,15 @@ void launch_gmres_cycle_start(int* st_, cd64* S, int m, double tol, int limit, i
 void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit, int fixed, int stop_on_est,
                          hipStream_t st);
 void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
+// single-reduction Arnoldi step (blas.hip): first sweep (shifted vector, its
+// dots with V_0..V_j and its norm), bookkeeping, last sweep (update + scale)
+void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st);
+template <typename R>
+void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
+                         hipStream_t st);
+template <typename R>
+void launch_update_scale(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, const cd64* nrm2,
+                         long n, const int* run, hipStream_t st);
 void launch_gmres_cycle_end(int* st_, hipStream_t st);
 
 // ---- the coarsest GMRES in one cooperative launch (coarse_persist.hip):

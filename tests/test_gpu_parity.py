@@ -426,6 +426,39 @@ def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store, nv)
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
 
 
+@pytest.mark.parametrize("levels,mixed,eo", [(2, True, 0), (2, False, 0), (1, False, 0), (2, True, 1)])
+def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo):
+    """The outer FGMRES with one reduction per Arnoldi step (shifted vector,
+    norm from |w'|^2 - |h|^2, second projection only on heavy cancellation,
+    which the unshifted first step of every cycle takes) against classical
+    Gram-Schmidt applied twice (reserved[0] flag 8): same outer iteration
+    counts, solutions equal to 1e-12, both to the 1e-10 target.  Two-level
+    mixed and FP64, one level (unpreconditioned GMRES), even-odd."""
+    w = wc()
+    L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 1931)
+    start = syn.complex_gaussian((nv, V, 12), 1932)
+    b = syn.complex_gaussian((V, 4, 3), 1933)
+    xs, infos = [], []
+    for flags in (0, 8):
+        kw = dict(dims=L, m0=-0.05 if levels > 1 else 0.3, n_levels=levels, block=(block,), n_vec=(nv,),
+                  even_odd=eo, reserved=(flags,), outer_maxit=4000)
+        if mixed:
+            kw.update(cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32)
+        ctx = w.Context(**kw)
+        ctx.set_gauge(dev(U))
+        if levels > 1:
+            ctx.set_null_vectors(0, dev(start))
+            ctx.setup()
+        x, info, st = ctx.solve(dev(b))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        xs.append(host(x))
+        infos.append(info[0])
+    assert infos[0]["outer_iters"] == infos[1]["outer_iters"], (infos[0]["outer_iters"], infos[1]["outer_iters"])
+    assert rel(xs[0], xs[1]) < 1e-12
+
+
 @pytest.mark.parametrize("Lc,nb,nrhs", [((2, 2, 2, 2), 8, 12), ((3, 2, 2, 4), 16, 5), ((4, 4, 4, 8), 24, 12),
                                          ((2, 3, 2, 2), 24, 16), ((3, 3, 2, 2), 32, 12), ((2, 2, 2, 2), 40, 17)])
 def test_coarse_apply_matrix_cores_parity(Lc, nb, nrhs):
