@@ -11,7 +11,7 @@
 
 namespace wcmg {
 
-constexpr int kRedBlocks = 512;  // partials per reduction (fixed: results do not depend on timing)
+constexpr int kRedBlocks = 2048;  // partials per reduction (fixed: results do not depend on timing)
 
 inline int red_blocks(long n) { return (int)std::min<long>(kRedBlocks, std::max<long>(1, (n + 1023) / 1024)); }
 

@@ -539,15 +539,18 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
       A(zj, w, run);
       // classical Gram-Schmidt applied twice; |w|^2 comes out of the last update
       launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, H + j, m, 0, run, stream);
+      // the partials of the second projection: from the fused sweep (the
+      // batched kernels' block count) or from a separate dot pass
+      const int Gp = j + 1 <= kFusedMaxM ? bred_blocks(nn) : Gb;
       if (j + 1 <= kFusedMaxM) {
         // first update and second projection in one sweep over the basis
         launch_bmulti_axpy_dot<R>(w, 0, V, nn, 0, j + 1, H + j, m, 0, nn, 1, part, run, 0, stream);
-        launch_dot_finish(part, Gb, j + 1, j + 1, tmp, 1, 0, run, stream);
+        launch_dot_finish(part, Gp, j + 1, j + 1, tmp, 1, 0, run, stream);
       } else {
         launch_multi_axpy<R>(w, V, nn, j + 1, nullptr, H + j, m, -1.0, nn, run, stream);
         launch_dot<R>(V, nn, j + 1, nullptr, w, nn, part, j + 1, tmp, 1, 0, run, stream);
       }
-      launch_dot_finish(part, Gb, j + 1, j + 1, H + j, m, 1, run, stream);
+      launch_dot_finish(part, Gp, j + 1, j + 1, H + j, m, 1, run, stream);
       launch_multi_axpy_norm<R>(w, V, nn, j + 1, tmp, 1, -1.0, nn, part, run, stream);
       launch_dot_finish(part, Gb, 1, 1, misc + 3, 1, 0, run, stream);
       launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);

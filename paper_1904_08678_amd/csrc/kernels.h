@@ -257,6 +257,6 @@ struct RaggedTable {
 };
 void launch_coarse_apply_mfma_ragged(int prec, RaggedTable t, hipStream_t st);
 
-constexpr int kPartialSlots = 512 * 48;  // partial buffer entries (blocks x max dots)
+constexpr int kPartialSlots = 2048 * 48;  // partial buffer entries (blocks x max dots)
 
 }  // namespace wcmg
