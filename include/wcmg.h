@@ -109,7 +109,9 @@ typedef struct {
                               1 no host progress checks inside cycles; 2 the generic coarsest GMRES;
                               4 the coarsest GMRES as four kernels per Arnoldi step instead of one
                               cooperative launch; 8 the outer Arnoldi step as classical Gram-Schmidt applied
-                              twice instead of the single-reduction step */
+                              twice instead of the single-reduction step; 16 the cooperative launch's barrier
+                              waits give up at once (every such solve then takes the four-kernel fallback: a
+                              test of that path) */
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;

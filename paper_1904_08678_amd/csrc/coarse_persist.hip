@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     const Chunk16* __restrict__ blk, const int* __restrict__ nbr, long Vc, const cplx<typename BlkTraits<P>::R>* b,
     cplx<typename BlkTraits<P>::R>* x, cplx<typename BlkTraits<P>::R>* zg, cplx<typename BlkTraits<P>::R>* r,
     cd64* part, cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
-    long long tick_limit) {
+    unsigned phase0, int* mailbox, long long tick_limit) {
   typedef PShape<P, NB> Sh;
   typedef typename Sh::R R;
   constexpr int K = Sh::K, NCH = Sh::NCH, NQ = Sh::NQ, ROWS = Sh::rows, SL = Sh::S;
@@ -192,7 +192,20 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     st[3] = 0;
     st[4] = 0;
   }
-  if (!ctl[1]) return;  // uniform: every workgroup reads the same flag
+  // the normal end of the launch, reported by workgroup 0 (after every
+  // barrier has been passed, unless a wait timed out somewhere)
+  auto report = [&](unsigned final_phase) {
+    if (blockIdx.x == 0 && tid == 0 && __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      __hip_atomic_store(mailbox + 1, ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(mailbox + 3, ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(mailbox + 4, (int)final_phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(mailbox, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  };
+  if (!ctl[1]) {  // uniform: every workgroup reads the same flag
+    report(phase0);
+    return;
+  }
 
   // this workgroup's rows of the nine blocks, resident for the whole solve
   {
@@ -279,7 +292,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   // write the next phase's partials while a slower one still reads the
   // previous phase's, and it can only come back to a buffer after the next
   // barrier, which every reader of that buffer has reached.
-  unsigned phase = 0;
+  unsigned phase = phase0;
   int pb = 0;
   const int ent = wred8_entry(lane);
   auto reduce = [&](int cnt, auto contrib) -> bool {
@@ -509,6 +522,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     st[2] = 0;
     st[3] = ctl[3];
   }
+  report(phase);
 }
 
 namespace {
@@ -523,7 +537,7 @@ bool cgp_shape_fits() {
 template <int P, int NB>
 bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* z, void* r, cd64* part,
                 cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
-                long long tick_limit, hipStream_t stream) {
+                unsigned phase0, int* mailbox, long long tick_limit, hipStream_t stream) {
   if constexpr (!PShape<P, NB>::fits) {
     return false;
   } else {
@@ -543,7 +557,8 @@ bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x
     cplx<R>* rr = (cplx<R>*)r;
     void* args[] = {(void*)&bk,   (void*)&nbr, (void*)&Vc,    (void*)&bc,    (void*)&xx,    (void*)&zz,
                     (void*)&rr,   (void*)&part, (void*)&misc, (void*)&st,    (void*)&parent, (void*)&m,
-                    (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&tick_limit};
+                    (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&phase0,
+                    (void*)&mailbox, (void*)&tick_limit};
     WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
     return true;
   }
@@ -580,7 +595,8 @@ size_t cg_persistent_bar_words(long Vc) { return (size_t)kBarWords + (size_t)kFl
 
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
-                          int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream) {
+                          int limit, int fixed, unsigned* bar, unsigned phase0, int* mailbox, double timeout_s,
+                          hipStream_t stream) {
   if (!cg_persistent_fits(prec, nb, Vc)) return false;
   int dev = 0, khz = 0;
   WCMG_HIP(hipGetDevice(&dev));
@@ -588,7 +604,7 @@ bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, lon
   const long long tick_limit = (long long)(timeout_s * 1000.0 * (khz > 0 ? khz : 100000));
 #define CGP(PP, NBc) \
   return cgp_launch<PP, NBc>(blk, nbr, Vc, b, x, z, r, part, misc, st, parent, m, tol, limit, fixed, bar, \
-                             tick_limit, stream)
+                             phase0, mailbox, tick_limit, stream)
   if (prec == WCMG_F32) {
     switch (nb) {
       case 8: CGP(WCMG_F32, 8);

@@ -195,6 +195,14 @@ struct Context {
   // grid-barrier timeout, and the last timeout's report
   long cgp_fallbacks = 0;
   std::string cgp_last_report;
+  // the cooperative coarsest GMRES: its barrier flags count phases across
+  // launches (per level and precision: the phase the next launch starts
+  // from, 0 = flags must be cleared first), and it reports completion in a
+  // coherent host-mapped mailbox instead of through copies
+  std::map<std::string, unsigned> cgp_phase;
+  std::map<std::string, void*> cgp_bar_at;
+  int* mailbox = nullptr;
+  int* mailbox_dev = nullptr;
   // workspaces
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::map<std::string, std::unique_ptr<GmresState>> gm;

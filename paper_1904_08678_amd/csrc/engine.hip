@@ -294,6 +294,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   bpart.alloc((size_t)16 * kPartialSlots * sizeof(cd64));
   scratch64.alloc(64 * sizeof(cd64));
   WCMG_HIP(hipHostMalloc((void**)&pinned, 256 * sizeof(int), hipHostMallocDefault));
+  WCMG_HIP(hipHostMalloc((void**)&mailbox, 16 * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+  WCMG_HIP(hipHostGetDevicePointer((void**)&mailbox_dev, mailbox, 0));
   const long V0 = geo[0].V;
   U_lex.alloc(V0 * 36 * sizeof(cd64));
   clover_lex.alloc(V0 * 72 * sizeof(cd64));
@@ -307,6 +309,7 @@ Context::~Context() {
   drop_graph();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
+  if (mailbox) (void)hipHostFree(mailbox);
 }
 
 template <typename T>
@@ -621,19 +624,32 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
     cd64* partP = buf<cd64>("cgp_part" + t, (long)cg_persistent_part_elems(C.V));
     const long nbar = (long)cg_persistent_bar_words(C.V);
     unsigned* bar = buf<unsigned>("cgp_bar" + t, nbar);
-    WCMG_HIP(hipMemsetAsync(bar, 0, nbar * sizeof(unsigned), stream));
     cplx<R>* zP = buf<cplx<R>>("cgp_z" + t, 2 * nn);
     cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+    // the flags keep counting phases from launch to launch; they are cleared
+    // only for a new buffer or after a timed-out launch
+    unsigned& phase = cgp_phase[t];
+    if (cgp_bar_at[t] != (void*)bar) phase = 0;
+    if (phase == 0) WCMG_HIP(hipMemsetAsync(bar, 0, nbar * sizeof(unsigned), stream));
+    cgp_bar_at[t] = (void*)bar;
+    volatile int* mb = mailbox;
+    mb[0] = kCgpPending;
     prof.begin("coarse_gmres_persistent", stream);
     const bool launched = launch_cg_persistent(prec, nb, blk, C.nbr.as<int>(), C.V, b, x, zP, r, partP, misc, st,
-                                               parent, m, p.coarse_tol, limit, fixed, bar, 5.0, stream);
+                                               parent, m, p.coarse_tol, limit, fixed, bar, phase, mailbox_dev,
+                                               (p.reserved[0] & 16) ? 0.0 : 5.0, stream);
     prof.end("coarse_gmres_persistent", stream);
     if (launched) {
-      WCMG_HIP(hipMemcpyAsync(pinned, st, 5 * sizeof(int), hipMemcpyDeviceToHost, stream));
+      sync();
+      if (mb[0] == 0) {
+        phase = (unsigned)mb[4];
+        return mb[3];
+      }
+      // a barrier wait timed out (the mailbox was not written): keep the
+      // report, clear the flags before the next launch, redo the solve below
       WCMG_HIP(hipMemcpyAsync(pinned + 8, bar, 8 * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
       sync();
-      if (pinned[10] == 0) return pinned[3];
-      // a barrier wait timed out: keep the report and redo the solve below
+      phase = 0;
       cgp_fallbacks++;
       cgp_last_report = "workgroup " + std::to_string(pinned[11]) + " of " + std::to_string((C.V + 1) / 2) +
                         " timed out at phase " + std::to_string(pinned[12]) + " waiting for workgroup " +

@@ -151,7 +151,12 @@ void launch_gmres_cycle_end(int* st_, hipStream_t st);
 // fit the LDS of co-resident workgroups; part: cd64 [cg_persistent_part_elems];
 // bar: cg_persistent_bar_words zeroed words (bar[2] is set when a barrier
 // wait timed out, bar[3..6] then hold the first timed-out workgroup, the
-// phase, the workgroup it waited for and the flag value it saw); misc: the
+// phase, the workgroup it waited for and the flag value it saw; the flags
+// hold phase numbers, which continue from phase0, the final phase of the
+// previous launch on the same buffer); mailbox (host-mapped, coherent): at a
+// normal end workgroup 0 writes [1] live flag, [3] iterations, [4] final
+// phase, then [0] = 0; a launch that ended otherwise leaves [0] as the host
+// set it; misc: the
 // solve's residual words, as the multi-kernel form writes them; z: 2 Vc Nb
 // vector elements; r: Vc Nb
 bool cg_persistent_fits(int prec, int nb, long Vc);
@@ -159,7 +164,10 @@ size_t cg_persistent_part_elems(long Vc);
 size_t cg_persistent_bar_words(long Vc);
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
-                          int limit, int fixed, unsigned* bar, double timeout_s, hipStream_t stream);
+                          int limit, int fixed, unsigned* bar, unsigned phase0, int* mailbox, double timeout_s,
+                          hipStream_t stream);
+// mailbox word 0 while a cooperative coarsest solve has not reported
+constexpr int kCgpPending = 0x5a5a5a5a;
 
 // ---- fused coarse GMRES (coarse_gmres.hip)
 bool cg_fused_supported(int nb);

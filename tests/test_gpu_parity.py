@@ -426,6 +426,37 @@ def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store, nv)
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
 
 
+def test_cooperative_coarse_gmres_timeout_falls_back():
+    """Barrier waits that give up at once (reserved[0] flag 16; every kernel
+    still exits normally): each cooperative coarsest solve reports no
+    completion, the host clears the barrier flags and redoes it with the
+    four-kernel form, so the solve equals the four-kernel solve; the
+    fallbacks are counted and the last one is described."""
+    w = wc()
+    L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 1941)
+    start = syn.complex_gaussian((nv, V, 12), 1942)
+    b = syn.complex_gaussian((V, 4, 3), 1943)
+    res = []
+    for flags in (16, 4, 0):
+        ctx = w.Context(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), cycle_prec=w.F32,
+                        coarse_store_prec=w.F32, setup_prec=w.F32, reserved=(flags,))
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        x, info, st = ctx.solve(dev(b))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        res.append((host(x), info[0], ctx.timers()["coarse_solve_fallbacks"], w.lib().wcmg_last_error(ctx.h)))
+    (x16, i16, f16, e16), (x4, i4, f4, _), (x0, i0, f0, _) = res
+    assert f16 > 0 and f4 == 0 and f0 == 0
+    assert b"timed out" in e16, e16
+    assert np.array_equal(x16, x4) and i16["outer_iters"] == i4["outer_iters"]
+    assert i16["coarse_iters"] == i4["coarse_iters"]
+    # the cooperative form itself agrees with both
+    assert abs(i0["outer_iters"] - i4["outer_iters"]) <= 1
+
+
 @pytest.mark.parametrize("levels,mixed,eo", [(2, True, 0), (2, False, 0), (1, False, 0), (2, True, 1)])
 def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo):
     """The outer FGMRES with one reduction per Arnoldi step (shifted vector,
