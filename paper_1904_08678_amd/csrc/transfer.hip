@@ -3,8 +3,9 @@
 //
 // Restriction is owned per coarse site (one workgroup per aggregate, the
 // race-free scheme of Sec. 3): the workgroup walks its aggregate through the
-// coarse-to-fine lookup table, every lane accumulates partial inner products,
-// and a fixed-order wave + LDS reduction produces the coarse components.
+// coarse-to-fine lookup table, every lane accumulates partial inner products
+// of one chirality, and a fixed-order wave + LDS reduction produces the
+// coarse components.
 // No atomics, so results are bitwise reproducible.
 //
 // Prolongator storage: P holds nv vectors [nv][level layout]; the chirality
@@ -15,34 +16,13 @@
 
 namespace wcmg {
 
-// Sum over the workgroup of NB complex values per lane, fixed order.
-// Result is valid in lds_out[0..NB) for every lane after the call.
-template <int NB>
-__device__ inline void block_sum(cd64 (&acc)[NB], cd64* lds /*[16][NB]*/, cd64* lds_out /*[NB]*/) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    double re = acc[b].re, im = acc[b].im;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      re += __shfl_xor(re, off, 64);
-      im += __shfl_xor(im, off, 64);
-    }
-    if (lane == 0) lds[wave * NB + b] = mkc(re, im);
-  }
-  __syncthreads();
-  if (threadIdx.x < NB) {
-    cd64 s = mkc(0.0, 0.0);
-    for (int w = 0; w < nw; ++w) s = cadd(s, lds[w * NB + threadIdx.x]);
-    lds_out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 // coarse(c, b) = sum_{x in c} sum_{k in chi(b)} conj(P_{b mod nv}(x)_k) fine(x)_k
-// grid item_rhs_grid(Vc, nrhs), block 256.
+// grid item_rhs_grid(Vc, nrhs), block 512: waves 0-3 take chirality 0 and
+// waves 4-7 chirality 1 of the aggregate's sites (a lane per site), so each
+// lane keeps nv accumulators and each wave reduces nv entries; the four
+// waves of a chirality are then added in order in LDS.
 template <typename R, int NB>
-__global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fine, cplx<R>* __restrict__ coarse,
+__global__ void __launch_bounds__(512) k_restrict(const cplx<R>* __restrict__ fine, cplx<R>* __restrict__ coarse,
                                                    const cplx<R>* __restrict__ P, FieldLayout lay,
                                                    const int* __restrict__ agg_sites, int A, long Vc,
                                                    int nrhs, const int* __restrict__ run, int rs) {
@@ -50,34 +30,48 @@ __global__ void __launch_bounds__(256) k_restrict(const cplx<R>* __restrict__ fi
   if (!item_rhs(Vc, nrhs, &c, &r)) return;
   if (run && !run[r * rs]) return;
   constexpr int nv = NB / 2;
-  __shared__ cd64 lds[16 * NB];
-  __shared__ cd64 res[NB];
+  __shared__ cd64 lds[8][nv];
   fine += r * lay.size();
   coarse += r * Vc * NB;
   const int h = lay.ns / 2;
   const long pstride = lay.size();
-  cd64 acc[NB];
+  const int chi = threadIdx.x >> 8;  // wave-uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  cd64 acc[nv];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = mkc(0.0, 0.0);
-  for (int o = threadIdx.x; o < A; o += blockDim.x) {
+  for (int i = 0; i < nv; ++i) acc[i] = mkc(0.0, 0.0);
+  for (int o = threadIdx.x & 255; o < A; o += 256) {
     const long s = agg_sites[c * A + o];
+    cplx<R> pa[nv];
 #pragma unroll
-    for (int chi = 0; chi < 2; ++chi) {
-      cplx<R> pa[nv];
+    for (int i = 0; i < nv; ++i) pa[i] = mkc((R)0, (R)0);
+    for (int k = 0; k < h; ++k) {
+      const long e = lay.at(s, chi * h + k);
+      const cplx<R> v = fine[e];
 #pragma unroll
-      for (int i = 0; i < nv; ++i) pa[i] = mkc((R)0, (R)0);
-      for (int k = 0; k < h; ++k) {
-        const long e = lay.at(s, chi * h + k);
-        const cplx<R> v = fine[e];
-#pragma unroll
-        for (int i = 0; i < nv; ++i) cfmac(pa[i], P[i * pstride + e], v);
-      }
-#pragma unroll
-      for (int i = 0; i < nv; ++i) acc[chi * nv + i] = cadd(acc[chi * nv + i], ccast<double>(pa[i]));
+      for (int i = 0; i < nv; ++i) cfmac(pa[i], P[i * pstride + e], v);
     }
+#pragma unroll
+    for (int i = 0; i < nv; ++i) acc[i] = cadd(acc[i], ccast<double>(pa[i]));
   }
-  block_sum<NB>(acc, lds, res);
-  if (threadIdx.x < NB) coarse[c * NB + threadIdx.x] = ccast<R>(res[threadIdx.x]);
+#pragma unroll
+  for (int i = 0; i < nv; ++i) {
+    double re = acc[i].re, im = acc[i].im;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) lds[wave][i] = mkc(re, im);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const int q = threadIdx.x / nv, i = threadIdx.x - q * nv;
+    cd64 t = mkc(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) t = cadd(t, lds[4 * q + w][i]);
+    coarse[c * NB + threadIdx.x] = ccast<R>(t);
+  }
 }
 
 // fine(x)_k (+)= sum_{i} P_i(x)_k coarse(c(x), chi(k) * nv + i); thread per site,
@@ -572,7 +566,7 @@ bool supported_nb(int nb) {
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(kBlock), 0, st, fine, coarse, P,
+  NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st, fine, coarse, P,
                              lay, agg_sites, A, Vc, nrhs, run, rs));
   WCMG_CHECK_LAUNCH();
 }
