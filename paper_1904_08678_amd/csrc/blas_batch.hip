@@ -69,6 +69,87 @@ __global__ void __launch_bounds__(256) k_bdot_partial(const cplx<R>* __restrict_
   }
 }
 
+// Single-reduction Arnoldi step, first sweep, per right-hand side:
+// y_r = V_{r,j+1} - s_r V_{r,j} written back (s_r = shift[r * shs]; no shift
+// when shift is null), then partial[r][blk][k] = <V_{r,k}, y_r> for k <= j
+// and |y_r|^2 at k = j + 1.  Only the first tile of columns forms y.
+template <typename R>
+__global__ void __launch_bounds__(256) k_barnoldi_dots(cplx<R>* __restrict__ V, long vvs, long vrs, int j, long n,
+                                                        const cd64* __restrict__ shift, long shs,
+                                                        cd64* __restrict__ partial, int mstride,
+                                                        const int* __restrict__ run, int rs) {
+  const int r = blockIdx.y;
+  if (!live_r(run, rs, r)) return;
+  constexpr int KT = 8;
+  __shared__ cd64 lds[4][KT];
+  const int m = j + 2;
+  V += r * vrs;
+  partial += (long)r * gridDim.x * mstride;
+  const R sh = shift ? (R)shift[r * shs].re : (R)0;
+  cplx<R>* yv = V + (long)(j + 1) * vvs;
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < m; k0 += KT) {
+    cd64 s[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
+    for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      cplx<R> y = yv[i];
+      if (k0 == 0 && shift) {
+        y = csub(y, cscale(sh, V[(long)j * vvs + i]));
+        yv[i] = y;
+      }
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int k = k0 + q;
+        if (k < m) {
+          const cplx<R> x = k == j + 1 ? y : V[(long)k * vvs + i];
+          s[q].re += (double)x.re * y.re + (double)x.im * y.im;
+          s[q].im += (double)x.re * y.im - (double)x.im * y.re;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      s[q] = wsum2(s[q]);
+      if (lane == 0) lds[wave][q] = s[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < KT && k0 + (int)threadIdx.x < m) {
+      cd64 t = mkc(0.0, 0.0);
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w][threadIdx.x]);
+      partial[(long)blockIdx.x * mstride + k0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Single-reduction Arnoldi step, last sweep, per right-hand side:
+// y_r = (y_r - sum_{k<m} coef_r[k] V_{r,k}) / sqrt(nrm2_r) (0 when nrm2_r is 0).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bupdate_scale(cplx<R>* __restrict__ y, long yrs,
+                                                        const cplx<R>* __restrict__ V, long vvs, long vrs, int m,
+                                                        const cd64* __restrict__ coef, long crs,
+                                                        const cd64* __restrict__ nrm2, long nrs, long n,
+                                                        const int* __restrict__ run, int rs) {
+  const int r = blockIdx.y;
+  if (!live_r(run, rs, r)) return;
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y += r * yrs;
+  V += r * vrs;
+  coef += r * crs;
+  const double q = nrm2[r * nrs].re;
+  const R inv = q > 0.0 ? (R)(1.0 / sqrt(q)) : (R)0;
+  cplx<R> acc = y[i];
+  for (int k = 0; k < m; ++k) {
+    const cd64 c = coef[k];
+    cfma(acc, mkc((R)-c.re, (R)-c.im), V[(long)k * vvs + i]);
+  }
+  y[i] = cscale(inv, acc);
+}
+
 // Second half of a Gram-Schmidt pass in one sweep over the basis:
 //   y_r -= sum_{k<m} coef_r[k] V_{r,k}, then partial[r][blk][k] = <V_{r,k}, y_r> of
 // the updated y.  Each element's m basis entries stay in registers between the
@@ -287,6 +368,43 @@ __global__ void k_bgmres_cycle_start(int* st, cd64* S, long ss, int B, int m, do
   s[0] = 1;
 }
 
+// Single-reduction Arnoldi step, bookkeeping, one thread per right-hand side
+// (the batched form of k_gmres_sr): stage 0 takes the first sweep's sums d_r
+// (column j of H, the shift, hn^2 = |w'|^2 - |d|^2, st[5] = repeat the
+// projection); stage 1, where st[5], adds the second sweep's sums d2_r.
+__global__ void k_bgmres_sr(int* st, cd64* S, long ss, int B, int m, int j, cd64* d, cd64* d2, int stage) {
+  const int r = threadIdx.x;
+  if (r >= B) return;
+  int* s = st + 8 * r;
+  cd64* H = S + r * ss;
+  cd64* misc = H + (m + 1) * m + 2 * m + (m + 1) + m;
+  cd64* dr = d + r * ss;
+  const cd64* d2r = d2 + r * ss;
+  if (stage == 0) {
+    s[5] = 0;
+    if (!s[0]) return;
+    const double n0 = dr[j + 1].re;
+    double n1 = n0;
+    for (int i = 0; i <= j; ++i) {
+      H[i * m + j] = dr[i];
+      n1 -= dr[i].re * dr[i].re + dr[i].im * dr[i].im;
+    }
+    if (j == 0) misc[4] = mkc(dr[0].re, 0.0);
+    else H[j * m + j].re += misc[4].re;
+    misc[3] = mkc(n1 > 0.0 ? n1 : 0.0, 0.0);
+    s[5] = n1 < 0.25 * n0 ? 1 : 0;
+  } else {
+    if (!s[0] || !s[5]) return;
+    double n2 = d2r[j + 1].re;
+    for (int i = 0; i <= j; ++i) {
+      H[i * m + j] = cadd(H[i * m + j], d2r[i]);
+      n2 -= d2r[i].re * d2r[i].re + d2r[i].im * d2r[i].im;
+      dr[i] = d2r[i];
+    }
+    misc[3] = mkc(n2 > 0.0 ? n2 : 0.0, 0.0);
+  }
+}
+
 __global__ void k_bgmres_givens(int* st, cd64* S, long ss, int B, int m, int j, double tol, int limit, int fixed,
                                 int stop_on_est) {
   const int r = threadIdx.x;
@@ -395,6 +513,26 @@ void launch_bmulti_axpy_dot(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, lo
   WCMG_CHECK_LAUNCH();
 }
 
+template <typename R>
+void launch_barnoldi_dots(cplx<R>* V, long vvs, long vrs, int j, long n, const cd64* shift, long shs,
+                          cd64* partial, int B, const int* run, int rs, hipStream_t st) {
+  hipLaunchKernelGGL(k_barnoldi_dots<R>, dim3(red_b(n), B), dim3(kBlock), 0, st, V, vvs, vrs, j, n, shift, shs,
+                     partial, j + 2, run, rs);
+  WCMG_CHECK_LAUNCH();
+}
+template <typename R>
+void launch_bupdate_scale(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const cd64* coef,
+                          long crs, const cd64* nrm2, long nrs, long n, int B, const int* run, int rs,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_bupdate_scale<R>, dim3(nblocks(n), B), dim3(kBlock), 0, st, y, yrs, V, vvs, vrs, m, coef, crs,
+                     nrm2, nrs, n, run, rs);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_bgmres_sr(int* st_, cd64* S, long ss, int B, int m, int j, cd64* d, cd64* d2, int stage, hipStream_t st) {
+  hipLaunchKernelGGL(k_bgmres_sr, dim3(1), dim3(64), 0, st, st_, S, ss, B, m, j, d, d2, stage);
+  WCMG_CHECK_LAUNCH();
+}
+
 void launch_bdot_finish(const cd64* partial, int G, int m, int mstride, int B, cd64* out, int ostride, long ors,
                         int mode, const int* run, int rs, hipStream_t st) {
   hipLaunchKernelGGL(k_bdot_finish, dim3(m, B), dim3(kBlock), 0, st, partial, G, m, mstride, out, ostride, ors, mode,
@@ -458,7 +596,11 @@ void launch_bgmres_cycle_end(int* st_, int B, hipStream_t st) {
   template void launch_bmr_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, const cd64*, long, int, const int*,    \
                                      int, hipStream_t);                                                             \
   template void launch_bmulti_axpy_dot<R>(cplx<R>*, long, const cplx<R>*, long, long, int, const cd64*, int, long,      \
-                                          long, int, cd64*, const int*, int, hipStream_t);
+                                          long, int, cd64*, const int*, int, hipStream_t);                          \
+  template void launch_barnoldi_dots<R>(cplx<R>*, long, long, int, long, const cd64*, long, cd64*, int, const int*,    \
+                                        int, hipStream_t);                                                          \
+  template void launch_bupdate_scale<R>(cplx<R>*, long, const cplx<R>*, long, long, int, const cd64*, long,            \
+                                        const cd64*, long, long, int, const int*, int, hipStream_t);
 INST_B(double)
 INST_B(float)
 template void launch_belem<cd64, cd64>(cd64*, long, const cd64*, long, const cd64*, long, const cd64*, long, long, int,

@@ -293,7 +293,7 @@ struct Context {
   template <typename R>
   void gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, const cplx<R>* b, cplx<R>* x, bool x0_zero,
               int restart, int maxit, double tol, int fixed, bool stop_on_est, const int* parent, int prs,
-              int check_every, int* iters);
+              int check_every, int* iters, bool single_reduction = false);
   void drop_graph();
   void dslash32_batch(const cf32* in, cf32* out, int B, const int* run, int rs, cd64* dots);
   std::string dslash_key(int B) const;

@@ -18,7 +18,7 @@
 namespace wcmg {
 
 namespace {
-long scalars_per_rhs(int m) { return (long)(m + 1) * m + 2 * m + (m + 1) + m + 8 + (m + 1); }
+long scalars_per_rhs(int m) { return (long)(m + 1) * m + 2 * m + (m + 1) + m + 8 + 2 * (m + 1); }
 constexpr int kMaxBatch = 16;
 }  // namespace
 
@@ -225,7 +225,7 @@ void Context::mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const i
 template <typename R>
 void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, const cplx<R>* b, cplx<R>* x,
                      bool x0_zero, int restart, int maxit, double tol, int fixed, bool stop_on_est,
-                     const int* parent, int prs, int check_every, int* iters) {
+                     const int* parent, int prs, int check_every, int* iters, bool single_reduction) {
   const long nn = G.n;
   const int m = restart, B = G.B;
   const long ss = G.ss, bn = (long)B * nn;
@@ -238,6 +238,7 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
   cd64* y = g + (m + 1);
   cd64* misc = y + m;
   cd64* tmp = misc + 8;
+  cd64* tmp2 = tmp + (m + 1);
   int* st = G.st.as<int>();
   int* run = st;
   int* live = st + 1;
@@ -271,6 +272,30 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
       cplx<R>* vj = V + j * bn;
       cplx<R>* zj = M ? Z + j * bn : vj;
       if (M) (*M)(vj, zj, run, 8);
+      if (single_reduction) {
+        // the single-reduction step of Context::gmres, per right-hand side:
+        // w' = A z_j - s v_j formed in the slot of v_{j+1}, one sweep for its
+        // dots and norm, the projection repeated only where it removed more
+        // than 3/4 of |w'|^2 (st[5] of that right-hand side), one sweep to
+        // subtract and normalise
+        cplx<R>* wj = V + (j + 1) * bn;
+        A(zj, wj, run, 8);
+        launch_barnoldi_dots<R>(V, bn, nn, j, nn, j > 0 ? misc + 4 : nullptr, ss, part, B, run, 8, stream);
+        launch_bdot_finish(part, Gb, j + 2, j + 2, B, tmp, 1, ss, 0, run, 8, stream);
+        launch_bgmres_sr(st, S, ss, B, m, j, tmp, tmp2, 0, stream);
+        launch_bmulti_axpy<R>(wj, nn, V, bn, nn, j + 1, nullptr, 0, tmp, 1, ss, -1.0, nn, B, nullptr, st + 5, 8,
+                              stream);
+        launch_barnoldi_dots<R>(V, bn, nn, j, nn, nullptr, ss, part, B, st + 5, 8, stream);
+        launch_bdot_finish(part, Gb, j + 2, j + 2, B, tmp2, 1, ss, 0, st + 5, 8, stream);
+        launch_bgmres_sr(st, S, ss, B, m, j, tmp, tmp2, 1, stream);
+        launch_bgmres_givens(st, S, ss, B, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
+        if (j + 1 < m) launch_bupdate_scale<R>(wj, nn, V, bn, nn, j + 1, tmp, ss, misc + 3, ss, nn, B, run, 8, stream);
+        if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
+          read_state();
+          if (!any(0)) break;
+        }
+        continue;
+      }
       A(zj, w, run, 8);
       // classical Gram-Schmidt applied twice; |w|^2 from the last update
       launch_bdot<R>(V, bn, nn, j + 1, w, nn, nn, B, part, H + j, m, ss, 0, run, 8, stream);
@@ -437,7 +462,8 @@ void Context::solve_batched(const cd64* b, cd64* x, int B, int* iters) {
     if (nlev >= 2) precondition64B(0, i, o, B, rn, s);
     else launch_belem<cd64, cd64>(o, nn, i, nn, nullptr, 0, nullptr, 0, nn, B, 1, rn, s, stream);
   };
-  gmresB<double>(G, A, &M, b, x, false, m, p.outer_maxit, p.outer_tol, 0, false, nullptr, 0, 1, iters);
+  gmresB<double>(G, A, &M, b, x, false, m, p.outer_maxit, p.outer_tol, 0, false, nullptr, 0, 1, iters,
+                 !(p.reserved[0] & 8));
 }
 
 template void Context::apply_opB<double>(int, const cd64*, cd64*, int, const int*, int);

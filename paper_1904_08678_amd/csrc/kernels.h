@@ -186,6 +186,17 @@ void launch_cg_givens(int* stw, cd64* S, int m, int j, const cd64* part, int G, 
 
 // ---- batched vector kernels (blas_batch.hip)
 int bred_blocks(long n);
+// batched single-reduction Arnoldi step (blas_batch.hip; the forms of
+// launch_arnoldi_dots, launch_gmres_sr and launch_update_scale with a
+// right-hand-side index)
+template <typename R>
+void launch_barnoldi_dots(cplx<R>* V, long vvs, long vrs, int j, long n, const cd64* shift, long shs,
+                          cd64* partial, int B, const int* run, int rs, hipStream_t st);
+template <typename R>
+void launch_bupdate_scale(cplx<R>* y, long yrs, const cplx<R>* V, long vvs, long vrs, int m, const cd64* coef,
+                          long crs, const cd64* nrm2, long nrs, long n, int B, const int* run, int rs,
+                          hipStream_t st);
+void launch_bgmres_sr(int* st_, cd64* S, long ss, int B, int m, int j, cd64* d, cd64* d2, int stage, hipStream_t st);
 template <typename R>
 void launch_bdot(const cplx<R>* a, long avs, long ars, int m, const cplx<R>* b, long brs, long n, int B,
                  cd64* partial, cd64* out, int ostride, long ors, int mode, const int* run, int rs, hipStream_t st);
