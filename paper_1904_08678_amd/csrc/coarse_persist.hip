@@ -14,9 +14,11 @@
 // A w1 = A p_j - Z h1 (Z = A V at the own rows), where A p_j needs p_j at the
 // neighbouring sites, which that reduction's barrier has made visible.
 // Gram-Schmidt is repeated (a second reduction, of h2 = V^H w1 and |w1|^2)
-// only when |w1|^2 < |p_j|^2 / 2, i.e. when the first pass cancelled more
-// than half of p_j's norm (the criterion of Daniel, Gragg, Kaufman and
-// Stewart); A w2 = A w1 - Z h2.  The Hessenberg column of A is
+// only when |w1|^2 < |p_j|^2 / 4, i.e. when the first pass removed more than
+// three quarters of |p_j|^2 (the criterion of Daniel, Gragg, Kaufman and
+// Stewart, with 1/4 in place of their 1/2: on these operators the first pass
+// removes about 65%, the previous basis vector's share, which is mild
+// cancellation); A w2 = A w1 - Z h2.  The Hessenberg column of A is
 // h1 + s e_j (+ h2), and v_{j+1} = w / |w|, z_{j+1} = A w / |w|.
 // Every workgroup sums the per-workgroup partials itself in a fixed order,
 // so every workgroup holds bit-identical reductions, Givens rotations,
@@ -33,11 +35,13 @@
 // stencil reads) is read with plain loads: the invalidate has dropped stale
 // lines from this XCD's L2, and the first workgroup of an XCD to read a line
 // brings it in for the others (agent-scope loads would bypass L2 and send
-// every workgroup's reads of the same partials to memory).  A
-// waiting thread gives up after a wall-clock timeout: the error word is set,
-// every workgroup leaves, and the host redoes the solve with the
-// multi-kernel form, so a fault in the launch configuration cannot hang the
-// device.
+// every workgroup's reads of the same partials to memory).  The phase
+// numbers continue from launch to launch, so the flags need no clearing, and
+// workgroup 0 reports a normal end in a host-mapped mailbox.  A waiting
+// thread gives up after a wall-clock timeout: the error word is set, every
+// workgroup leaves without reporting, and the host clears the flags and
+// redoes the solve with the multi-kernel form, so a fault in the launch
+// configuration cannot hang the device.
 #include "coarse_common.h"
 
 namespace wcmg {
