@@ -426,6 +426,39 @@ def test_cooperative_coarse_gmres_matches_multi_kernel_path(L, block, store, nv)
     assert abs(infos[0]["coarse_iters"] - infos[1]["coarse_iters"]) <= max(2, infos[1]["coarse_iters"] // 50)
 
 
+@pytest.mark.parametrize("restart,tol,fixed", [(4, 1e-4, 0), (40, 0.05, 0), (6, 0.05, 15)])
+def test_cooperative_coarse_gmres_restart_cycles(restart, tol, fixed):
+    """Restart cycles inside the cooperative launch (x complete, residual
+    recomputed from A x, new shift, y solved per cycle): restart 4 to 1e-4
+    (several cycles per coarse solve), restart 40 (every LDS array at its
+    largest), and 15 fixed iterations over restarts of 6; the cycle output
+    against the four-kernel form to FP32 rounding and bit-identical on repeat,
+    solves with the same outer iteration counts (within one)."""
+    w = wc()
+    L, block, nv = (16, 16, 16, 16), (4, 4, 4, 4), 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 1961)
+    start = syn.complex_gaussian((nv, V, 12), 1962)
+    r = syn.complex_gaussian((V, 4, 3), 1963)
+    outs, its = [], []
+    for flags in (0, 4):
+        kw = dict(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), cycle_prec=w.F32,
+                  coarse_store_prec=w.F32, setup_prec=w.F32, reserved=(flags,), coarse_restart=restart,
+                  coarse_tol=tol, coarse_maxit=200, coarse_fixed_iters=fixed)
+        ctx = w.Context(**kw)
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        outs.append(host(ctx.cycle(dev(r.astype(np.complex128)))))
+        assert np.array_equal(host(ctx.cycle(dev(r.astype(np.complex128)))), outs[-1])
+        x, info, st = ctx.solve(dev(r))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        assert ctx.timers()["coarse_solve_fallbacks"] == 0, w.lib().wcmg_last_error(ctx.h)
+        its.append(info[0])
+    assert rel(outs[0], outs[1]) < 5e-5
+    assert abs(its[0]["outer_iters"] - its[1]["outer_iters"]) <= 1
+
+
 def test_cooperative_coarse_gmres_timeout_falls_back():
     """Barrier waits that give up at once (reserved[0] flag 16; every kernel
     still exits normally): each cooperative coarsest solve reports no
@@ -457,14 +490,16 @@ def test_cooperative_coarse_gmres_timeout_falls_back():
     assert abs(i0["outer_iters"] - i4["outer_iters"]) <= 1
 
 
-@pytest.mark.parametrize("levels,mixed,eo", [(2, True, 0), (2, False, 0), (1, False, 0), (2, True, 1)])
-def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo):
+@pytest.mark.parametrize("levels,mixed,eo,restart", [(2, True, 0, 20), (2, False, 0, 20), (1, False, 0, 20),
+                                                     (2, True, 1, 20), (2, True, 0, 5), (1, False, 0, 7)])
+def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo, restart):
     """The outer FGMRES with one reduction per Arnoldi step (shifted vector,
     norm from |w'|^2 - |h|^2, second projection only on heavy cancellation,
     which the unshifted first step of every cycle takes) against classical
     Gram-Schmidt applied twice (reserved[0] flag 8): same outer iteration
     counts, solutions equal to 1e-12, both to the 1e-10 target.  Two-level
-    mixed and FP64, one level (unpreconditioned GMRES), even-odd."""
+    mixed and FP64, one level (unpreconditioned GMRES), even-odd, and short
+    restarts (several restart cycles, each with its own shift)."""
     w = wc()
     L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
     V = int(np.prod(L))
@@ -474,7 +509,7 @@ def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo):
     xs, infos = [], []
     for flags in (0, 8):
         kw = dict(dims=L, m0=-0.05 if levels > 1 else 0.3, n_levels=levels, block=(block,), n_vec=(nv,),
-                  even_odd=eo, reserved=(flags,), outer_maxit=4000)
+                  even_odd=eo, reserved=(flags,), outer_maxit=4000, outer_restart=restart)
         if mixed:
             kw.update(cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32)
         ctx = w.Context(**kw)
