@@ -516,11 +516,8 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
         launch_eo_local<double>(b64, r64, bh, nullptr, par, 1, 4, V, c.stream);
         launch_eo_gather<double>(bh, bc, odd, V, Vh, c.stream);
         launch_eo_gather<double>(x64, xc, odd, V, Vh, c.stream);
-        std::function<void(const cd64*, cd64*, const int*)> Ah = [&c, fi, fo, odd, pos, par, V, Vh](
-                                                                      const cd64* i, cd64* o, const int* rn) {
-          launch_eo_scatter<double>(i, fi, pos, par, V, Vh, c.stream);
-          c.schur64(fi, fo, rn);
-          launch_eo_gather<double>(fo, o, odd, V, Vh, c.stream);
+        std::function<void(const cd64*, cd64*, const int*)> Ah = [&c](const cd64* i, cd64* o, const int* rn) {
+          c.schur64c(i, o, rn);
         };
         std::function<void(const cd64*, cd64*, const int*)> Mh = [&c, &M, fi, fo, odd, pos, par, V, Vh](
                                                                       const cd64* i, cd64* o, const int* rn) {

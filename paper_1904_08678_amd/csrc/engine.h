@@ -185,7 +185,7 @@ struct Context {
   bool gauge_set = false, setup_done = false;
   // even-odd preconditioning: site parity (device order) and A^{-1} (packed)
   DevBuf par0, clovinv64, clovinv32;
-  DevBuf eo_odd, eo_pos;  // odd sites in device order and their compact positions
+  DevBuf eo_odd, eo_even, eo_pos;  // odd and even sites in device order; each site's compact position
   long eo_half = 0;       // number of odd sites
   bool eo_ready = false;
   // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
@@ -261,6 +261,7 @@ struct Context {
   // x's even part must be zero, y's even part is set to zero)
   void eo_prepare();
   void schur64(const cd64* x, cd64* y, const int* run);
+  void schur64c(const cd64* xo, cd64* yo, const int* run);
   template <typename R>
   void sap(const cplx<R>* b, cplx<R>* x, int cycles, int nrhs, const int* run, int rs);
   template <typename R>

@@ -751,14 +751,15 @@ void Context::eo_prepare() {
   }
   par0.alloc(G.V);
   WCMG_HIP(hipMemcpy(par0.p, par.data(), G.V, hipMemcpyHostToDevice));
-  std::vector<int> odd, pos(G.V, 0);
-  for (long s = 0; s < G.V; ++s)
-    if (par[s]) {
-      pos[s] = (int)odd.size();
-      odd.push_back((int)s);
-    }
+  std::vector<int> odd, even, pos(G.V, 0);
+  for (long s = 0; s < G.V; ++s) {
+    std::vector<int>& list = par[s] ? odd : even;
+    pos[s] = (int)list.size();
+    list.push_back((int)s);
+  }
   require(2 * (long)odd.size() == G.V, WCMG_ERR_DIMS, "even-odd preconditioning needs as many odd as even sites");
   upload(eo_odd, odd);
+  upload(eo_even, even);
   upload(eo_pos, pos);
   eo_half = (long)odd.size();
   clovinv64.alloc(clov64.bytes);
@@ -772,17 +773,28 @@ void Context::eo_prepare() {
   eo_ready = true;
 }
 
-// y = A_oo x_o - H_oe A_ee^{-1} H_eo x_o: the hopping-only Dslash twice, with
-// A^{-1} on the even sites between them and A on the odd sites at the end.
+// y_o = A_oo x_o - H_oe A_ee^{-1} H_eo x_o on parity-compact fields: two
+// launches, each the hops into one parity's sites with the site-local block
+// in its epilogue (A^{-1} on the even sites, then A on the odd ones).
+void Context::schur64c(const cd64* xo, cd64* yo, const int* run) {
+  const long V = geo[0].V, Vh = eo_half;
+  cd64* ue = buf<cd64>("eo_ue", 12 * Vh);
+  const int* nbr = geo[0].nbr.as<int>();
+  launch_schur_hop<double>(xo, ue, nullptr, U64.as<cd64>(), clovinv64.as<double>(), nbr, eo_even.as<int>(),
+                           eo_pos.as<int>(), V, Vh, 0, run, stream);
+  launch_schur_hop<double>(ue, yo, xo, U64.as<cd64>(), clov64.as<double>(), nbr, eo_odd.as<int>(), eo_pos.as<int>(),
+                           V, Vh, 1, run, stream);
+}
+
+// The same on full-length fields (the even part of x is ignored, that of y
+// is zero): gather the odd sites, apply, scatter.
 void Context::schur64(const cd64* x, cd64* y, const int* run) {
-  const long V = geo[0].V, nn = n(0);
-  cd64* t = buf<cd64>("eo_t", nn);
-  cd64* u = buf<cd64>("eo_u", nn);
-  const unsigned char* par = (const unsigned char*)par0.p;
-  apply_op<double>(0, x, t, 1, run, 0x1fe);
-  launch_eo_local<double>(t, nullptr, u, clovinv64.as<double>(), par, 0, 0, V, stream);
-  apply_op<double>(0, u, t, 1, run, 0x1fe);
-  launch_eo_local<double>(x, t, y, clov64.as<double>(), par, 1, 1, V, stream);
+  const long V = geo[0].V, Vh = eo_half;
+  cd64* xo = buf<cd64>("eo_xo", 12 * Vh);
+  cd64* yo = buf<cd64>("eo_yo", 12 * Vh);
+  launch_eo_gather<double>(x, xo, eo_odd.as<int>(), V, Vh, stream);
+  schur64c(xo, yo, run);
+  launch_eo_scatter<double>(yo, y, eo_pos.as<int>(), (const unsigned char*)par0.p, V, Vh, stream);
 }
 
 // SAP domains: the level-0 aggregates, coloured by the parity of their coarse

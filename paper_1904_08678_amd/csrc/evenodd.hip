@@ -200,6 +200,117 @@ __global__ void __launch_bounds__(256) k_eo_local(const cplx<R>* in, const cplx<
   }
 }
 
+namespace {
+// One hop of the compact operator: the neighbour's spinor from the compact
+// field of the other parity (pos: full site index -> compact index), the link
+// from the full-lattice field.
+template <typename R, int MU, bool FWD>
+__device__ inline void hop_compact(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                                   const int* __restrict__ nbr, const int* __restrict__ pos, long V, long Vh, long s) {
+  const long y = nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s];
+  const long yc = pos[y];
+  cplx<R> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = in[(long)k * Vh + yc];
+  const long ls = FWD ? s : y;
+  cplx<R> u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[(long)(MU * 9 + e) * V + ls];
+  hop_core<R, MU, FWD>(acc, p, u);
+}
+
+// o = B p for one chirality's Hermitian 6 x 6 block, packed as 6 diagonal
+// reals and the 15 entries below the diagonal (B_ji = conj(B_ij)).
+template <typename R>
+__device__ inline void block6(const R (&e)[36], const cplx<R> (&p)[6], cplx<R> (&o)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) o[i] = cscale(e[i], p[i]);
+  int idx = 0;
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j, ++idx) {
+      const cplx<R> a = mkc(e[6 + 2 * idx], e[7 + 2 * idx]);
+      cfma(o[i], a, p[j]);
+      cfmac(o[j], a, p[i]);
+    }
+}
+}  // namespace
+
+// The two halves of the Schur complement on parity-compact fields (each
+// compact field holds one parity: component k of compact site j at k Vh + j).
+// For the target sites tgt[j] (full index, compact index j): h = the eight
+// hops from the other parity's values in `in`, then
+//   mode 0: out_j = B h               (B = A^{-1}: u_e = A_ee^{-1} H_eo x_o)
+//   mode 1: out_j = B aux_j - h       (B = A: y_o = A_oo x_o - H_oe u_e)
+// B: the packed per-site blocks [2][36 / RC][V][RC] at the full index.
+// A workgroup of 4 waves owns 64 target sites; wave mu takes the two hops
+// along mu, the partial spinors meet in LDS in a fixed order, and waves 0 and
+// 1 apply chirality 0 and 1 of the site-local block.
+template <typename R>
+__global__ void __launch_bounds__(256) k_schur_hop(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                    const cplx<R>* __restrict__ aux, const cplx<R>* __restrict__ U,
+                                                    const R* __restrict__ B, const int* __restrict__ nbr,
+                                                    const int* __restrict__ tgt, const int* __restrict__ pos, long V,
+                                                    long Vh, int mode, const int* __restrict__ run) {
+  if (run && !*run) return;
+  long blk, r;
+  if (!item_rhs((Vh + 63) / 64, 1, &blk, &r)) return;
+  __shared__ cplx<R> part[4][12][64];
+  const int lane = threadIdx.x & 63;
+  const int mu = threadIdx.x >> 6;  // wave-uniform
+  const long j = blk * 64 + lane;
+  const bool valid = j < Vh;
+  const long s = valid ? tgt[j] : 0;
+  cplx<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mkc((R)0, (R)0);
+  if (valid) {
+    if (mu == 0) {
+      hop_compact<R, 0, true>(acc, in, U, nbr, pos, V, Vh, s);
+      hop_compact<R, 0, false>(acc, in, U, nbr, pos, V, Vh, s);
+    } else if (mu == 1) {
+      hop_compact<R, 1, true>(acc, in, U, nbr, pos, V, Vh, s);
+      hop_compact<R, 1, false>(acc, in, U, nbr, pos, V, Vh, s);
+    } else if (mu == 2) {
+      hop_compact<R, 2, true>(acc, in, U, nbr, pos, V, Vh, s);
+      hop_compact<R, 2, false>(acc, in, U, nbr, pos, V, Vh, s);
+    } else {
+      hop_compact<R, 3, true>(acc, in, U, nbr, pos, V, Vh, s);
+      hop_compact<R, 3, false>(acc, in, U, nbr, pos, V, Vh, s);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
+  __syncthreads();
+  if (mu >= 2 || !valid) return;
+  const int chi = mu;
+  cplx<R> h[6], pin[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int k = chi * 6 + i;
+    h[i] = cadd(cadd(cadd(part[0][k][lane], part[1][k][lane]), part[2][k][lane]), part[3][k][lane]);
+    pin[i] = mode == 0 ? h[i] : aux[(long)k * Vh + j];
+  }
+  R e[36];
+  load_block<R>(B, chi, V, s, e);
+  cplx<R> o[6];
+  block6<R>(e, pin, o);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[(long)(chi * 6 + i) * Vh + j] = mode == 1 ? csub(o[i], h[i]) : o[i];
+}
+
+template <typename R>
+void launch_schur_hop(const cplx<R>* in, cplx<R>* out, const cplx<R>* aux, const cplx<R>* U, const R* B,
+                      const int* nbr, const int* tgt, const int* pos, long V, long Vh, int mode, const int* run,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_schur_hop<R>, dim3(item_rhs_grid(nblocks(Vh, 64), 1)), dim3(kBlock), 0, st, in, out, aux, U,
+                     B, nbr, tgt, pos, V, Vh, mode, run);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_schur_hop<double>(const cd64*, cd64*, const cd64*, const cd64*, const double*, const int*,
+                                       const int*, const int*, long, long, int, const int*, hipStream_t);
+
 // Odd-site compaction: compact[k][j] = full[k][odd[j]] (gather), and
 // full[k][s] = compact[k][pos[s]] on odd sites, 0 on even ones (scatter).
 template <typename R>

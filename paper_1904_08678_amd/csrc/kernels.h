@@ -32,6 +32,12 @@ void launch_wilson_mrhs(const cf32* in, cf32* out, const cf32* U, const float* c
 // ---- even-odd preconditioning (evenodd.hip): A^{-1} per site (packed like A,
 // FP64 and FP32 copies; bad set on a vanishing pivot) and parity-masked
 // site-local operations (modes in evenodd.hip)
+// the halves of the Schur complement on parity-compact fields (evenodd.hip):
+// mode 0 out = B h, mode 1 out = B aux - h, h the hops from the other parity
+template <typename R>
+void launch_schur_hop(const cplx<R>* in, cplx<R>* out, const cplx<R>* aux, const cplx<R>* U, const R* B,
+                      const int* nbr, const int* tgt, const int* pos, long V, long Vh, int mode, const int* run,
+                      hipStream_t st);
 void launch_clover_invert(const double* A, long V, double* inv64, float* inv32, int* bad, hipStream_t st);
 template <typename R>
 void launch_eo_local(const cplx<R>* in, const cplx<R>* aux, cplx<R>* out, const R* B, const unsigned char* par,
