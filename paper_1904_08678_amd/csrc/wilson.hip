@@ -239,11 +239,15 @@ __global__ void k_unpack_fermion(const cplx<Ti>* __restrict__ in, const int* __r
 // hops along direction mu for all 64 sites (waves 0 and 1 also the clover
 // block of chirality 0 and 1), so every branch is wave-uniform and four times
 // as many loads are in flight as with one lane per site.  The four partial
-// spinors are combined in LDS in a fixed order.
+// spinors are combined in LDS in a fixed order.  ALL: every term (the whole
+// operator, the common case) with no per-term branches, so the compiler can
+// issue both hops' loads together.
 // dots != nullptr: per-workgroup partials of <out, in> and <out, out> (the
 // inner products of an MR step, where in = r and out = D r) go to
-// dots[2*blk], dots[2*blk+1].
-template <typename R>
+// dots[2*blk], dots[2*blk+1].  Waves 0 and 1 then write the output of their
+// chirality and form the products with the input components they loaded for
+// the clover block.
+template <typename R, bool ALL>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                                  const int* __restrict__ nbr, long V, int terms, int nrhs,
@@ -253,7 +257,7 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
   if (!item_rhs(nblk, nrhs, &blk, &r)) return;
   if (run && !run[r * rs]) return;
   __shared__ cplx<R> part[4][12][64];
-  __shared__ cd64 red[8];
+  __shared__ cd64 red[4];
   const int lane = threadIdx.x & 63;
   const int mu = threadIdx.x >> 6;  // wave-uniform
   const long s = blk * 64 + lane;
@@ -263,46 +267,84 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
   cplx<R> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mkc((R)0, (R)0);
+  // waves 0 and 1: the input at the own site, chirality mu
+  cplx<R> pin[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pin[k] = mkc((R)0, (R)0);
   if (valid) {
-    if ((terms & 1) && mu == 0) clover_chirality<R, 0>(acc, in, clov, V, s);
-    if ((terms & 1) && mu == 1) clover_chirality<R, 1>(acc, in, clov, V, s);
-    if (mu == 0) {
-      if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
-      if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
-    } else if (mu == 1) {
-      if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
-      if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
-    } else if (mu == 2) {
-      if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
-      if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
+    if (mu < 2 && (ALL || (terms & 1) || dots)) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pin[k] = in[(long)(mu * 6 + k) * V + s];
+    }
+    if (ALL) {
+      if (mu == 0) {
+        clover_chirality_p<R, 0>(acc, pin, clov, V, s);
+        hop<R, 0, true>(acc, in, U, nbr, V, s);
+        hop<R, 0, false>(acc, in, U, nbr, V, s);
+      } else if (mu == 1) {
+        clover_chirality_p<R, 1>(acc, pin, clov, V, s);
+        hop<R, 1, true>(acc, in, U, nbr, V, s);
+        hop<R, 1, false>(acc, in, U, nbr, V, s);
+      } else if (mu == 2) {
+        hop<R, 2, true>(acc, in, U, nbr, V, s);
+        hop<R, 2, false>(acc, in, U, nbr, V, s);
+      } else {
+        hop<R, 3, true>(acc, in, U, nbr, V, s);
+        hop<R, 3, false>(acc, in, U, nbr, V, s);
+      }
     } else {
-      if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
-      if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
+      if ((terms & 1) && mu == 0) clover_chirality_p<R, 0>(acc, pin, clov, V, s);
+      if ((terms & 1) && mu == 1) clover_chirality_p<R, 1>(acc, pin, clov, V, s);
+      if (mu == 0) {
+        if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
+        if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
+      } else if (mu == 1) {
+        if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
+        if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
+      } else if (mu == 2) {
+        if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
+        if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
+      } else {
+        if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
+        if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
   __syncthreads();
-  // wave mu writes components 3 mu .. 3 mu + 2 (spin mu), summed over the 4 waves in order
-  double pr = 0.0, pi = 0.0, pp = 0.0;
+  if (!dots) {
+    // wave mu writes components 3 mu .. 3 mu + 2 (spin mu), summed over the 4 waves in order
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int k = 3 * mu + c;
-    cplx<R> v = part[0][k][lane];
-    v = cadd(v, part[1][k][lane]);
-    v = cadd(v, part[2][k][lane]);
-    v = cadd(v, part[3][k][lane]);
-    if (valid) {
-      out[(long)k * V + s] = v;
-      if (dots) {
-        const cplx<R> x = in[(long)k * V + s];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * mu + c;
+      cplx<R> v = part[0][k][lane];
+      v = cadd(v, part[1][k][lane]);
+      v = cadd(v, part[2][k][lane]);
+      v = cadd(v, part[3][k][lane]);
+      if (valid) out[(long)k * V + s] = v;
+    }
+    return;
+  }
+  // waves 0 and 1 write the six components of chirality mu and form the
+  // products with the input they hold
+  if (mu < 2) {
+    double pr = 0.0, pi = 0.0, pp = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int k = 6 * mu + c;
+      cplx<R> v = part[0][k][lane];
+      v = cadd(v, part[1][k][lane]);
+      v = cadd(v, part[2][k][lane]);
+      v = cadd(v, part[3][k][lane]);
+      if (valid) {
+        out[(long)k * V + s] = v;
+        const cplx<R> x = pin[c];
         pr += (double)v.re * x.re + (double)v.im * x.im;
         pi += (double)v.re * x.im - (double)v.im * x.re;
         pp += (double)v.re * v.re + (double)v.im * v.im;
       }
     }
-  }
-  if (dots) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       pr += __shfl_xor(pr, off, 64);
@@ -313,17 +355,12 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
       red[2 * mu] = mkc(pr, pi);
       red[2 * mu + 1] = mkc(pp, 0.0);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      cd64 a = mkc(0.0, 0.0), b = mkc(0.0, 0.0);
-      for (int w = 0; w < 4; ++w) {
-        a = cadd(a, red[2 * w]);
-        b = cadd(b, red[2 * w + 1]);
-      }
-      const long bi = r * nblk + blk;
-      dots[2 * bi] = a;
-      dots[2 * bi + 1] = b;
-    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long bi = r * nblk + blk;
+    dots[2 * bi] = cadd(red[0], red[2]);
+    dots[2 * bi + 1] = cadd(red[1], red[3]);
   }
 }
 
@@ -521,8 +558,12 @@ INST_PACK(float, double)
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs) {
-  WCMG_LAUNCH(k_wilson<R>, dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov, nbr, V,
-              terms, nrhs, dots, run, rs);
+  if (terms == 0x1ff)
+    WCMG_LAUNCH((k_wilson<R, true>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
+                nbr, V, terms, nrhs, dots, run, rs);
+  else
+    WCMG_LAUNCH((k_wilson<R, false>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
+                nbr, V, terms, nrhs, dots, run, rs);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,

@@ -114,6 +114,31 @@ __device__ inline void clover_block_apply(cplx<R> (&acc)[12], const R (&e)[36], 
     }
 }
 
+// Clover block of chirality chi applied to p (the six components of that
+// chirality at site s, already loaded).
+template <typename R, int chi>
+__device__ inline void clover_chirality_p(cplx<R> (&acc)[12], const cplx<R> (&p)[6], const R* __restrict__ clov,
+                                          long V, long s) {
+  constexpr int RC = 16 / sizeof(R);
+  typedef typename std::conditional<sizeof(R) == 4, float4, double2>::type V16;
+  R e[36];
+  const V16* cb = (const V16*)(clov + (long)chi * 36 * V);
+#pragma unroll
+  for (int q = 0; q < 36 / RC; ++q) {
+    V16 c = cb[(long)q * V + s];
+    if constexpr (RC == 4) {
+      e[q * 4 + 0] = c.x;
+      e[q * 4 + 1] = c.y;
+      e[q * 4 + 2] = c.z;
+      e[q * 4 + 3] = c.w;
+    } else {
+      e[q * 2 + 0] = c.x;
+      e[q * 2 + 1] = c.y;
+    }
+  }
+  clover_block_apply<R, chi>(acc, e, p);
+}
+
 template <typename R, int chi>
 __device__ inline void clover_chirality(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in,
                                         const R* __restrict__ clov, long V, long s) {
