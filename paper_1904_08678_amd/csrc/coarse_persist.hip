@@ -255,11 +255,17 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     }
   }
   cplx<R>* ustf = &ust[0][0][0];
-  auto apply_row = [&](const cplx<R>* u) -> cplx<R> {
+  // the stencil's source values are loaded into registers first, so their
+  // loads can be in flight together with others (the reduction's partials)
+  auto stage_load = [&](const cplx<R>* u, cplx<R>(&sv)[kStage]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int kk = 0; kk < kStage; ++kk) sv[kk] = srcrow[kk] >= 0 ? u[srcrow[kk]] : mkc((R)0, (R)0);
+  };
+  auto apply_staged = [&](const cplx<R>(&sv)[kStage]) __attribute__((always_inline)) -> cplx<R> {
     __syncthreads();  // the previous apply's readers are done with ust
 #pragma unroll
     for (int kk = 0; kk < kStage; ++kk)
-      if (srcrow[kk] >= 0) ustf[tid + 256 * kk] = u[srcrow[kk]];
+      if (srcrow[kk] >= 0) ustf[tid + 256 * kk] = sv[kk];
     __syncthreads();
     cplx<R> acc = mkc((R)0, (R)0), acc2 = mkc((R)0, (R)0);
     if (lr < nrow) {
@@ -288,6 +294,11 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     }
     return acc;
   };
+  auto apply_row = [&](const cplx<R>* u) __attribute__((always_inline)) -> cplx<R> {
+    cplx<R> sv[kStage];
+    stage_load(u, sv);
+    return apply_staged(sv);
+  };
 
   // Grid-wide sums of cnt entries: this workgroup's partials go to
   // part[pb][block][i]; after the barrier every workgroup adds the G
@@ -299,7 +310,10 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   unsigned phase = phase0;
   int pb = 0;
   const int ent = wred8_entry(lane);
-  auto reduce = [&](int cnt, auto contrib) -> bool {
+  // reduce_begin: this workgroup's partials, then the grid barrier;
+  // reduce_end: the sums into hs.  Loads issued between the two overlap the
+  // partials' loads.
+  auto reduce_begin = [&](int cnt, auto contrib) -> bool {
     for (int i0 = 0; i0 < cnt; i0 += 8) {
       cd64 a[8];
 #pragma unroll
@@ -314,7 +328,9 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     if (tid < cnt)
       part[((size_t)pb * G + blockIdx.x) * kPStride + tid] =
           cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
-    if (!pbarrier(bar, G, ++phase, &fail, tick_limit)) return false;
+    return pbarrier(bar, G, ++phase, &fail, tick_limit);
+  };
+  auto reduce_end = [&](int cnt) {
     for (int i0 = 0; i0 < cnt; i0 += 8) {
       cd64 a[8];
 #pragma unroll
@@ -335,6 +351,10 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     if (tid < cnt) hs[tid] = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
     __syncthreads();
     pb ^= 1;
+  };
+  auto reduce = [&](int cnt, auto contrib) -> bool {
+    if (!reduce_begin(cnt, contrib)) return false;
+    reduce_end(cnt);
     return true;
   };
 
@@ -395,11 +415,14 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
       // two global buffers, so a workgroup writing z_{j+1} cannot overwrite
       // rows a slower one still reads)
       const cplx<R> zj = pj;
-      if (!reduce(j + 2, [&](int i) {
+      if (!reduce_begin(j + 2, [&](int i) {
             return i <= j ? cdotd(vl[i][lrc], zj) : mkc((double)zj.re * zj.re + (double)zj.im * zj.im, 0.0);
           }))
         return;
-      cplx<R> aw = apply_row(zg + (long)(j & 1) * n);
+      cplx<R> sv[kStage];
+      stage_load(zg + (long)(j & 1) * n, sv);
+      reduce_end(j + 2);
+      cplx<R> aw = apply_staged(sv);
       cplx<R> wv = zj;
       if (own)
         for (int i = 0; i <= j; ++i) {
