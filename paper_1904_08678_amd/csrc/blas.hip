@@ -289,6 +289,66 @@ __global__ void k_mr_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, co
   r[i] = ri;
 }
 
+// The MR update with the step length formed from the operator's
+// per-workgroup partials (part[2g] = <p, r>_g, part[2g+1] = <p, p>_g, g < G)
+// by every workgroup itself, in the order of k_dot_finish (per-thread strided
+// sums, wave sums, waves in order), so all workgroups hold the same alpha and
+// it equals the one a separate k_dot_finish launch would give.  A fixed grid
+// of kMrGrid workgroups keeps the partials' reads down; each thread updates
+// four elements per pass.
+constexpr int kMrGrid = 512;
+template <typename R>
+__global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
+                                                         const cplx<R>* __restrict__ p, const cd64* __restrict__ part,
+                                                         int G, long n, const int* __restrict__ run) {
+  if (run && !*run) return;
+  __shared__ cd64 lds[2][4];
+  cd64 s0 = mkc(0.0, 0.0), s1 = mkc(0.0, 0.0);
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    s0 = cadd(s0, part[2L * g]);
+    s1 = cadd(s1, part[2L * g + 1]);
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    lds[0][wave] = s0;
+    lds[1][wave] = s1;
+  }
+  __syncthreads();
+  cd64 t0 = mkc(0.0, 0.0), t1 = mkc(0.0, 0.0);
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    t0 = cadd(t0, lds[0][w]);
+    t1 = cadd(t1, lds[1][w]);
+  }
+  const double pp = t1.re;
+  const cd64 al = pp > 0.0 ? mkc(t0.re / pp, t0.im / pp) : mkc(0.0, 0.0);
+  const cplx<R> a = mkc((R)al.re, (R)al.im), na = cneg(a);
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    cplx<R> xi[4], ri[4], pi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long i = i0 + u * stride;
+      if (i < n) {
+        xi[u] = x[i];
+        ri[u] = r[i];
+        pi[u] = p[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long i = i0 + u * stride;
+      if (i < n) {
+        cfma(xi[u], a, ri[u]);
+        cfma(ri[u], na, pi[u]);
+        x[i] = xi[u];
+        r[i] = ri[u];
+      }
+    }
+  }
+}
+
 // partial[blk][0] = <p, r>, partial[blk][1] = <p, p>
 template <typename R>
 __global__ void __launch_bounds__(256) k_dot2_partial(const cplx<R>* __restrict__ p, const cplx<R>* __restrict__ r,
@@ -550,6 +610,14 @@ void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots
 }
 
 template <typename R>
+void launch_mr_update_part(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* part, int G, long n, const int* run,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_mr_update_part<R>, dim3((unsigned)std::min<long>(kMrGrid, nblocks(n))), dim3(kBlock), 0, st, x,
+                     r, p, part, G, n, run);
+  WCMG_CHECK_LAUNCH();
+}
+
+template <typename R>
 void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
                            const int* run, hipStream_t st) {
   int G = red_blocks(n);
@@ -571,6 +639,8 @@ void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd6
   template void launch_sub<R>(cplx<R>*, const cplx<R>*, const cplx<R>*, long, const int*, hipStream_t);              \
   template void launch_scale_inv_norm<R>(cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t);      \
   template void launch_mr_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t); \
+  template void launch_mr_update_part<R>(cplx<R>*, cplx<R>*, const cplx<R>*, const cd64*, int, long, const int*,      \
+                                         hipStream_t);                                                              \
   template void launch_mr_dots_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, cd64*, cd64*, const int*,         \
                                          hipStream_t);
 INST_BLAS(double)

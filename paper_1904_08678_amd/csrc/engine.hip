@@ -452,8 +452,7 @@ void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, c
     cd64* part = buf<cd64>("mr_part" + t, 2L * G);
     for (int k = 0; k < steps; ++k) {
       apply_op<R>(l, r, pp, 1, run, 0x1ff, part);
-      launch_dot_finish(part, G, 2, 2, dots, 1, 0, run, stream);
-      launch_mr_update<R>(x, r, pp, dots, nn, run, stream);
+      launch_mr_update_part<R>(x, r, pp, part, G, nn, run, stream);
     }
     return;
   }

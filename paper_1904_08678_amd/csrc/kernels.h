@@ -133,6 +133,12 @@ void launch_convert(const cplx<Ti>* x, cplx<To>* y, long n, const int* run, hipS
 template <typename R>
 void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots, long n, const int* run,
                       hipStream_t st);
+// MR update whose step length <p, r> / <p, p> is summed from G per-workgroup
+// partial pairs part[2g], part[2g+1] inside the update kernel (same order and
+// result as launch_dot_finish).
+template <typename R>
+void launch_mr_update_part(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* part, int G, long n, const int* run,
+                           hipStream_t st);
 template <typename R>
 void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
                            const int* run, hipStream_t st);
