@@ -293,14 +293,16 @@ __global__ void k_mr_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, co
 // per-workgroup partials (part[2g] = <p, r>_g, part[2g+1] = <p, p>_g, g < G)
 // by every workgroup itself, in the order of k_dot_finish (per-thread strided
 // sums, wave sums, waves in order), so all workgroups hold the same alpha and
-// it equals the one a separate k_dot_finish launch would give.  A fixed grid
+// it equals the one a separate k_dot_finish launch would give.  xout !=
+// nullptr: the updated x is written there in FP64 (x itself is left as is).  A fixed grid
 // of kMrGrid workgroups keeps the partials' reads down; each thread updates
 // four elements per pass.
 constexpr int kMrGrid = 512;
 template <typename R>
 __global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
                                                          const cplx<R>* __restrict__ p, const cd64* __restrict__ part,
-                                                         int G, long n, const int* __restrict__ run) {
+                                                         int G, long n, const int* __restrict__ run,
+                                                         cd64* __restrict__ xout) {
   if (run && !*run) return;
   __shared__ cd64 lds[2][4];
   cd64 s0 = mkc(0.0, 0.0), s1 = mkc(0.0, 0.0);
@@ -342,7 +344,8 @@ __global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x,
       if (i < n) {
         cfma(xi[u], a, ri[u]);
         cfma(ri[u], na, pi[u]);
-        x[i] = xi[u];
+        if (xout) xout[i] = ccast<double>(xi[u]);
+        else x[i] = xi[u];
         r[i] = ri[u];
       }
     }
@@ -611,9 +614,9 @@ void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots
 
 template <typename R>
 void launch_mr_update_part(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* part, int G, long n, const int* run,
-                           hipStream_t st) {
+                           hipStream_t st, cd64* xout) {
   hipLaunchKernelGGL(k_mr_update_part<R>, dim3((unsigned)std::min<long>(kMrGrid, nblocks(n))), dim3(kBlock), 0, st, x,
-                     r, p, part, G, n, run);
+                     r, p, part, G, n, run, xout);
   WCMG_CHECK_LAUNCH();
 }
 
@@ -640,7 +643,7 @@ void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd6
   template void launch_scale_inv_norm<R>(cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t);      \
   template void launch_mr_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, const cd64*, long, const int*, hipStream_t); \
   template void launch_mr_update_part<R>(cplx<R>*, cplx<R>*, const cplx<R>*, const cd64*, int, long, const int*,      \
-                                         hipStream_t);                                                              \
+                                         hipStream_t, cd64*);                                                       \
   template void launch_mr_dots_update<R>(cplx<R>*, cplx<R>*, const cplx<R>*, long, cd64*, cd64*, const int*,         \
                                          hipStream_t);
 INST_BLAS(double)

@@ -237,6 +237,9 @@ struct Context {
   template <typename R>
   void apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const int* run, int terms = 0x1ff,
                 cd64* dots = nullptr);
+  // r = b - D x at the fine level, one launch
+  template <typename R>
+  void residual0(const cplx<R>* b, const cplx<R>* x, cplx<R>* r, const int* run);
   int store_prec_for(int l, bool single) const;
 
   // building blocks
@@ -253,7 +256,8 @@ struct Context {
   void setup_learned(Net& net, double threshold, int relax_sweeps, int* fell_back, double* quality);
 
   template <typename R>
-  void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run);
+  // x64 != nullptr (fine level): the final x goes to x64 in FP64 instead of x
+  void mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run, cd64* x64 = nullptr);
   // `cycles` SAP cycles on D x = b at level 0 for nrhs fields (run flags with
   // stride rs; run may be null)
   void sap_prepare();
@@ -265,7 +269,8 @@ struct Context {
   template <typename R>
   void sap(const cplx<R>* b, cplx<R>* x, int cycles, int nrhs, const int* run, int rs);
   template <typename R>
-  void cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run);
+  // x64 != nullptr: the result goes to x64 in FP64 (x is then scratch)
+  void cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run, cd64* x64 = nullptr);
   void precondition64(int l, const cd64* r, cd64* x, const int* run);
   template <typename R>
   int coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* parent, int check_every);

@@ -372,6 +372,20 @@ void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const i
 }
 
 template <typename R>
+void Context::residual0(const cplx<R>* b, const cplx<R>* x, cplx<R>* r, const int* run) {
+  const bool single = sizeof(R) == 4;
+  const char* fam = single ? "dslash_f32" : "dslash_f64";
+  prof.begin_kernel(fam);
+  if (single)
+    launch_wilson<float>((const cf32*)x, (cf32*)r, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V,
+                         0x1ff, 1, run, stream, nullptr, 0, (const cf32*)b);
+  else
+    launch_wilson<double>((const cd64*)x, (cd64*)r, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
+                          geo[0].V, 0x1ff, 1, run, stream, nullptr, 0, (const cd64*)b);
+  prof.end(fam, stream);
+}
+
+template <typename R>
 double Context::norm2_host(const cplx<R>* v, long n) {
   cd64* s = scratch64.as<cd64>() + 8;
   launch_dot<R>(v, 0, 1, nullptr, v, n, partial.as<cd64>(), 1, s, 1, 0, nullptr, stream);
@@ -431,7 +445,7 @@ void Context::prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumula
 //   p = D r; alpha = <p,r>/<p,p>; x += alpha r; r -= alpha p.
 // b == nullptr means b = 0 (relaxation on D x = 0).
 template <typename R>
-void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run) {
+void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, const int* run, cd64* x64) {
   const long nn = n(l);
   const std::string t = std::to_string(l) + (sizeof(R) == 8 ? "d" : "f");
   cplx<R>* r = buf<cplx<R>>("mr_r" + t, nn);
@@ -441,6 +455,8 @@ void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, c
     launch_zero<R>(x, nn, run, stream);
     if (b) launch_convert<R, R>(b, r, nn, run, stream);
     else launch_zero<R>(r, nn, run, stream);
+  } else if (l == 0 && b) {
+    residual0<R>(b, x, r, run);
   } else {
     apply_op<R>(l, x, pp, 1, run);
     if (b) launch_sub<R>(r, b, pp, nn, run, stream);
@@ -452,10 +468,12 @@ void Context::mr(int l, const cplx<R>* b, cplx<R>* x, bool x0_zero, int steps, c
     cd64* part = buf<cd64>("mr_part" + t, 2L * G);
     for (int k = 0; k < steps; ++k) {
       apply_op<R>(l, r, pp, 1, run, 0x1ff, part);
-      launch_mr_update_part<R>(x, r, pp, part, G, nn, run, stream);
+      launch_mr_update_part<R>(x, r, pp, part, G, nn, run, stream, k + 1 == steps ? x64 : nullptr);
     }
+    if (x64 && steps == 0) launch_convert<R, double>(x, x64, nn, run, stream);
     return;
   }
+  require(!x64, WCMG_ERR_ARG, "MR: the FP64 output form is for the fine level");
   for (int k = 0; k < steps; ++k) {
     apply_op<R>(l, r, pp, 1, run);
     launch_mr_dots_update<R>(x, r, pp, nn, partial.as<cd64>(), dots, run, stream);
@@ -702,7 +720,7 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
 // correction (GMRES on the coarsest level, FGMRES preconditioned by the next
 // cycle for a K-cycle, or the next V-cycle), prolong, post-smooth with MR.
 template <typename R>
-void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
+void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run, cd64* x64) {
   const int lc = l + 1;
   const std::string t = std::to_string(lc) + (sizeof(R) == 8 ? "d" : "f");
   const long nc = n(lc);
@@ -731,8 +749,15 @@ void Context::cycle(int l, const cplx<R>* r, cplx<R>* x, const int* run) {
     cycle<R>(lc, rc, ec, run);
   }
   prolong_<R>(l, ec, x, 0, 1, run);
-  if (l == 0 && p.smoother == 1) sap<R>(r, x, p.post_smooth, 1, run, 0);
-  else mr<R>(l, r, x, false, p.post_smooth, run);
+  if (l == 0 && p.smoother == 1) {
+    sap<R>(r, x, p.post_smooth, 1, run, 0);
+    if (x64) launch_convert<R, double>(x, x64, n(l), run, stream);
+  } else if (l == 0) {
+    mr<R>(l, r, x, false, p.post_smooth, run, x64);
+  } else {
+    mr<R>(l, r, x, false, p.post_smooth, run);
+    if (x64) launch_convert<R, double>(x, x64, n(l), run, stream);
+  }
   cycles++;
 }
 
@@ -846,8 +871,7 @@ void Context::precondition64(int l, const cd64* r, cd64* x, const int* run) {
   cf32* r32 = buf<cf32>("pc_r32" + t, nn);
   cf32* x32 = buf<cf32>("pc_x32" + t, nn);
   launch_convert<double, float>(r, r32, nn, run, stream);
-  cycle<float>(l, r32, x32, run);
-  launch_convert<float, double>(x32, x, nn, run, stream);
+  cycle<float>(l, r32, x32, run, x);
 }
 
 // ---------------------------------------------------------------- setup
@@ -989,12 +1013,12 @@ template void Context::restrict_<double>(int, const cd64*, cd64*, int, const int
 template void Context::restrict_<float>(int, const cf32*, cf32*, int, const int*);
 template void Context::prolong_<double>(int, const cd64*, cd64*, int, int, const int*);
 template void Context::prolong_<float>(int, const cf32*, cf32*, int, int, const int*);
-template void Context::mr<double>(int, const cd64*, cd64*, bool, int, const int*);
-template void Context::mr<float>(int, const cf32*, cf32*, bool, int, const int*);
-template void Context::cycle<double>(int, const cd64*, cd64*, const int*);
+template void Context::mr<double>(int, const cd64*, cd64*, bool, int, const int*, cd64*);
+template void Context::mr<float>(int, const cf32*, cf32*, bool, int, const int*, cd64*);
+template void Context::cycle<double>(int, const cd64*, cd64*, const int*, cd64*);
 template int Context::coarse_gmres<double>(int, const cd64*, cd64*, const int*, int);
 template int Context::coarse_gmres<float>(int, const cf32*, cf32*, const int*, int);
-template void Context::cycle<float>(int, const cf32*, cf32*, const int*);
+template void Context::cycle<float>(int, const cf32*, cf32*, const int*, cd64*);
 template int Context::gmres<double>(GmresState&, const std::function<void(const cd64*, cd64*, const int*)>&,
                                     const std::function<void(const cd64*, cd64*, const int*)>*, const cd64*, cd64*,
                                     bool, int, int, double, int, bool, const int*, int, bool);

@@ -21,8 +21,10 @@ void launch_pack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, 
 template <typename Ti, typename To>
 void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
 template <typename R>
+// bsub != nullptr (whole operator, no dots): out = bsub - D in.
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0);
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0,
+                   const cplx<R>* bsub = nullptr);
 int wilson_blocks(long V);
 // FP32 D on nrhs fields with the links and clover read once per launch; MR
 // partials (optional) at dots[2 * (r * wilson_blocks(V) + blk)]
@@ -135,10 +137,11 @@ void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots
                       hipStream_t st);
 // MR update whose step length <p, r> / <p, p> is summed from G per-workgroup
 // partial pairs part[2g], part[2g+1] inside the update kernel (same order and
-// result as launch_dot_finish).
+// result as launch_dot_finish).  xout != nullptr: the new x goes there in
+// FP64 instead of to x.
 template <typename R>
 void launch_mr_update_part(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* part, int G, long n, const int* run,
-                           hipStream_t st);
+                           hipStream_t st, cd64* xout = nullptr);
 template <typename R>
 void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd64* partial, cd64* dots,
                            const int* run, hipStream_t st);

@@ -246,12 +246,14 @@ __global__ void k_unpack_fermion(const cplx<Ti>* __restrict__ in, const int* __r
 // inner products of an MR step, where in = r and out = D r) go to
 // dots[2*blk], dots[2*blk+1].  Waves 0 and 1 then write the output of their
 // chirality and form the products with the input components they loaded for
-// the clover block.
+// the clover block.  bsub != nullptr (without dots): out = bsub - D in, the
+// residual of in for the right-hand side bsub.
 template <typename R, bool ALL>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                                  const int* __restrict__ nbr, long V, int terms, int nrhs,
-                                                 cd64* __restrict__ dots, const int* __restrict__ run, int rs) {
+                                                 cd64* __restrict__ dots, const int* __restrict__ run, int rs,
+                                                 const cplx<R>* __restrict__ bsub) {
   const long nblk = (V + 63) / 64;
   long blk, r;
   if (!item_rhs(nblk, nrhs, &blk, &r)) return;
@@ -322,7 +324,10 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
       v = cadd(v, part[1][k][lane]);
       v = cadd(v, part[2][k][lane]);
       v = cadd(v, part[3][k][lane]);
-      if (valid) out[(long)k * V + s] = v;
+      if (valid) {
+        if (bsub) v = csub(bsub[r * 12 * V + (long)k * V + s], v);
+        out[(long)k * V + s] = v;
+      }
     }
     return;
   }
@@ -557,19 +562,20 @@ INST_PACK(float, double)
 
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs) {
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs, const cplx<R>* bsub) {
+  require(!bsub || (!dots && terms == 0x1ff), WCMG_ERR_ARG, "Dslash: the residual form takes the whole operator");
   if (terms == 0x1ff)
     WCMG_LAUNCH((k_wilson<R, true>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
-                nbr, V, terms, nrhs, dots, run, rs);
+                nbr, V, terms, nrhs, dots, run, rs, bsub);
   else
     WCMG_LAUNCH((k_wilson<R, false>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
-                nbr, V, terms, nrhs, dots, run, rs);
+                nbr, V, terms, nrhs, dots, run, rs, bsub);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
-                                    const int*, hipStream_t, cd64*, int);
+                                    const int*, hipStream_t, cd64*, int, const cd64*);
 template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
-                                   const int*, hipStream_t, cd64*, int);
+                                   const int*, hipStream_t, cd64*, int, const cf32*);
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 
