@@ -151,6 +151,9 @@ __global__ void __launch_bounds__(256) k_multi_axpy_norm(cplx<R>* __restrict__ y
 // back (s = *shift; no shift when shift is null), then per-workgroup partials
 // of <V_q, y> for q <= j and of |y|^2 (entry j + 1), mstride entries per
 // workgroup.  Columns are taken KT at a time; only the first tile forms y.
+// Elements are dealt out grid-stride (workgroup b takes blocks b, b + G, ...
+// of 256 elements), so the resident workgroups read one contiguous window of
+// each vector at a time.
 template <typename R>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(cplx<R>* __restrict__ V, long n, int j,
                                                        const cd64* __restrict__ shift, cd64* __restrict__ partial,
@@ -159,8 +162,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(cplx<R>* __restrict__ V, l
   constexpr int KT = 8;
   __shared__ cd64 lds[4][KT];
   const int m = j + 2;
-  const long chunk = (n + gridDim.x - 1) / gridDim.x;
-  const long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const long gs = (long)gridDim.x * blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const R sh = shift ? (R)shift->re : (R)0;
   cplx<R>* yv = V + (long)(j + 1) * n;
@@ -168,17 +170,26 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(cplx<R>* __restrict__ V, l
     cd64 s[KT];
 #pragma unroll
     for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
-    for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += gs) {
+      // every load of the tile first (vector index clamped to j, so each
+      // address is valid and y is taken by value below), then the stores
       cplx<R> y = yv[i];
+      cplx<R> xs[KT];
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int k = k0 + q;
+        xs[q] = V[(long)(k <= j ? k : j) * n + i];
+      }
       if (k0 == 0 && shift) {
-        y = csub(y, cscale(sh, V[(long)j * n + i]));
+        const cplx<R> vj = V[(long)j * n + i];
+        y = csub(y, cscale(sh, vj));
         yv[i] = y;
       }
 #pragma unroll
       for (int q = 0; q < KT; ++q) {
         const int k = k0 + q;
         if (k < m) {
-          const cplx<R> x = k == j + 1 ? y : V[(long)k * n + i];
+          const cplx<R> x = k == j + 1 ? y : xs[q];
           s[q].re += (double)x.re * y.re + (double)x.im * y.im;
           s[q].im += (double)x.re * y.im - (double)x.im * y.re;
         }
@@ -672,9 +683,9 @@ void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, i
 }
 template <typename R>
 void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_dots<R>, dim3(red_blocks(n)), dim3(kBlock), 0, st, V, n, j, shift, partial, mstride,
-                     run);
+                         hipStream_t st, int grid) {
+  hipLaunchKernelGGL(k_arnoldi_dots<R>, dim3(grid > 0 ? grid : red_blocks(n)), dim3(kBlock), 0, st, V, n, j, shift,
+                     partial, mstride, run);
   WCMG_CHECK_LAUNCH();
 }
 template <typename R>
@@ -683,8 +694,8 @@ void launch_update_scale(cplx<R>* y, const cplx<R>* V, long vstride, int m, cons
   hipLaunchKernelGGL(k_update_scale<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, V, vstride, m, coef, nrm2, n, run);
   WCMG_CHECK_LAUNCH();
 }
-template void launch_arnoldi_dots<double>(cd64*, long, int, const cd64*, cd64*, int, const int*, hipStream_t);
-template void launch_arnoldi_dots<float>(cf32*, long, int, const cd64*, cd64*, int, const int*, hipStream_t);
+template void launch_arnoldi_dots<double>(cd64*, long, int, const cd64*, cd64*, int, const int*, hipStream_t, int);
+template void launch_arnoldi_dots<float>(cf32*, long, int, const cd64*, cd64*, int, const int*, hipStream_t, int);
 template void launch_update_scale<double>(cd64*, const cd64*, long, int, const cd64*, const cd64*, long, const int*,
                                           hipStream_t);
 template void launch_update_scale<float>(cf32*, const cf32*, long, int, const cd64*, const cd64*, long, const int*,

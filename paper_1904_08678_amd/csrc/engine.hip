@@ -545,8 +545,10 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
         launch_dot_finish(part, Gb, j + 2, j + 2, tmp, 1, 0, run, stream);
         launch_gmres_sr(st, S, m, j, tmp, tmp2, 0, stream);
         launch_multi_axpy<R>(wj, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, st + 5, stream);
-        launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream);
-        launch_dot_finish(part, Gb, j + 2, j + 2, tmp2, 1, 0, st + 5, stream);
+        // the second projection is rare: a small grid, so that skipping it is cheap
+        const int G2 = std::min(Gb, 256);
+        launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream, G2);
+        launch_dot_finish(part, G2, j + 2, j + 2, tmp2, 1, 0, st + 5, stream);
         launch_gmres_sr(st, S, m, j, tmp, tmp2, 1, stream);
         launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
         if (j + 1 < m) launch_update_scale<R>(wj, V, nn, j + 1, tmp, misc + 3, nn, run, stream);

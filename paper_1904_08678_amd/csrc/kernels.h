@@ -154,8 +154,9 @@ void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
 // dots with V_0..V_j and its norm), bookkeeping, last sweep (update + scale)
 void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st);
 template <typename R>
+// grid: workgroups (partials) to use, 0 = reduction_blocks(n)
 void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
-                         hipStream_t st);
+                         hipStream_t st, int grid = 0);
 template <typename R>
 void launch_update_scale(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, const cd64* nrm2,
                          long n, const int* run, hipStream_t st);
