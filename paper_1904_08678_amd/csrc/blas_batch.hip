@@ -95,16 +95,25 @@ __global__ void __launch_bounds__(256) k_barnoldi_dots(cplx<R>* __restrict__ V, 
 #pragma unroll
     for (int q = 0; q < KT; ++q) s[q] = mkc(0.0, 0.0);
     for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      // every load of the tile first (vector index clamped to j, so each
+      // address is valid and y is taken by value below), then the stores
       cplx<R> y = yv[i];
+      cplx<R> xs[KT];
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const int k = k0 + q;
+        xs[q] = V[(long)(k <= j ? k : j) * vvs + i];
+      }
       if (k0 == 0 && shift) {
-        y = csub(y, cscale(sh, V[(long)j * vvs + i]));
+        const cplx<R> vj = V[(long)j * vvs + i];
+        y = csub(y, cscale(sh, vj));
         yv[i] = y;
       }
 #pragma unroll
       for (int q = 0; q < KT; ++q) {
         const int k = k0 + q;
         if (k < m) {
-          const cplx<R> x = k == j + 1 ? y : V[(long)k * vvs + i];
+          const cplx<R> x = k == j + 1 ? y : xs[q];
           s[q].re += (double)x.re * y.re + (double)x.im * y.im;
           s[q].im += (double)x.re * y.im - (double)x.im * y.re;
         }
