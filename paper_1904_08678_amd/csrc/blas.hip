@@ -104,15 +104,16 @@ __global__ void __launch_bounds__(256) k_multi_axpy(cplx<R>* __restrict__ y, con
                                                      const int* __restrict__ run) {
   if (run && !*run) return;
   if (m_dev) m = *m_dev;
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  cplx<R> acc = y[i];
-  for (int k = 0; k < m; ++k) {
-    cd64 c = coef[(long)k * cstride];
-    cplx<R> cc = mkc((R)(sign * c.re), (R)(sign * c.im));
-    cfma(acc, cc, V[k * vstride + i]);
+  // grid-stride (the grid may be capped below one thread per element)
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    cplx<R> acc = y[i];
+    for (int k = 0; k < m; ++k) {
+      cd64 c = coef[(long)k * cstride];
+      cplx<R> cc = mkc((R)(sign * c.re), (R)(sign * c.im));
+      cfma(acc, cc, V[k * vstride + i]);
+    }
+    y[i] = acc;
   }
-  y[i] = acc;
 }
 
 // y[i] += sign * sum_{k<m} coef[k] V_k[i], then per-workgroup partials of |y|^2
@@ -581,9 +582,10 @@ void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out
 
 template <typename R>
 void launch_multi_axpy(cplx<R>* y, const cplx<R>* V, long vstride, int m, const int* m_dev, const cd64* coef,
-                       int cstride, double sign, long n, const int* run, hipStream_t st) {
-  hipLaunchKernelGGL(k_multi_axpy<R>, dim3(nblocks(n)), dim3(kBlock), 0, st, y, V, vstride, m, m_dev, coef, cstride,
-                     sign, n, run);
+                       int cstride, double sign, long n, const int* run, hipStream_t st, int grid) {
+  const long g = nblocks(n);
+  hipLaunchKernelGGL(k_multi_axpy<R>, dim3((unsigned)(grid > 0 && grid < g ? grid : g)), dim3(kBlock), 0, st, y, V,
+                     vstride, m, m_dev, coef, cstride, sign, n, run);
   WCMG_CHECK_LAUNCH();
 }
 
@@ -647,7 +649,7 @@ void launch_mr_dots_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, long n, cd6
   template void launch_dot<R>(const cplx<R>*, long, int, const int*, const cplx<R>*, long, cd64*, int, cd64*, int,   \
                               int, const int*, hipStream_t);                                                        \
   template void launch_multi_axpy<R>(cplx<R>*, const cplx<R>*, long, int, const int*, const cd64*, int, double, long, \
-                                     const int*, hipStream_t);                                                      \
+                                     const int*, hipStream_t, int);                                                 \
   template void launch_axpby<R>(cplx<R>*, const cplx<R>*, double, double, long, const int*, hipStream_t);            \
   template void launch_zero<R>(cplx<R>*, long, const int*, hipStream_t);                                             \
   template void launch_sub<R>(cplx<R>*, const cplx<R>*, const cplx<R>*, long, const int*, hipStream_t);              \

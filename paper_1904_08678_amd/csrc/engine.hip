@@ -544,7 +544,7 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
         launch_arnoldi_dots<R>(V, nn, j, j > 0 ? misc + 4 : nullptr, part, j + 2, run, stream);
         launch_dot_finish(part, Gb, j + 2, j + 2, tmp, 1, 0, run, stream);
         launch_gmres_sr(st, S, m, j, tmp, tmp2, 0, stream);
-        launch_multi_axpy<R>(wj, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, st + 5, stream);
+        launch_multi_axpy<R>(wj, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, st + 5, stream, 1024);
         // the second projection is rare: a small grid, so that skipping it is cheap
         const int G2 = std::min(Gb, 256);
         launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream, G2);

@@ -121,7 +121,7 @@ void launch_dot_finish(const cd64* partial, int G, int m, int mstride, cd64* out
                        const int* run, hipStream_t st);
 template <typename R>
 void launch_multi_axpy(cplx<R>* y, const cplx<R>* V, long vstride, int m, const int* m_dev, const cd64* coef,
-                       int cstride, double sign, long n, const int* run, hipStream_t st);
+                       int cstride, double sign, long n, const int* run, hipStream_t st, int grid = 0);
 template <typename R>
 void launch_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, long n, const int* run, hipStream_t st);
 template <typename R>
