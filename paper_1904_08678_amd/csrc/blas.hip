@@ -466,8 +466,8 @@ __global__ void k_gmres_sr(int* st, cd64* S, int m, int j, cd64* d, const cd64* 
 }
 
 // Givens update for column j (after H[0..j][j] and hn^2 = misc[3]).
-__global__ void k_gmres_givens(int* st, cd64* S, int m, int j, double tol, int limit, int fixed,
-                               int stop_on_estimate) {
+__device__ void gmres_givens_body(int* st, cd64* S, int m, int j, double tol, int limit, int fixed,
+                                  int stop_on_estimate) {
   if (!st[0]) return;
   cd64* H = S;
   cd64* cs = S + (m + 1) * m;
@@ -520,6 +520,58 @@ __global__ void k_gmres_givens(int* st, cd64* S, int m, int j, double tol, int l
     st[4] = (est == est) ? 1 : 3;
   }
   if (stop || j + 1 == m) st[0] = 0;
+}
+__global__ void k_gmres_givens(int* st, cd64* S, int m, int j, double tol, int limit, int fixed,
+                               int stop_on_estimate) {
+  gmres_givens_body(st, S, m, j, tol, limit, fixed, stop_on_estimate);
+}
+
+// The end of a single-reduction Arnoldi step in one workgroup: when the
+// second projection ran (st[5]), its G2 per-workgroup partials (mstride =
+// j + 2 entries each) are summed in k_dot_finish's order, then the stage-1
+// bookkeeping of k_gmres_sr, then the Givens update of column j.  d2: j + 2
+// entries of scratch for the sums (written and read by thread 0 only).
+__global__ void __launch_bounds__(256) k_gmres_sr_finish(int* st, cd64* S, int m, int j, cd64* d, cd64* d2,
+                                                          const cd64* __restrict__ part2, int G2, double tol,
+                                                          int limit, int fixed, int stop_on_estimate) {
+  __shared__ cd64 lds[4];
+  if (!st[0]) return;
+  const bool reorth = st[5] != 0;  // the same value in every thread
+  if (reorth) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < j + 2; ++k) {
+      cd64 v = mkc(0.0, 0.0);
+      for (int g = threadIdx.x; g < G2; g += blockDim.x) v = cadd(v, part2[(long)g * (j + 2) + k]);
+      v = wave_sum(v);
+      if (lane == 0) lds[wave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        cd64 t = mkc(0.0, 0.0);
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
+        d2[k] = t;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x != 0) return;
+  if (reorth) {
+    cd64* H = S;
+    cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+    double n2 = d2[j + 1].re;
+    for (int i = 0; i <= j; ++i) {
+      H[i * m + j] = cadd(H[i * m + j], d2[i]);
+      n2 -= d2[i].re * d2[i].re + d2[i].im * d2[i].im;
+      d[i] = d2[i];
+    }
+    misc[3] = mkc(n2 > 0.0 ? n2 : 0.0, 0.0);
+  }
+  gmres_givens_body(st, S, m, j, tol, limit, fixed, stop_on_estimate);
+}
+void launch_gmres_sr_finish(int* st_, cd64* S, int m, int j, cd64* d, cd64* d2, const cd64* part2, int G2,
+                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_sr_finish, dim3(1), dim3(kBlock), 0, st, st_, S, m, j, d, d2, part2, G2, tol, limit,
+                     fixed, stop_on_est);
+  WCMG_CHECK_LAUNCH();
 }
 
 // Back substitution H y = g on the leading jdone x jdone triangle.

@@ -548,9 +548,7 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
         // the second projection is rare: a small grid, so that skipping it is cheap
         const int G2 = std::min(Gb, 256);
         launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream, G2);
-        launch_dot_finish(part, G2, j + 2, j + 2, tmp2, 1, 0, st + 5, stream);
-        launch_gmres_sr(st, S, m, j, tmp, tmp2, 1, stream);
-        launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
+        launch_gmres_sr_finish(st, S, m, j, tmp, tmp2, part, G2, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
         if (j + 1 < m) launch_update_scale<R>(wj, V, nn, j + 1, tmp, misc + 3, nn, run, stream);
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
           read_state();

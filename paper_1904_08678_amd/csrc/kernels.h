@@ -153,6 +153,11 @@ void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
 // single-reduction Arnoldi step (blas.hip): first sweep (shifted vector, its
 // dots with V_0..V_j and its norm), bookkeeping, last sweep (update + scale)
 void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st);
+// Stage 1 of launch_gmres_sr (its second-projection products summed from G2
+// partials part2[g * (j + 2) + k] inside, into d2) followed by
+// launch_gmres_givens, in one single-workgroup launch.
+void launch_gmres_sr_finish(int* st_, cd64* S, int m, int j, cd64* d, cd64* d2, const cd64* part2, int G2,
+                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st);
 template <typename R>
 // grid: workgroups (partials) to use, 0 = reduction_blocks(n)
 void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
