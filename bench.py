@@ -632,8 +632,8 @@ def main():
     global COARSE_POINTS
     COARSE_POINTS = args.coarse_points
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; N=%d is not supported (the path would shard by 4D domain "
-              "decomposition, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; N=%d is not supported (a multi-GPU run would shard the "
+              "lattice by 4D domain decomposition, which is not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.family:
         kernel_mode(args)
