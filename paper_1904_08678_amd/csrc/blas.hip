@@ -309,7 +309,7 @@ __global__ void k_mr_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, co
 // nullptr: the updated x is written there in FP64 (x itself is left as is).  A fixed grid
 // of kMrGrid workgroups keeps the partials' reads down; each thread updates
 // four elements per pass.
-constexpr int kMrGrid = 512;
+constexpr int kMrGrid = 1024;
 template <typename R>
 __global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
                                                          const cplx<R>* __restrict__ p, const cd64* __restrict__ part,
