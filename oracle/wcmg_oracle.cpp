@@ -764,8 +764,17 @@ KrylovResult gmres_core(const LinOp& A, const LinOp* M, long n, const cd* b, cd*
       }
       cd hjj = H[j * restart + j];
       double den = std::sqrt(std::norm(hjj) + hn * hn);
-      if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-      else { cs[j] = hjj / den; sn[j] = hn / den; }
+      if (den == 0.0) {
+        // A z_j lies in the span of the earlier basis vectors and the rotated
+        // column vanishes: it adds nothing to the least-squares problem, whose
+        // minimiser is that of the leading j x j system; the residual stays |g_j|
+        res.iters++;
+        res.est = std::abs(g[j]) / bnorm;
+        stop = true;
+        break;
+      }
+      cs[j] = hjj / den;
+      sn[j] = hn / den;
       // rotation [c s; -conj(s) conj(c)] with c = h/den, s = hn/den maps (h, hn) to (|.|, 0)
       cs[j] = std::conj(cs[j]);
       H[j * restart + j] = cs[j] * hjj + sn[j] * hn;
@@ -904,9 +913,11 @@ int initial_setup(Hierarchy& H, int l) {
   return rebuild(H, l);
 }
 
-// Re-take the Galerkin products below level l with the existing prolongators.
+// Re-take the Galerkin products below level l with the existing prolongators
+// (down to the first level whose prolongator has not been built yet).
 int regalerkin_below(Hierarchy& H, int l) {
   for (int k = l + 1; k < (int)H.lv.size(); ++k) {
+    if (!H.lv[k].coarse || H.lv[k].Pv.empty()) break;
     int st = galerkin(H.op(k), H.lv[k].ag, H.lv[k].nv, H.lv[k].Pv, *H.lv[k].coarse);
     if (st) return st;
   }
@@ -1157,6 +1168,10 @@ int or_mg_refine(void* h, int iters) {
 // P_l and D_{l+1}; deeper Galerkin products are re-taken.
 int or_mg_set_vectors(void* h, int l, const double* v) {
   Hierarchy* H = (Hierarchy*)h;
+  if (l < 0 || l >= (int)H->lv.size() || (l > 0 && !H->lv[l - 1].coarse)) {
+    H->err = "level operator not built";
+    return 3;
+  }
   long n = or_mg_size(h, l);
   H->lv[l].vecs.assign((const cd*)v, (const cd*)v + (long)H->lv[l].nv * n);
   int st = rebuild(*H, l);

@@ -493,10 +493,12 @@ __device__ void gmres_givens_body(int* st, cd64* S, int m, int j, double tol, in
   sn[j] = s;
   H[j * m + j] = mkc(den, 0.0);
   H[(j + 1) * m + j] = mkc(0.0, 0.0);
+  // den == 0: A z_j adds nothing (a singular Hessenberg column); the column is
+  // dropped from the least-squares solve and the residual stays |g_j|
   const cd64 gj = g[j];
-  g[j + 1] = cmul(cneg(cconj(s)), gj);
+  g[j + 1] = den == 0.0 ? gj : cmul(cneg(cconj(s)), gj);
   g[j] = cmul(c, gj);
-  st[2] = j + 1;
+  st[2] = den == 0.0 ? j : j + 1;
   st[3] += 1;
   const double bn = sqrt(misc[0].re);
   const double est = bn > 0 ? sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im) / bn : 0.0;
@@ -517,7 +519,7 @@ __device__ void gmres_givens_body(int* st, cd64* S, int m, int j, double tol, in
   if (hn == 0.0 || !(est == est)) {
     stop = true;
     st[1] = 0;
-    st[4] = (est == est) ? 1 : 3;
+    st[4] = (est == est) ? (den == 0.0 ? 4 : 1) : 3;
   }
   if (stop || j + 1 == m) st[0] = 0;
 }
@@ -589,7 +591,7 @@ __global__ void k_gmres_solve_y(const int* st, cd64* S, int m) {
     }
     const cd64 d = H[i * m + i];
     const double dd = d.re * d.re + d.im * d.im;
-    y[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
+    y[i] = dd > 0.0 ? mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd) : mkc(0.0, 0.0);
   }
 }
 

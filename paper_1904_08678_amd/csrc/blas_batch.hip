@@ -445,9 +445,9 @@ __global__ void k_bgmres_givens(int* st, cd64* S, long ss, int B, int m, int j, 
   H[j * m + j] = mkc(den, 0.0);
   H[(j + 1) * m + j] = mkc(0.0, 0.0);
   const cd64 gj = g[j];
-  g[j + 1] = cmul(cneg(cconj(sv)), gj);
+  g[j + 1] = den == 0.0 ? gj : cmul(cneg(cconj(sv)), gj);  // den == 0: singular column, dropped
   g[j] = cmul(c, gj);
-  s[2] = j + 1;
+  s[2] = den == 0.0 ? j : j + 1;
   s[3] += 1;
   const double bn = sqrt(misc[0].re);
   const double est = bn > 0 ? sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im) / bn : 0.0;
@@ -468,7 +468,7 @@ __global__ void k_bgmres_givens(int* st, cd64* S, long ss, int B, int m, int j, 
   if (hn == 0.0 || !(est == est)) {
     stop = true;
     s[1] = 0;
-    s[4] = (est == est) ? 1 : 3;
+    s[4] = (est == est) ? (den == 0.0 ? 4 : 1) : 3;
   }
   if (stop || j + 1 == m) s[0] = 0;
 }
@@ -486,7 +486,7 @@ __global__ void k_bgmres_solve_y(const int* st, cd64* S, long ss, int B, int m) 
     for (int k = i + 1; k < jd; ++k) s = csub(s, cmul(H[i * m + k], y[k]));
     const cd64 d = H[i * m + i];
     const double dd = d.re * d.re + d.im * d.im;
-    y[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
+    y[i] = dd > 0.0 ? mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd) : mkc(0.0, 0.0);
   }
 }
 

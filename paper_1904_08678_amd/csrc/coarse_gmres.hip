@@ -230,9 +230,9 @@ __global__ void __launch_bounds__(256) k_cg_givens(int* st, cd64* S, int m, int 
   H[j * m + j] = mkc(den, 0.0);
   H[(j + 1) * m + j] = mkc(0.0, 0.0);
   const cd64 gj = c.g[j];
-  c.g[j + 1] = cmul(cneg(cconj(ss)), gj);
+  c.g[j + 1] = den == 0.0 ? gj : cmul(cneg(cconj(ss)), gj);  // den == 0: singular column, dropped
   c.g[j] = cmul(cc, gj);
-  st[2] = j + 1;
+  st[2] = den == 0.0 ? j : j + 1;
   st[3] += 1;
   const double bn = sqrt(c.misc[0].re);
   const double est = bn > 0 ? sqrt(c.g[j + 1].re * c.g[j + 1].re + c.g[j + 1].im * c.g[j + 1].im) / bn : 0.0;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_cg_givens(int* st, cd64* S, int m, int 
   if (hn == 0.0 || !(est == est)) {
     stop = true;
     st[1] = 0;
-    st[4] = (est == est) ? 1 : 3;
+    st[4] = (est == est) ? (den == 0.0 ? 4 : 1) : 3;
   }
   if (stop || j + 1 == m) st[0] = 0;
 }

@@ -486,9 +486,9 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         hcol[j] = mkc(den, 0.0);
         for (int i = 0; i <= j; ++i) rtri[j * (j + 1) / 2 + i] = hcol[i];
         const cd64 gj = gv[j];
-        gv[j + 1] = cmul(cneg(cconj(ss)), gj);
+        gv[j + 1] = den == 0.0 ? gj : cmul(cneg(cconj(ss)), gj);  // den == 0: singular column, dropped
         gv[j] = cmul(cc, gj);
-        ctl[2] = j + 1;
+        ctl[2] = den == 0.0 ? j : j + 1;
         ctl[3] += 1;
         const double bn = sqrt(scal[1]);
         const double est = bn > 0 ? sqrt(gv[j + 1].re * gv[j + 1].re + gv[j + 1].im * gv[j + 1].im) / bn : 0.0;
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         }
         if (hn == 0.0 || !(est == est)) {
           stop = true;
-          reason = (est == est) ? 1 : 3;
+          reason = (est == est) ? (den == 0.0 ? 4 : 1) : 3;
         }
         if (stop) ctl[1] = 0;
         ctl[0] = (stop || j + 1 == m) ? 0 : 1;
@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         for (int k = i + 1; k < jd; ++k) s = csub(s, cmul(rtri[k * (k + 1) / 2 + i], yv[k]));
         const cd64 d = rtri[i * (i + 1) / 2 + i];
         const double dd = d.re * d.re + d.im * d.im;
-        yv[i] = mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd);
+        yv[i] = dd > 0.0 ? mkc((s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd) : mkc(0.0, 0.0);
       }
     __syncthreads();
     if (own) {

@@ -5,9 +5,13 @@ kernels of libwcmg.so.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import itertools
 import json
 import os
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -17,6 +21,30 @@ BATCH_GRAPH, BATCH_VECTOR, BATCH_MFMA, BATCH_DSLASH_PER_RHS = 1, 2, 4, 8
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libwcmg.so")
 _lib = None
+
+# Every live handle (context, network, standalone coarse operator), so that
+# they can be destroyed from an atexit hook: Python runs atexit hooks before
+# it tears modules down, while the HIP runtime (and any profiling tool loaded
+# into the process) is still fully alive.  Destroying them later, from
+# finalizer order during interpreter shutdown, would free pinned host memory
+# and streams after the runtime has begun its own teardown.
+_live = weakref.WeakValueDictionary()
+_order = itertools.count()
+
+
+def _register(obj):
+    _live[next(_order)] = obj
+
+
+def close_all():
+    """Destroy every live wcmg handle, newest first (also run at exit)."""
+    for k in sorted(list(_live.keys()), reverse=True):
+        obj = _live.get(k)
+        if obj is not None:
+            obj.close()
+
+
+atexit.register(close_all)
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DIMS", 3: "ERR_STATE", 4: "ERR_HIP", 5: "ERR_NOMEM", 6: "ERR_BREAKDOWN",
           7: "ERR_NOCONV", 8: "ERR_NAN"}
@@ -163,11 +191,23 @@ class Context:
         for l in range(self.nlev - 1):
             self.level_dims.append(tuple(self.level_dims[-1][m] // self.p.block[l][m] for m in range(4)))
         self.ns = [12] + [2 * self.p.n_vec[l] for l in range(self.nlev - 1)]
+        _register(self)
 
-    def __del__(self):
+    def close(self):
+        """wcmg_destroy: synchronises the context's stream, frees its buffers."""
         if getattr(self, "h", None) and _lib is not None:
             _lib.wcmg_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
     def _chk(self, st):
         if st:
@@ -374,11 +414,16 @@ class Network:
         n = C.c_int64(0)
         lib().wcmg_nn_num_weights(self.h, C.byref(n))
         self.n_floats = n.value
+        _register(self)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.wcmg_nn_destroy(self.h)
+        self.h = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().wcmg_nn_destroy(self.h)
-            self.h = None
+        if not sys.is_finalizing():
+            self.close()
 
     def _chk(self, st):
         if st:
@@ -426,11 +471,16 @@ class CoarseOperator:
         self.nb = nb
         self.store = store_prec
         self.Vc = int(dims[0] * dims[1] * dims[2] * dims[3])
+        _register(self)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.wcmg_coarse_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
     def _chk(self, st):
         if st:

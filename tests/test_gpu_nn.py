@@ -77,6 +77,12 @@ def test_loss_and_gradient_parity(act, tol):
     assert abs(loss - ref_loss) < tol * ref_loss
     ref_flat = np.concatenate([np.stack([2 * x.real, 2 * x.imag], -1).ravel() for x in ref_g])
     assert rel(g, ref_flat) < tol
+    # layer by layer, so that one small layer's wrong sign cannot hide in the total
+    off = 0
+    for x in ref_g:
+        n = 2 * x.size
+        assert rel(g[off:off + n], ref_flat[off:off + n]) < tol
+        off += n
 
 
 def test_forward_gauge_covariance_on_gpu():

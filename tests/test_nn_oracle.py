@@ -146,3 +146,51 @@ def test_squash_backward_matches_differences():
             fd = (f(zp) - f(zm)) / (2 * d)
             an = 2 * (gz[idx].real if part == 1.0 else gz[idx].imag)
             assert abs(fd - an) < 1e-8
+
+
+def test_adam_first_step_closed_form():
+    """At t = 1 the bias corrections make m_hat = g and v_hat = g^2, so the
+    step is -lr g / (|g| + eps) per real parameter, whatever b1 and b2 are."""
+    from oracle import nn as onn
+    g = np.array([0.3, -2.0, 1e-9, 0.0, 5e3], np.float64)
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.8)):
+        w = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+        w0 = w.copy()
+        m = np.zeros_like(w)
+        v = np.zeros_like(w)
+        onn.adam_step(w, g, m, v, 1, 0.01, b1=b1, b2=b2, eps=1e-8)
+        assert np.allclose(w - w0, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+        assert np.allclose(m, (1 - b1) * g, rtol=1e-15) and np.allclose(v, (1 - b2) * g * g, rtol=1e-15)
+
+
+def test_adam_constant_gradient_keeps_the_first_step():
+    """With the same gradient at every step, m = (1 - b1^t) g and
+    v = (1 - b2^t) g^2 exactly, so every bias-corrected step equals the first:
+    after t steps w moved by -t lr g / (|g| + eps)."""
+    from oracle import nn as onn
+    g = np.array([0.7, -0.2, 3.0])
+    w = np.zeros(3)
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for t in range(1, 8):
+        onn.adam_step(w, g, m, v, t, 1e-3)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+        assert np.allclose(w, -t * 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-10)
+
+
+def test_adam_second_step_hand_computed():
+    """Two different gradients: the second step from the definitions
+    m_2 = b1 (1-b1) g1 + (1-b1) g2, v_2 = b2 (1-b2) g1^2 + (1-b2) g2^2,
+    divided by (1 - b^2)."""
+    from oracle import nn as onn
+    g1, g2 = np.array([1.0, -3.0]), np.array([-0.5, 2.0])
+    w = np.zeros(2)
+    m = np.zeros(2)
+    v = np.zeros(2)
+    onn.adam_step(w, g1, m, v, 1, 0.1)
+    w1 = w.copy()
+    onn.adam_step(w, g2, m, v, 2, 0.1)
+    m2 = (0.9 * 0.1 * g1 + 0.1 * g2) / (1 - 0.81)
+    v2 = (0.999 * 0.001 * g1 ** 2 + 0.001 * g2 ** 2) / (1 - 0.999 ** 2)
+    assert np.allclose(w - w1, -0.1 * m2 / (np.sqrt(v2) + 1e-8), rtol=1e-12)

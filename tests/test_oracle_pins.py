@@ -463,3 +463,21 @@ def test_refinement_trend_and_three_level_kcycle():
     H3.refine(1)
     x, it, rel, st = H3.solve(b)
     assert st == 0 and rel <= 1e-10
+
+
+def test_gmres_on_a_singular_operator_keeps_the_least_squares_minimiser():
+    """A zero operator makes the first rotated Hessenberg column vanish
+    exactly: the minimiser over the Krylov space is x = 0 with the residual
+    |b| (not a division by zero).  A block-diagonal operator with a null space
+    and b inside it gives the same."""
+    Lc, nb = (2, 2, 2, 2), 4
+    Vc = 16
+    b = syn.complex_gaussian((Vc, nb), 98)
+    x, it, est = oracle.coarse_gmres(Lc, np.zeros((Vc, 9, nb, nb), np.complex128), b, restart=10, maxit=10, tol=1e-12)
+    assert it == 1 and np.all(x == 0) and abs(est - 1.0) < 1e-15
+    blocks = np.zeros((Vc, 9, nb, nb), np.complex128)
+    blocks[:, 0] = np.diag([1.0, 2.0, 0.0, 0.0])
+    bn = np.zeros((Vc, nb), np.complex128)
+    bn[:, 2:] = b[:, 2:]
+    x, it, est = oracle.coarse_gmres(Lc, blocks, bn, restart=10, maxit=10, tol=1e-12)
+    assert it == 1 and np.all(x == 0) and abs(est - 1.0) < 1e-15
