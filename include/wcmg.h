@@ -153,7 +153,10 @@ int wcmg_setup(wcmg_ctx* ctx);
  * operators are rebuilt. */
 int wcmg_refine(wcmg_ctx* ctx, int iterations);
 /* Replace the near-null vectors of level l (complex128 [nv][V_l][ns_l]) and
- * rebuild P_l, D_{l+1} and the Galerkin products below. */
+ * rebuild P_l, D_{l+1} and the Galerkin products below (down to the first
+ * level not built yet).  Finer levels must be built.  Once every level has
+ * been built (by wcmg_setup, a checkpoint import or these calls) the context
+ * accepts cycles and solves. */
 int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v);
 
 /* Setup checkpoint (Sec. 2.1: a setup serves many solves, and more setup

@@ -191,6 +191,10 @@ int wcmg_rebuild_from_vectors(wcmg_ctx* ctx, int level, const void* v) {
     level_vectors_in(c, level, (const cd64*)v, c.tr[level].vecs64.as<cd64>(), c.tr[level].nv);
     c.rebuild(level);
     c.regalerkin_below(level);
+    // a hierarchy whose every level has been built from given vectors is ready to cycle and solve
+    bool all = true;
+    for (int l = 0; l + 1 < c.nlev; ++l) all = all && c.tr[l].built;
+    if (all) c.setup_done = true;
   });
 }
 

@@ -932,7 +932,8 @@ void Context::galerkin(int l) {
 }
 
 void Context::regalerkin_below(int l) {
-  for (int k = l + 1; k + 1 < nlev; ++k) galerkin(k);
+  // down to the first level whose prolongator has not been built yet
+  for (int k = l + 1; k + 1 < nlev && tr[k].built; ++k) galerkin(k);
 }
 
 // Initial setup (Sec. 2.1): iterate the smoother on random vectors.  Reading:

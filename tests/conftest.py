@@ -26,3 +26,19 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture
+def measured(request):
+    """Record a measured value (an error, an iteration count) of a test: when
+    WCMG_MEASURED names a file, one JSON line per value is appended to it."""
+    import json
+
+    path = os.environ.get("WCMG_MEASURED")
+
+    def record(name, value):
+        if path:
+            with open(path, "a") as f:
+                f.write(json.dumps({"test": request.node.nodeid, "name": name, "value": value}) + "\n")
+
+    return record

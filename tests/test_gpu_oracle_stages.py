@@ -135,7 +135,7 @@ def test_three_level_kcycle_solve_iterations_match_oracle():
 # ---------------------------------------------------------------- the FP32 preconditioner of the benchmark
 @pytest.mark.parametrize("L,store", [((8, 8, 8, 8), "f32"), ((8, 8, 8, 8), "bf16"), ((16, 16, 16, 32), "f32"),
                                      ((16, 16, 16, 32), "bf16")])
-def test_fp32_cycle_matches_oracle(L, store):
+def test_fp32_cycle_matches_oracle(L, store, measured):
     """The mixed-precision cycle (FP32 restriction, cooperative coarsest GMRES
     with fixed iterations, FP32 prolongation, FP32 MR post-smoothing whose
     step length is summed from the Dslash's partials, FP64 output) against the
@@ -162,12 +162,15 @@ def test_fp32_cycle_matches_oracle(L, store):
         cfg = dict(CFG, coarse_fixed_iters=10)
         ref = v_cycle(_with_coarse(lv, 1, bf16_round(lv.Dc[1])), 0, r.reshape(-1), cfg)
     err = rel(got, ref)
+    measured("cycle_rel_err", err)
     assert err < 1e-5, err
-    if store == "bf16":  # the BF16 storage error itself is far larger than the bar
-        assert rel(got, H.cycle(0, r)) > 1e-4
+    if store == "bf16":  # the composition with the rounded blocks explains the BF16 storage error
+        e64 = rel(got, H.cycle(0, r))
+        measured("cycle_rel_err_vs_unrounded_blocks", e64)
+        assert err < 0.25 * e64, (err, e64)
 
 
-def test_fp32_setup_relaxation_matches_oracle():
+def test_fp32_setup_relaxation_matches_oracle(measured):
     """setup_prec = F32: 20 FP32 MR sweeps per vector on D x = 0, then FP64
     Gram-Schmidt and Galerkin.  Measured differences from the FP64 oracle are
     ~2e-5 (vectors) after 20 sweeps: each sweep adds FP32 rounding (6e-8 x
@@ -183,10 +186,11 @@ def test_fp32_setup_relaxation_matches_oracle():
     ev = rel(host(ctx.null_vectors(0)), H.vectors(0))
     ep = rel(host(ctx.prolongator(0)), H.P(0))
     ec = rel(host(ctx.coarse_op(1)), H.coarse(1))
+    measured("vectors_P_Dc_rel_err", [ev, ep, ec])
     assert ev < 2e-4 and ep < 2e-4 and ec < 2e-4, (ev, ep, ec)
 
 
-def test_mixed_solve_with_refinement_iterations_match_oracle():
+def test_mixed_solve_with_refinement_iterations_match_oracle(measured):
     """The benchmark's method on 8^4 (4^4 aggregates, Nv = 12): FP32 setup
     relaxation + 1 refinement iteration, FP32 cycle with FP32 blocks, FP64
     FGMRES(20) to 1e-10, against the oracle's all-FP64 solve: outer iteration
@@ -205,6 +209,7 @@ def test_mixed_solve_with_refinement_iterations_match_oracle():
     x, info, st = ctx.solve(dev(b))
     xo, ito, rro, sto = H.solve(b)
     assert st == 0 and sto == 0 and info[0]["true_rel_res"] <= 1e-10 and rro <= 1e-10
+    measured("outer_iters_gpu_oracle", [info[0]["outer_iters"], ito])
     assert abs(info[0]["outer_iters"] - ito) <= 1, (info[0]["outer_iters"], ito)
     assert rel(host(x), xo) < 1e-8
 
