@@ -378,6 +378,22 @@ int wcmg_coarse_set(wcmg_coarse* op, const void* blocks, int src_prec);
  * right-hand sides the product runs on the matrix cores (each site and
  * direction is a complex [Nb x Nb] x [Nb x nrhs] GEMM), up to 16 per launch. */
 int wcmg_coarse_apply(wcmg_coarse* op, const void* in, void* out, int nrhs);
+/* wcmg_coarse_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, but no
+ * device allocation and no hipFree on any call.  Where the kernel needs a
+ * scratch buffer (the scatter buffer of the five-point owner-computes apply,
+ * kernel 3 on large lattices: 4 * nrhs * Vc * Nb complex values of the
+ * storage's vector type) it uses a library-owned 64 MiB device array, one
+ * per GPU, held until the process ends (its address is looked up on the
+ * first call on a device).  WCMG_ERR_ARG when the scratch would exceed
+ * 64 MiB (use fewer right-hand sides per call); WCMG_ERR_STATE when the
+ * blocks of the chosen kernel's layout are not set.  Every call on a GPU
+ * shares that GPU's scratch, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race; calls on one stream are ordered and
+ * safe.  Nothing in the scratch needs clearing: each call writes every entry
+ * it reads. */
+int wcmg_coarse_apply_noalloc(wcmg_coarse* op, const void* in, void* out, int nrhs);
 /* Kernel choice for wcmg_coarse_apply: 0 automatic (matrix cores from 4
  * right-hand sides on), 1 per-row vector kernel, 2 matrix cores (FP32/BF16
  * storage, Nb in {8, 16, 24, 32, 40}), 3 per-row kernel on five-point

@@ -3,6 +3,8 @@
 // the message for wcmg_last_error.
 #include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "engine.h"
 
@@ -808,6 +810,30 @@ int wcmg_profile_stats(wcmg_ctx* ctx, const char* family, int64_t* launches, dou
 }  // extern "C"
 
 // ---------------------------------------------------------------- standalone coarse operator
+namespace {
+// Scratch of wcmg_coarse_apply_noalloc: the five-point scatter buffer in a
+// file-scope device array, one copy per GPU, held until the process ends.  In
+// host code `scratch` is only a stand-in for the symbol; its device address
+// comes from hipGetSymbolAddress, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of that device's `scratch`
+
+void* scratch_address() {
+  int dev = 0;
+  WCMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  WCMG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  require(ptr != nullptr, WCMG_ERR_HIP, "no device address for the no-allocation scratch");
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+}  // namespace
+
 struct wcmg_coarse {
   CoarseOp op;
   int store = WCMG_F32;
@@ -886,6 +912,13 @@ int wcmg_coarse_apply(wcmg_coarse* h, const void* in, void* out, int nrhs) {
   return guarded_c(h, [&](wcmg_coarse& o) {
     require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
     o.op.apply_batch(o.store, in, out, nrhs, o.kernel, nullptr, 0, o.stream);
+  });
+}
+
+int wcmg_coarse_apply_noalloc(wcmg_coarse* h, const void* in, void* out, int nrhs) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
+    o.op.apply_batch_scratch(o.store, in, out, nrhs, o.kernel, scratch_address(), kNoAllocScratchBytes, o.stream);
   });
 }
 

@@ -89,6 +89,10 @@ struct CoarseOp {
                    hipStream_t st);
   void apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run, hipStream_t st,
              int run_stride = 0);
+  // apply_batch without any device allocation: the five-point scatter buffer is
+  // the caller's `scratch` (scratch_bytes long); every layout must already be built
+  void apply_batch_scratch(int prec, const void* in, void* out, int nrhs, int kernel, void* scratch,
+                           size_t scratch_bytes, hipStream_t st);
 };
 
 // B independent (F)GMRES solves advancing through shared launches.  Basis

@@ -149,6 +149,28 @@ void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int ke
   }
 }
 
+void CoarseOp::apply_batch_scratch(int prec, const void* in, void* out, int nrhs, int kernel, void* scratch,
+                                   size_t scratch_bytes, hipStream_t st) {
+  const bool can_mfma = prec != WCMG_F64 && mfma_supported_nb(nb);
+  const bool use_mfma = can_mfma && (kernel == 2 || (kernel == 0 && nrhs >= 4));
+  if (!use_mfma && fresh5[prec]) {
+    void* tmp = nullptr;
+    if (coarse5_uses_owner(V, nb, nrhs)) {
+      const size_t need = 4 * (size_t)nrhs * V * nb * cbytes(prec);
+      require(need <= scratch_bytes, WCMG_ERR_ARG,
+              "five-point apply of " + std::to_string(nrhs) + " fields needs " + std::to_string(need) +
+                  " bytes of scratch; the no-allocation buffer holds " + std::to_string(scratch_bytes));
+      tmp = scratch;
+    }
+    launch_coarse_apply5(prec, dev5[prec].p, in, out, tmp, nbr.as<int>(), V, nb, 0, nrhs, nullptr, st, 0);
+    return;
+  }
+  // the other kernels use no scratch; with their layout built they allocate nothing
+  require(use_mfma ? mfma_fresh[prec] : fresh[prec], WCMG_ERR_STATE,
+          "coarse operator not built in the requested precision");
+  apply_batch(prec, in, out, nrhs, kernel, nullptr, 0, st);
+}
+
 void CoarseOp::apply(int prec, const void* in, void* out, int dmask, int accumulate, int nrhs, const int* run,
                      hipStream_t st, int run_stride) {
   require(built(prec), WCMG_ERR_STATE, "coarse operator not built in the requested precision");

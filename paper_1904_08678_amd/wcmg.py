@@ -114,6 +114,7 @@ def lib():
         l.wcmg_coarse_destroy.argtypes = [vp]
         l.wcmg_coarse_set.argtypes = [vp, vp, ip]
         l.wcmg_coarse_apply.argtypes = [vp, vp, vp, ip]
+        l.wcmg_coarse_apply_noalloc.argtypes = [vp, vp, vp, ip]
         l.wcmg_coarse_set_kernel.argtypes = [vp, ip]
         l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
         l.wcmg_coarse_last_error.argtypes = [vp]
@@ -500,6 +501,13 @@ class CoarseOperator:
         nrhs = x.numel() // (self.Vc * self.nb)
         out = torch.empty_like(x) if out is None else out
         self._chk(lib().wcmg_coarse_apply(self.h, _ptr(x), _ptr(out), nrhs))
+        return out
+
+    def apply_noalloc(self, x: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """wcmg_coarse_apply_noalloc: out = D_c x with no device allocation
+        (out is the caller's)."""
+        nrhs = x.numel() // (self.Vc * self.nb)
+        self._chk(lib().wcmg_coarse_apply_noalloc(self.h, _ptr(x), _ptr(out), nrhs))
         return out
 
     def time(self, x: torch.Tensor, out: torch.Tensor, reps=20) -> float:
