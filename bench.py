@@ -574,7 +574,7 @@ def kernel_mode(args):
     L = wl["L"]
     V = int(np.prod(L))
     U, start, b = make_inputs(wl)
-    ctx = make_context(w, wl, mixed=True)
+    ctx = make_context(w, wl, mixed=True, reserved=args.reserved)
     ctx.set_gauge(torch.from_numpy(U).cuda())
     nr = max(1, args.nrhs)
     if fam in ("dslash_f32", "dslash_f64"):
@@ -619,6 +619,7 @@ def main():
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, three_level")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--reserved", type=int, default=0, help="kernel mode: reserved[0] flags (reference forms)")
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
     ap.add_argument("--coarse-points", type=int, default=9, choices=(5, 9),
                     help="coarse blocks stored per site: 9, or 5 (Mdiag and forward hops)")

@@ -153,6 +153,65 @@ __device__ inline bool item_rhs(long n_items, int nrhs, long* item, long* rhs) {
 }
 inline unsigned item_rhs_grid(long n_items, int nrhs) { return (unsigned)((n_items * nrhs + 7) / 8 * 8); }
 
+// Division of 32-bit unsigned n < 2^31 by an invariant d >= 1 with a
+// multiply-high and a shift (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994): l = ceil(log2 d),
+// m = floor(2^(32+l) / d) - 2^32 + 1, q = (mulhi(n, m) + n) >> l.
+struct FastDiv {
+  uint32_t d = 1, m = 1, l = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t dv) : d(dv) {
+    l = 0;
+    while ((1ull << l) < dv) ++l;
+    m = (uint32_t)((((uint64_t)1 << (32 + l)) / dv) - ((uint64_t)1 << 32) + 1);
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const {
+    const uint32_t hi = (uint32_t)(((uint64_t)n * m) >> 32);  // a multiply-high on the GPU
+    return (uint32_t)(((uint64_t)hi + n) >> l);
+  }
+  __host__ __device__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
+// Device site order of level 0 as arithmetic: s = c * A + o, c the aggregate
+// (lexicographic over the coarse extents Lc) and o the offset inside it
+// (lexicographic over the block b), x fastest in both.  Neighbours follow from
+// the coordinates without a table: a hop stays inside the aggregate unless it
+// leaves through a face, then it enters the neighbouring aggregate (periodic
+// over the coarse lattice) on the opposite face.
+struct SiteGeom {
+  FastDiv divA, div_so[4], mod_b[4], div_sc[4], mod_Lc[4];
+  uint32_t A = 1, so[4] = {1, 1, 1, 1}, sc[4] = {1, 1, 1, 1}, b[4] = {1, 1, 1, 1}, Lc[4] = {1, 1, 1, 1};
+  SiteGeom() = default;
+  SiteGeom(const int L[4], const int blk[4]) {
+    A = 1;
+    uint32_t cs = 1;
+    for (int m = 0; m < 4; ++m) {
+      b[m] = (uint32_t)blk[m];
+      Lc[m] = (uint32_t)(L[m] / blk[m]);
+      so[m] = A;
+      sc[m] = cs;
+      A *= b[m];
+      cs *= Lc[m];
+    }
+    divA = FastDiv(A);
+    for (int m = 0; m < 4; ++m) {
+      div_so[m] = FastDiv(so[m]);
+      mod_b[m] = FastDiv(b[m]);
+      div_sc[m] = FastDiv(sc[m]);
+      mod_Lc[m] = FastDiv(Lc[m]);
+    }
+  }
+  // the neighbours of site s in directions +mu and -mu
+  template <int MU>
+  __host__ __device__ void hop_sites(uint32_t s, uint32_t& fwd, uint32_t& bwd) const {
+    const uint32_t c = divA.div(s), o = s - c * A;
+    const uint32_t om = mod_b[MU].mod(div_so[MU].div(o)), cm = mod_Lc[MU].mod(div_sc[MU].div(c));
+    const uint32_t cstep = sc[MU] * A, cwrap = (Lc[MU] - 1) * cstep, owrap = (b[MU] - 1) * so[MU];
+    fwd = om + 1 < b[MU] ? s + so[MU] : (cm + 1 < Lc[MU] ? s + cstep : s - cwrap) - owrap;
+    bwd = om > 0 ? s - so[MU] : (cm > 0 ? s - cstep : s + cwrap) + owrap;
+  }
+};
+
 // Site geometry of one level as the kernels see it.
 //   layout SoA (level 0): element (site s, component k) at k * V + s
 //   layout AoS (levels >= 1): element at s * ns + k

@@ -186,6 +186,9 @@ struct Context {
   DevBuf perm0;                 // int32 device site -> lexicographic
   DevBuf U_lex, clover_lex;     // canonical copies (FP64)
   DevBuf U64, U32, clov64, clov32;
+  SiteGeom sgeo;  // the level-0 device site order as arithmetic (Dslash neighbours)
+  // neighbours of the fine Dslash: site arithmetic, or the table (reserved[0] flag 32, the reference form)
+  const SiteGeom* dslash_geo() const { return (p.reserved[0] & 32) ? nullptr : &sgeo; }
   bool gauge_set = false, setup_done = false;
   // even-odd preconditioning: site parity (device order) and A^{-1} (packed)
   DevBuf par0, clovinv64, clovinv32;

@@ -261,6 +261,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
       for (long s = 0; s < G.V; ++s) nb_host[(d - 1) * G.V + s] = iperm[lex_neighbour(G.perm[s], G.L, d)];
     upload(G.nbr, nb_host);
     upload(perm0, G.perm);
+    sgeo = SiteGeom(G.L, b);
   }
   for (int l = 1; l < nlev; ++l) {
     LevelGeom& G = geo[l];
@@ -378,10 +379,10 @@ void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const i
     prof.begin_kernel(fam);
     if (single)
       launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
-                           geo[0].V, terms, nrhs, run, stream, dots);
+                           geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo());
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                            geo[0].V, terms, nrhs, run, stream, dots);
+                            geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo());
     prof.end(fam, stream);
   } else {
     const int prec = store_prec_for(l, single);
@@ -400,10 +401,10 @@ void Context::residual0(const cplx<R>* b, const cplx<R>* x, cplx<R>* r, const in
   prof.begin_kernel(fam);
   if (single)
     launch_wilson<float>((const cf32*)x, (cf32*)r, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V,
-                         0x1ff, 1, run, stream, nullptr, 0, (const cf32*)b);
+                         0x1ff, 1, run, stream, nullptr, 0, (const cf32*)b, dslash_geo());
   else
     launch_wilson<double>((const cd64*)x, (cd64*)r, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                          geo[0].V, 0x1ff, 1, run, stream, nullptr, 0, (const cd64*)b);
+                          geo[0].V, 0x1ff, 1, run, stream, nullptr, 0, (const cd64*)b, dslash_geo());
   prof.end(fam, stream);
 }
 

@@ -21,10 +21,11 @@ void launch_pack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, 
 template <typename Ti, typename To>
 void launch_unpack_fermion(const cplx<Ti>* in, const int* perm, long V, int nrhs, cplx<To>* out, hipStream_t st);
 template <typename R>
-// bsub != nullptr (whole operator, no dots): out = bsub - D in.
+// bsub != nullptr (whole operator, no dots): out = bsub - D in.  geo != nullptr:
+// neighbours from the site arithmetic of the level-0 device order instead of nbr.
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0,
-                   const cplx<R>* bsub = nullptr);
+                   const cplx<R>* bsub = nullptr, const SiteGeom* geo = nullptr);
 int wilson_blocks(long V);
 // FP32 D on nrhs fields with the links and clover read once per launch; MR
 // partials (optional) at dots[2 * (r * wilson_blocks(V) + blk)]

@@ -248,12 +248,31 @@ __global__ void k_unpack_fermion(const cplx<Ti>* __restrict__ in, const int* __r
 // chirality and form the products with the input components they loaded for
 // the clover block.  bsub != nullptr (without dots): out = bsub - D in, the
 // residual of in for the right-hand side bsub.
-template <typename R, bool ALL>
+// The two hops along MU (selected by the terms mask unless ALL), neighbours
+// from the site arithmetic (GEO) or from the table.
+template <typename R, int MU, bool GEO, bool ALL>
+__device__ inline void hops_mu(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                               const int* __restrict__ nbr, const SiteGeom& geo, long V, long s, int terms) {
+  long yf, yb;
+  if constexpr (GEO) {
+    uint32_t f, b;
+    geo.hop_sites<MU>((uint32_t)s, f, b);
+    yf = f;
+    yb = b;
+  } else {
+    yf = nbr[(long)(2 * MU) * V + s];
+    yb = nbr[(long)(2 * MU + 1) * V + s];
+  }
+  if (ALL || (terms & (1 << (2 * MU + 1)))) hop_at<R, MU, true>(acc, in, U, V, s, yf);
+  if (ALL || (terms & (1 << (2 * MU + 2)))) hop_at<R, MU, false>(acc, in, U, V, s, yb);
+}
+
+template <typename R, bool ALL, bool GEO>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
-                                                 const int* __restrict__ nbr, long V, int terms, int nrhs,
-                                                 cd64* __restrict__ dots, const int* __restrict__ run, int rs,
-                                                 const cplx<R>* __restrict__ bsub) {
+                                                 const int* __restrict__ nbr, SiteGeom geo, long V, int terms,
+                                                 int nrhs, cd64* __restrict__ dots, const int* __restrict__ run,
+                                                 int rs, const cplx<R>* __restrict__ bsub) {
   const long nblk = (V + 63) / 64;
   long blk, r;
   if (!item_rhs(nblk, nrhs, &blk, &r)) return;
@@ -278,39 +297,14 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
 #pragma unroll
       for (int k = 0; k < 6; ++k) pin[k] = in[(long)(mu * 6 + k) * V + s];
     }
-    if (ALL) {
-      if (mu == 0) {
-        clover_chirality_p<R, 0>(acc, pin, clov, V, s);
-        hop<R, 0, true>(acc, in, U, nbr, V, s);
-        hop<R, 0, false>(acc, in, U, nbr, V, s);
-      } else if (mu == 1) {
-        clover_chirality_p<R, 1>(acc, pin, clov, V, s);
-        hop<R, 1, true>(acc, in, U, nbr, V, s);
-        hop<R, 1, false>(acc, in, U, nbr, V, s);
-      } else if (mu == 2) {
-        hop<R, 2, true>(acc, in, U, nbr, V, s);
-        hop<R, 2, false>(acc, in, U, nbr, V, s);
-      } else {
-        hop<R, 3, true>(acc, in, U, nbr, V, s);
-        hop<R, 3, false>(acc, in, U, nbr, V, s);
-      }
-    } else {
-      if ((terms & 1) && mu == 0) clover_chirality_p<R, 0>(acc, pin, clov, V, s);
-      if ((terms & 1) && mu == 1) clover_chirality_p<R, 1>(acc, pin, clov, V, s);
-      if (mu == 0) {
-        if (terms & (1 << 1)) hop<R, 0, true>(acc, in, U, nbr, V, s);
-        if (terms & (1 << 2)) hop<R, 0, false>(acc, in, U, nbr, V, s);
-      } else if (mu == 1) {
-        if (terms & (1 << 3)) hop<R, 1, true>(acc, in, U, nbr, V, s);
-        if (terms & (1 << 4)) hop<R, 1, false>(acc, in, U, nbr, V, s);
-      } else if (mu == 2) {
-        if (terms & (1 << 5)) hop<R, 2, true>(acc, in, U, nbr, V, s);
-        if (terms & (1 << 6)) hop<R, 2, false>(acc, in, U, nbr, V, s);
-      } else {
-        if (terms & (1 << 7)) hop<R, 3, true>(acc, in, U, nbr, V, s);
-        if (terms & (1 << 8)) hop<R, 3, false>(acc, in, U, nbr, V, s);
-      }
+    if (ALL || (terms & 1)) {
+      if (mu == 0) clover_chirality_p<R, 0>(acc, pin, clov, V, s);
+      if (mu == 1) clover_chirality_p<R, 1>(acc, pin, clov, V, s);
     }
+    if (mu == 0) hops_mu<R, 0, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
+    else if (mu == 1) hops_mu<R, 1, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
+    else if (mu == 2) hops_mu<R, 2, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
+    else hops_mu<R, 3, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
@@ -560,22 +554,35 @@ INST_PACK(double, float)
 INST_PACK(float, float)
 INST_PACK(float, double)
 
+template <typename R, bool ALL>
+static void launch_wilson_t(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr,
+                            const SiteGeom* geo, long V, int terms, int nrhs, const int* run, hipStream_t st,
+                            cd64* dots, int rs, const cplx<R>* bsub) {
+  const dim3 grid(item_rhs_grid(nblocks(V, 64), nrhs));
+  if (geo)
+    WCMG_LAUNCH((k_wilson<R, ALL, true>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, *geo, V, terms, nrhs,
+                dots, run, rs, bsub);
+  else
+    WCMG_LAUNCH((k_wilson<R, ALL, false>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, SiteGeom(), V, terms,
+                nrhs, dots, run, rs, bsub);
+}
+
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
-                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs, const cplx<R>* bsub) {
+                   int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs, const cplx<R>* bsub,
+                   const SiteGeom* geo) {
   require(!bsub || (!dots && terms == 0x1ff), WCMG_ERR_ARG, "Dslash: the residual form takes the whole operator");
+  require(!geo || V < (1L << 31), WCMG_ERR_DIMS, "Dslash: lattice too large for 32-bit site arithmetic");
   if (terms == 0x1ff)
-    WCMG_LAUNCH((k_wilson<R, true>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
-                nbr, V, terms, nrhs, dots, run, rs, bsub);
+    launch_wilson_t<R, true>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub);
   else
-    WCMG_LAUNCH((k_wilson<R, false>), dim3(item_rhs_grid(nblocks(V, 64), nrhs)), dim3(kBlock), 0, st, in, out, U, clov,
-                nbr, V, terms, nrhs, dots, run, rs, bsub);
+    launch_wilson_t<R, false>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
-                                    const int*, hipStream_t, cd64*, int, const cd64*);
+                                    const int*, hipStream_t, cd64*, int, const cd64*, const SiteGeom*);
 template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
-                                   const int*, hipStream_t, cd64*, int, const cf32*);
+                                   const int*, hipStream_t, cd64*, int, const cf32*, const SiteGeom*);
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 

@@ -83,10 +83,10 @@ __device__ inline void hop_core(cplx<R> (&acc)[12], const cplx<R> (&p)[12], cons
   reconstruct_add<R, MU, FWD>(acc, g);
 }
 
+// The hop along (MU, FWD) from the neighbour site y of s.
 template <typename R, int MU, bool FWD>
-__device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
-                           const int* __restrict__ nbr, long V, long s) {
-  const long y = nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s];
+__device__ inline void hop_at(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                              long V, long s, long y) {
   cplx<R> p[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) p[k] = in[(long)k * V + y];
@@ -95,6 +95,12 @@ __device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, c
 #pragma unroll
   for (int e = 0; e < 9; ++e) u[e] = U[(long)(MU * 9 + e) * V + ls];
   hop_core<R, MU, FWD>(acc, p, u);
+}
+
+template <typename R, int MU, bool FWD>
+__device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
+                           const int* __restrict__ nbr, long V, long s) {
+  hop_at<R, MU, FWD>(acc, in, U, V, s, nbr[(long)(2 * MU + (FWD ? 0 : 1)) * V + s]);
 }
 
 // acc[chi*6 .. chi*6+5] += (block chi of (4 + m0) + C) p, block given by its
