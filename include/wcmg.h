@@ -250,6 +250,28 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
 #define WCMG_BATCH_DSLASH_PER_RHS 8
 int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flags, wcmg_solve_info* info);
 
+/* Ragged batched solve: nprob problems, each on its own context (its own
+ * lattice, gauge field, hierarchy and tolerances), problem k solving
+ * nrhs[k] right-hand sides b[k] -> x[k] (complex128 [nrhs[k]][V_k][4][3],
+ * device, x[k] holding the initial guesses), solved together.  Each problem
+ * runs the method of wcmg_solve_batched (one FP64 FGMRES per right-hand side
+ * preconditioned by the two-level cycle, Sec. 2.1); the problems advance in
+ * lock-step so that the coarse-grid GMRES of all of them is one batch whose
+ * coarse-operator applies (Mdiag + Mdir, Sec. 2.1) are ONE matrix-core launch
+ * over the sum of their coarse sites per Arnoldi step.  Results equal each
+ * problem's own batched solve up to rounding order.  Requirements
+ * (WCMG_ERR_ARG otherwise): 1..8 problems, 1..16 right-hand sides each,
+ * every context set up (WCMG_ERR_STATE otherwise), two levels, FP32 cycle,
+ * the same coarse block size Nb in {8,16,24,32,40} and the same coarse
+ * storage (FP32 or BF16), the same outer_restart and coarse_restart, the
+ * same stream, no even-odd outer solve, no context twice.  info: host array of
+ * sum(nrhs) entries in problem order (may be NULL); t_solve_s is the whole
+ * ragged solve's wall time, cycles the number of shared coarse-operator
+ * launches.  WCMG_ERR_NOCONV / WCMG_ERR_NAN as wcmg_solve (x is written);
+ * messages through wcmg_last_error(ctxs[0]). */
+int wcmg_solve_ragged(wcmg_ctx* const* ctxs, int nprob, const void* const* b, void* const* x, const int* nrhs,
+                      wcmg_solve_info* info);
+
 /* ---------------------------------------------------------------------------
  * Learned near-null proposal (a setup accelerator; not part of the paper's
  * method).  A gauge-covariant network of three parallel-transport convolution

@@ -7,5 +7,5 @@ built library every call raises.
 """
 from .wcmg import (  # noqa: F401
     F64, F32, BF16, Context, CoarseOperator, Network, WcmgError, coarse_apply_ragged, coarse_time_ragged,
-    default_params, lib, library_path,
+    default_params, lib, library_path, solve_ragged, close_all,
 )

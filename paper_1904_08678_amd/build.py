@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwcmg.so")
-SOURCES = ["wilson.hip", "coarse.hip", "coarse5.hip", "sap.hip", "evenodd.hip", "coarse_gmres.hip", "coarse_persist.hip", "coarse_mfma.hip", "transfer.hip", "blas.hip", "blas_batch.hip", "engine_batch.hip", "nn.hip", "nn_engine.hip", "engine.hip", "capi.hip"]
+SOURCES = ["wilson.hip", "coarse.hip", "coarse5.hip", "sap.hip", "evenodd.hip", "coarse_gmres.hip", "coarse_persist.hip", "coarse_mfma.hip", "transfer.hip", "blas.hip", "blas_batch.hip", "engine_batch.hip", "engine_ragged.hip", "nn.hip", "nn_engine.hip", "engine.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -641,6 +641,97 @@ int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flag
   return status;
 }
 
+int wcmg_solve_ragged(wcmg_ctx* const* ctxs, int nprob, const void* const* b, void* const* x, const int* nrhs,
+                      wcmg_solve_info* info) {
+  if (!ctxs || nprob < 1 || !ctxs[0] || !ctxs[0]->c) return WCMG_ERR_ARG;
+  int status = WCMG_OK;
+  int rc = guarded(ctxs[0], [&](Context& c0) {
+    require(nprob <= kRaggedMax, WCMG_ERR_ARG, "ragged solve: 1..8 problems");
+    require(b && x && nrhs, WCMG_ERR_ARG, "ragged solve: null argument");
+    std::vector<Context*> cs(nprob);
+    for (int k = 0; k < nprob; ++k) {
+      require(ctxs[k] && ctxs[k]->c, WCMG_ERR_ARG, "ragged solve: null context");
+      Context& c = *ctxs[k]->c;
+      cs[k] = &c;
+      require(b[k] && x[k] && nrhs[k] >= 1 && nrhs[k] <= 16, WCMG_ERR_ARG,
+              "ragged solve: every problem needs fields and 1..16 right-hand sides");
+      require(c.gauge_set && c.setup_done, WCMG_ERR_STATE, "ragged solve: run wcmg_setup on every context first");
+      require(c.nlev == 2 && c.p.cycle_prec == WCMG_F32, WCMG_ERR_ARG,
+              "ragged solve: two-level hierarchies with an FP32 cycle");
+      require(c.p.even_odd == 0, WCMG_ERR_ARG, "ragged solve: no even-odd outer solve");
+      const int prec = c.store_prec_for(1, true);
+      require(mfma_supported_nb(c.cop[0]->nb), WCMG_ERR_ARG, "ragged solve: Nb in {8,16,24,32,40}");
+      require(c.cop[0]->nb == c0.cop[0]->nb && prec == c0.store_prec_for(1, true), WCMG_ERR_ARG,
+              "ragged solve: every problem needs the same Nb and coarse storage precision");
+      require(c.p.outer_restart == c0.p.outer_restart && c.p.coarse_restart == c0.p.coarse_restart, WCMG_ERR_ARG,
+              "ragged solve: every problem needs the same outer and coarse restart lengths");
+      require(c.stream == c0.stream, WCMG_ERR_ARG, "ragged solve: every context must use the same stream");
+      for (int j = 0; j < k; ++j) require(cs[j] != &c, WCMG_ERR_ARG, "ragged solve: a context appears twice");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<const cd64*> b64(nprob);
+    std::vector<cd64*> x64(nprob);
+    std::vector<int> Bs(nprob);
+    for (int k = 0; k < nprob; ++k) {
+      Context& c = *cs[k];
+      const long V = c.geo[0].V, nn = c.n(0);
+      Bs[k] = nrhs[k];
+      cd64* bb = c.buf<cd64>("rsolve_b", Bs[k] * nn);
+      x64[k] = c.buf<cd64>("rsolve_x", Bs[k] * nn);
+      launch_pack_fermion<double, double>((const cd64*)b[k], c.perm0.as<int>(), V, Bs[k], bb, c.stream);
+      launch_pack_fermion<double, double>((const cd64*)x[k], c.perm0.as<int>(), V, Bs[k], x64[k], c.stream);
+      b64[k] = bb;
+    }
+    std::vector<std::vector<int>> its(nprob);
+    for (int k = 0; k < nprob; ++k) its[k].assign(Bs[k], 0);
+    int64_t launches = 0;
+    solve_ragged(cs, b64, x64, Bs, its, &launches);
+    // true residuals in FP64, per problem
+    std::vector<std::vector<cd64>> hn(nprob);
+    for (int k = 0; k < nprob; ++k) {
+      Context& c = *cs[k];
+      const long V = c.geo[0].V, nn = c.n(0);
+      const int B = Bs[k];
+      cd64* r64 = c.buf<cd64>("rsolve_r", B * nn);
+      cd64* nrm = c.buf<cd64>("rsolve_n", 2L * B);
+      c.apply_opB<double>(0, x64[k], r64, B, nullptr, 0);
+      launch_belem<cd64, cd64>(r64, nn, b64[k], nn, r64, nn, nullptr, 0, nn, B, 2, nullptr, 0, c.stream);
+      launch_bdot<double>(r64, 0, nn, 1, r64, nn, nn, B, c.bpart.as<cd64>(), nrm, 1, 2, 0, nullptr, 0, c.stream);
+      launch_bdot<double>(b64[k], 0, nn, 1, b64[k], nn, nn, B, c.bpart.as<cd64>(), nrm + 1, 1, 2, 0, nullptr, 0,
+                          c.stream);
+      hn[k].resize(2 * B);
+      WCMG_HIP(hipMemcpyAsync(hn[k].data(), nrm, 2 * B * sizeof(cd64), hipMemcpyDeviceToHost, c.stream));
+      launch_unpack_fermion<double, double>(x64[k], c.perm0.as<int>(), V, B, (cd64*)x[k], c.stream);
+    }
+    c0.sync();
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int slot = 0;
+    for (int k = 0; k < nprob; ++k) {
+      Context& c = *cs[k];
+      c.timers[5] = dt;
+      for (int r = 0; r < Bs[k]; ++r, ++slot) {
+        const double rr = hn[k][2 * r].re, bb = hn[k][2 * r + 1].re;
+        const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        const bool conv = rel <= c.p.outer_tol;
+        if (!(rel == rel)) status = WCMG_ERR_NAN;
+        else if (!conv && status == WCMG_OK) status = WCMG_ERR_NOCONV;
+        if (info) {
+          wcmg_solve_info& I = info[slot];
+          I.outer_iters = its[k][r];
+          I.converged = conv ? 1 : 0;
+          I.true_rel_res = rel;
+          I.t_solve_s = dt;
+          I.coarse_iters = c.coarse_iters;
+          I.cycles = launches;  // shared coarse-operator launches of the whole ragged solve
+        }
+      }
+    }
+  });
+  if (rc != WCMG_OK) return rc;
+  if (status != WCMG_OK) ctxs[0]->err = status == WCMG_ERR_NAN ? "NaN in residual" : "solver did not converge";
+  return status;
+}
+
 }  // extern "C"
 
 struct wcmg_nn {
@@ -952,7 +1043,7 @@ static RaggedTable ragged_table(wcmg_coarse* const* ops, int nprob, const void* 
     require(in[p] && out[p], WCMG_ERR_ARG, "ragged batch: null field");
     require(o.op.mfma_fresh[o.store], WCMG_ERR_STATE, "ragged batch: operator blocks not set");
     t.p[p] = RaggedProblem{o.op.mfma[o.store].p, (const cf32*)in[p], (cf32*)out[p], o.op.nbr.as<int>(), o.op.V,
-                           nrhs[p]};
+                           nrhs[p], nullptr, 0};
   }
   return t;
 }

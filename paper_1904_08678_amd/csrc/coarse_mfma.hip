@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma_ragged(RaggedTable t)
   int p = 0;
   while (p + 1 < t.n && g >= t.site0[p + 1]) ++p;
   const RaggedProblem& q = t.p[p];
-  mfma_site<P, NB>((const typename MfmaChunk<P>::T*)q.blk, q.in, q.out, q.nbr, q.Vc, q.nrhs, nullptr, 0,
+  mfma_site<P, NB>((const typename MfmaChunk<P>::T*)q.blk, q.in, q.out, q.nbr, q.Vc, q.nrhs, q.run, q.rs,
                    g - t.site0[p]);
 }
 
@@ -288,11 +288,11 @@ template <int P>
 static void mfma_ragged_nb(const RaggedTable& t, long total, hipStream_t st) {
   const dim3 g((unsigned)((total + 3) / 4)), b(kBlock);
   switch (t.nb) {
-    case 8: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 8>), g, b, 0, st, t); break;
-    case 16: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 16>), g, b, 0, st, t); break;
-    case 24: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 24>), g, b, 0, st, t); break;
-    case 32: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 32>), g, b, 0, st, t); break;
-    default: hipLaunchKernelGGL((k_coarse_apply_mfma_ragged<P, 40>), g, b, 0, st, t); break;
+    case 8: WCMG_LAUNCH((k_coarse_apply_mfma_ragged<P, 8>), g, b, 0, st, t); break;
+    case 16: WCMG_LAUNCH((k_coarse_apply_mfma_ragged<P, 16>), g, b, 0, st, t); break;
+    case 24: WCMG_LAUNCH((k_coarse_apply_mfma_ragged<P, 24>), g, b, 0, st, t); break;
+    case 32: WCMG_LAUNCH((k_coarse_apply_mfma_ragged<P, 32>), g, b, 0, st, t); break;
+    default: WCMG_LAUNCH((k_coarse_apply_mfma_ragged<P, 40>), g, b, 0, st, t); break;
   }
 }
 

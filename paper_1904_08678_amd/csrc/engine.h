@@ -314,4 +314,13 @@ struct Context {
   void solve_batched(const cd64* b, cd64* x, int B, int* iters);
 };
 
+// Ragged batched solve (engine_ragged.hip): problem k solves B[k] right-hand
+// sides b[k] -> x[k] (device-order FP64 fields) on context cs[k]; the coarse
+// solves of all problems share one coarse-operator launch per Arnoldi step.
+// iters[k][r]: outer iterations; coarse_launches (may be null) counts those
+// shared launches.  The caller validates the contexts (two levels, FP32
+// cycle, equal Nb, storage, restarts and stream).
+void solve_ragged(const std::vector<Context*>& cs, const std::vector<const cd64*>& b, const std::vector<cd64*>& x,
+                  const std::vector<int>& B, std::vector<std::vector<int>>& iters, int64_t* coarse_launches);
+
 }  // namespace wcmg

@@ -290,6 +290,8 @@ struct RaggedProblem {
   const int* nbr;   // [8][Vc]
   long Vc;
   int nrhs;
+  const int* run = nullptr;  // per-RHS run flags (stride rs), or none
+  int rs = 0;
 };
 struct RaggedTable {
   RaggedProblem p[kRaggedMax];

@@ -104,6 +104,8 @@ def lib():
         l.wcmg_cycle.argtypes = [vp, vp, vp]
         l.wcmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(SolveInfo)]
         l.wcmg_solve_batched.argtypes = [vp, vp, vp, ip, ip, C.POINTER(SolveInfo)]
+        l.wcmg_solve_ragged.argtypes = [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int),
+                                        C.POINTER(SolveInfo)]
         l.wcmg_tune_enable.argtypes = [vp, ip]
         l.wcmg_tune_table.argtypes = [vp, C.c_char_p, ip, C.POINTER(C.c_int)]
         l.wcmg_tune_load.argtypes = [vp, C.c_char_p]
@@ -515,6 +517,32 @@ class CoarseOperator:
         ms = C.c_double(0.0)
         self._chk(lib().wcmg_coarse_time(self.h, _ptr(x), _ptr(out), nrhs, int(reps), C.byref(ms)))
         return ms.value
+
+
+def solve_ragged(ctxs, bs, xs=None, check=True):
+    """wcmg_solve_ragged: problem k solves bs[k] ([nrhs_k][V_k][4][3]
+    complex128) on context ctxs[k]; all problems together, their coarse
+    solves sharing one coarse-operator launch per Arnoldi step.  Returns
+    (xs, infos per problem, status, shared coarse launches)."""
+    n = len(ctxs)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    nr = [b.numel() // (c.V * 12) for c, b in zip(ctxs, bs)]
+    total = sum(nr)
+    info = (SolveInfo * total)()
+    h = (C.c_void_p * n)(*[c.h for c in ctxs])
+    pb = (C.c_void_p * n)(*[_ptr(b).value for b in bs])
+    px = (C.c_void_p * n)(*[_ptr(x).value for x in xs])
+    pn = (C.c_int * n)(*nr)
+    st = lib().wcmg_solve_ragged(h, n, pb, px, pn, info)
+    if check and st != 0:
+        ctxs[0]._chk(st)
+    infos, k = [], 0
+    for q in range(n):
+        infos.append([dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
+                           t_solve_s=i.t_solve_s, coarse_iters=i.coarse_iters) for i in info[k:k + nr[q]]])
+        k += nr[q]
+    return xs, infos, st, (info[0].cycles if total else 0)
 
 
 def _ragged_args(ops, ins):
