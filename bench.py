@@ -395,6 +395,62 @@ def batched_point_sources(w, torch, wl, fp64=True):
     return out
 
 
+def ragged_solve(w, torch, wl=WORKLOAD_BATCH):
+    """The ragged batch as a whole solve: 8^4, 16^4 and 24^3 x 48 (own gauge
+    fields and start vectors, the batched workload's parameters), 12 point
+    sources each, solved by one wcmg_solve_ragged call (the coarse solves of
+    all three share one matrix-core launch per Arnoldi step) against the three
+    problems' own batched solves one after another."""
+    import numpy as np
+    import synthetic as syn
+    lats = [(8, 8, 8, 8), (16, 16, 16, 16), tuple(wl["L"])]
+    ctxs, bs = [], []
+    base = syn.config_seeds(wl["seed"])
+    for k, L in enumerate(lats):
+        V = int(np.prod(L))
+        wk = dict(wl, L=L)
+        c = make_context(w, wk, mixed=True)
+        c.set_gauge(torch.from_numpy(syn.gauge_field(L, wl["eps"], base["gauge"] + 10 * k)).cuda())
+        c.set_null_vectors(0, torch.from_numpy(syn.start_vectors(wl["nv"], V, 12, base["start"] + 10 * k)).cuda())
+        c.setup()
+        ctxs.append(c)
+        bs.append(torch.from_numpy(syn.point_sources(V, site=0)).cuda())
+    for c, b in zip(ctxs, bs):  # first calls allocate every Krylov space
+        c.solve_batched(b)
+    w.solve_ragged(ctxs, bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sep = [c.solve_batched(b) for c, b in zip(ctxs, bs)]
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    fam = "coarse_mfma_ragged_f32"
+    ctxs[0].profile(fam, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos, st, launches = w.solve_ragged(ctxs, bs)
+    torch.cuda.synchronize()
+    t_rag = time.perf_counter() - t0
+    n, ms = ctxs[0].profile_stats(fam)
+    ctxs[0].profile(fam, False)
+    out = {"lattices": [list(l) for l in lats], "nrhs_each": 12, "ragged_solve_s": t_rag, "separate_batched_s": t_sep,
+           "speedup": t_sep / t_rag, "status": st, "shared_coarse_launches": launches,
+           "shared_launch_avg_us": ms * 1e3 / max(n, 1),
+           "per_problem": []}
+    for k in range(3):
+        out["per_problem"].append({
+            "lattice": list(lats[k]), "outer_iters": [i["outer_iters"] for i in infos[k]],
+            "separate_outer_iters": [i["outer_iters"] for i in sep[k][1]],
+            "max_true_rel_res": max(i["true_rel_res"] for i in infos[k]),
+            "coarse_iters_all_rhs": infos[k][0]["coarse_iters"]})
+    out["converged"] = st == 0 and all(i["converged"] for inf in infos for i in inf)
+    print("[bench] ragged solve %.3f s (separate batched solves %.3f s), %d shared coarse launches" % (
+        t_rag, t_sep, launches), file=sys.stderr, flush=True)
+    for c in ctxs:
+        c.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def ragged_batch(w, torch, nrhs=12, reps=50):
     """One matrix-core launch over the coarse operators of three lattices (8^4,
     16^4 and 24^3 x 48 under 4^4 aggregates: 16 + 256 + 2592 coarse sites,
@@ -541,6 +597,9 @@ def kernel_mode(args):
     if fam == "three_level":
         print(json.dumps({"family": fam, **three_level(w, torch)}))
         return
+    if fam == "ragged_solve":
+        print(json.dumps({"family": fam, **ragged_solve(w, torch)}))
+        return
     if fam == "learned_setup":
         # the learned-setup study at a chosen size: --lattice, --ntrain, --ntest, --epochs
         L = tuple(int(v) for v in args.lattice.split(","))
@@ -617,7 +676,8 @@ def main():
                     help="skip the solves with the reference forms of the coarsest GMRES and the outer Arnoldi step")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
-                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, three_level")
+                         "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, "
+                         "three_level, ragged_solve")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--reserved", type=int, default=0, help="kernel mode: reserved[0] flags (reference forms)")
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
@@ -782,6 +842,8 @@ def main():
         extra["batched_24x48"] = batched_point_sources(w, torch, WORKLOAD_BATCH, fp64=not args.no_fp64)
         print("[bench] ragged batch of coarse operators", file=sys.stderr, flush=True)
         extra["ragged_coarse_apply"] = ragged_batch(w, torch)
+        print("[bench] ragged solve: 8^4 + 16^4 + 24^3x48, 12 point sources each", file=sys.stderr, flush=True)
+        extra["ragged_solve"] = ragged_solve(w, torch)
     if not args.no_learned:
         print("[bench] learned setup (16^4, 6 training / 4 held-out fields)", file=sys.stderr, flush=True)
         extra["learned_setup"] = learned_setup(w, torch)

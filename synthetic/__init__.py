@@ -55,28 +55,100 @@ def gell_mann() -> np.ndarray:
     return l
 
 
-def _reunitarise(u: np.ndarray) -> np.ndarray:
-    # polar projection onto U(3), then fix the determinant to 1
-    w, _, vh = np.linalg.svd(u)
-    u = w @ vh
-    det = np.linalg.det(u)
-    return u / (det ** (1.0 / 3.0))[..., None, None]
+def _mm3(a, b):
+    """Batched 3x3 products [..., 3, 3] as broadcast elementwise operations."""
+    return (a[..., :, 0, None] * b[..., None, 0, :] + a[..., :, 1, None] * b[..., None, 1, :]
+            + a[..., :, 2, None] * b[..., None, 2, :])
+
+
+def _expi_traceless_hermitian(Q):
+    """exp(iQ) for traceless Hermitian Q (torch complex128 [..., 3, 3]).
+
+    Cayley-Hamilton reduces the exponential to exp(iQ) = f0 + f1 Q + f2 Q^2;
+    the coefficients follow from the eigenvalues of Q in the parametrisation
+    of C. Morningstar and M. Peardon, Phys. Rev. D 69, 054501 (2004):
+    c0 = det Q, c1 = tr(Q^2)/2, theta = arccos(|c0| / (2 (c1/3)^(3/2))),
+    u = sqrt(c1/3) cos(theta/3), w = sqrt(c1) sin(theta/3), and
+    f_j = h_j / (9u^2 - w^2) with
+      h0 = (u^2 - w^2) e^{2iu} + e^{-iu} (8u^2 cos w + 2iu (3u^2 + w^2) xi0(w)),
+      h1 = 2u e^{2iu} - e^{-iu} (2u cos w - i (3u^2 - w^2) xi0(w)),
+      h2 = e^{2iu} - e^{-iu} (cos w + 3iu xi0(w)),   xi0(w) = sin(w)/w;
+    for c0 < 0, f_j(-c0) = (-1)^j conj(f_j(c0)).
+    """
+    import torch
+    Q2 = _mm3(Q, Q)
+    c1 = 0.5 * (Q2[..., 0, 0] + Q2[..., 1, 1] + Q2[..., 2, 2]).real
+    c0 = (Q[..., 0, 0] * (Q[..., 1, 1] * Q[..., 2, 2] - Q[..., 1, 2] * Q[..., 2, 1])
+          - Q[..., 0, 1] * (Q[..., 1, 0] * Q[..., 2, 2] - Q[..., 1, 2] * Q[..., 2, 0])
+          + Q[..., 0, 2] * (Q[..., 1, 0] * Q[..., 2, 1] - Q[..., 1, 1] * Q[..., 2, 0])).real
+    neg = c0 < 0
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    one = torch.ones_like(c0)
+    ratio = torch.where(c0max > 0, c0.abs() / torch.where(c0max > 0, c0max, one), one)
+    theta = torch.arccos(ratio.clamp(-1.0, 1.0))
+    u = torch.sqrt(c1 / 3.0) * torch.cos(theta / 3.0)
+    w = torch.sqrt(c1) * torch.sin(theta / 3.0)
+    w2 = w * w
+    xi0 = torch.where(w.abs() > 0.05, torch.sin(w) / torch.where(w == 0, one, w),
+                      1 - w2 / 6 * (1 - w2 / 20 * (1 - w2 / 42)))
+    e2iu = torch.exp(2j * u)
+    emiu = torch.exp(-1j * u)
+    cw = torch.cos(w)
+    h0 = (u * u - w2) * e2iu + emiu * (8 * u * u * cw + 2j * u * (3 * u * u + w2) * xi0)
+    h1 = 2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u * u - w2) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9 * u * u - w2
+    f0, f1, f2 = h0 / den, h1 / den, h2 / den
+    f0 = torch.where(neg, f0.conj(), f0)
+    f1 = torch.where(neg, -f1.conj(), f1)
+    f2 = torch.where(neg, f2.conj(), f2)
+    out = f1[..., None, None] * Q + f2[..., None, None] * Q2
+    for i in range(3):
+        out[..., i, i] += f0
+    return out
+
+
+def _reunitarise(U):
+    """Projection onto SU(3) (torch [..., 3, 3]): Gram-Schmidt of the first two
+    rows, third row = conj(row0 x row1), so that det = 1."""
+    import torch
+    r0 = U[..., 0, :]
+    r1 = U[..., 1, :]
+    r0 = r0 / torch.sqrt((r0.abs() ** 2).sum(-1))[..., None]
+    r1 = r1 - (r0.conj() * r1).sum(-1)[..., None] * r0
+    r1 = r1 / torch.sqrt((r1.abs() ** 2).sum(-1))[..., None]
+    r2 = torch.stack([r0[..., 1] * r1[..., 2] - r0[..., 2] * r1[..., 1],
+                      r0[..., 2] * r1[..., 0] - r0[..., 0] * r1[..., 2],
+                      r0[..., 0] * r1[..., 1] - r0[..., 1] * r1[..., 0]], dim=-1).conj()
+    return torch.stack([r0, r1, r2], dim=-2)
+
+
+def _su3_from_algebra(w: np.ndarray, scale: float) -> np.ndarray:
+    """exp(i scale H), H = sum_a w_a lambda_a / 2, for coefficients w [..., 8],
+    re-unitarised; evaluated in chunks (the closed form above, in FP64)."""
+    import torch
+    gm = torch.from_numpy(gell_mann().reshape(8, 9) / 2.0)
+    flat = w.reshape(-1, 8)
+    out = np.empty((flat.shape[0], 3, 3), dtype=np.complex128)
+    step = 1 << 20
+    for a in range(0, flat.shape[0], step):
+        H = (torch.from_numpy(flat[a:a + step]).to(torch.complex128) @ gm).reshape(-1, 3, 3)
+        out[a:a + step] = _reunitarise(_expi_traceless_hermitian(scale * H)).numpy()
+    return out.reshape(w.shape[:-1] + (3, 3))
 
 
 def gauge_field(dims, eps: float, seed: int) -> np.ndarray:
     """SU(3) links U = exp(i*eps*H), H = sum_a w_a lambda_a / 2, w_a ~ N(0,1).
 
     Draw order: ``standard_normal((V, 4, 8))`` in lexicographic site order,
-    then direction, then Gell-Mann index.  The exponential is taken through
-    the eigendecomposition of the Hermitian H, then re-unitarised.
+    then direction, then Gell-Mann index.  The exponential is taken in closed
+    form (Cayley-Hamilton with the Morningstar-Peardon coefficients; equal to
+    the eigendecomposition route to ~1e-15), then re-unitarised.
     """
     V = volume(dims)
     g = rng(seed)
     w = g.standard_normal((V, 4, 8))
-    H = np.einsum("vma,aij->vmij", w, gell_mann() / 2.0)
-    e, q = np.linalg.eigh(H)
-    U = (q * np.exp(1j * eps * e)[..., None, :]) @ np.conj(np.swapaxes(q, -1, -2))
-    return np.ascontiguousarray(_reunitarise(U))
+    return np.ascontiguousarray(_su3_from_algebra(w, eps))
 
 
 def unit_gauge(dims) -> np.ndarray:
@@ -91,10 +163,7 @@ def random_gauge_transform(dims, seed: int) -> np.ndarray:
     V = volume(dims)
     g = rng(seed)
     w = g.standard_normal((V, 8))
-    H = np.einsum("va,aij->vij", w, gell_mann() / 2.0)
-    e, q = np.linalg.eigh(H)
-    G = (q * np.exp(1j * 1.7 * e)[..., None, :]) @ np.conj(np.swapaxes(q, -1, -2))
-    return np.ascontiguousarray(_reunitarise(G))
+    return np.ascontiguousarray(_su3_from_algebra(w, 1.7))
 
 
 def complex_gaussian(shape, seed: int) -> np.ndarray:
