@@ -193,9 +193,15 @@ int wcmg_setup_import(wcmg_ctx* ctx, const void* buf, size_t bytes);
  * the coarse site and the offset inside its aggregate.  Host int32 arrays of V_l. */
 int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32_t* offset_host);
 
-/* Coarse operator of level l >= 1 as complex128 [Vc][9][Nb][Nb] (device). */
-int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks);
-int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks);
+/* Coarse operator of level l >= 1 (the Galerkin operator, Sec. 2.1: Mdiag and
+ * the eight Mdir blocks per site) as [Vc][9][Nb][Nb] (device, caller-owned).
+ * get: prec WCMG_F64 -> complex128 (the FP64 master); WCMG_F32 -> complex64
+ * rounded from it; WCMG_BF16 -> complex64 holding the BF16-rounded values the
+ * cycle's BF16 block storage uses (Nb divisible by 4).  set: prec WCMG_F64
+ * (complex128) or WCMG_F32 (complex64, widened); the master and every stored
+ * copy used by the cycle are replaced.  WCMG_ERR_ARG for other precisions. */
+int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks, int prec);
+int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks, int prec);
 
 /* out = D_l in for nrhs fields (level 0: Wilson-clover, Sec. 2.1 "Dirac
  * operator"; level >= 1: Mdiag + the eight Mdir blocks, Sec. 2.1).  prec: the

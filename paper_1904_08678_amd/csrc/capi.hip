@@ -312,20 +312,31 @@ int wcmg_get_aggregate_map(wcmg_ctx* ctx, int level, int32_t* coarse_host, int32
   });
 }
 
-int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks) {
+int wcmg_get_coarse_op(wcmg_ctx* ctx, int level, void* blocks, int prec) {
   return guarded(ctx, [&](Context& c) {
     require(level >= 1 && level < c.nlev && blocks, WCMG_ERR_ARG, "level must name a coarse level");
+    require(prec == WCMG_F64 || prec == WCMG_F32 || prec == WCMG_BF16, WCMG_ERR_ARG, "bad precision");
     CoarseOp& C = *c.cop[level - 1];
-    WCMG_HIP(hipMemcpyAsync(blocks, C.M64.p, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    require(prec != WCMG_BF16 || C.nb % 4 == 0, WCMG_ERR_ARG, "BF16 storage needs Nb divisible by 4");
+    if (prec == WCMG_F64)
+      WCMG_HIP(hipMemcpyAsync(blocks, C.M64.p, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    else
+      launch_c128_to_c64(C.M64.as<cd64>(), (cf32*)blocks, (long)(C.M64.bytes / sizeof(cd64)), prec == WCMG_BF16,
+                         c.stream);
     c.sync();
   });
 }
 
-int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks) {
+int wcmg_set_coarse_op(wcmg_ctx* ctx, int level, const void* blocks, int prec) {
   return guarded(ctx, [&](Context& c) {
     require(level >= 1 && level < c.nlev && blocks, WCMG_ERR_ARG, "level must name a coarse level");
+    require(prec == WCMG_F64 || prec == WCMG_F32, WCMG_ERR_ARG,
+            "blocks are given in FP64 or FP32 (BF16 is a storage format of the cycle)");
     CoarseOp& C = *c.cop[level - 1];
-    WCMG_HIP(hipMemcpyAsync(C.M64.p, blocks, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    if (prec == WCMG_F64)
+      WCMG_HIP(hipMemcpyAsync(C.M64.p, blocks, C.M64.bytes, hipMemcpyDeviceToDevice, c.stream));
+    else
+      launch_c64_to_c128((const cf32*)blocks, C.M64.as<cd64>(), (long)(C.M64.bytes / sizeof(cd64)), c.stream);
     C.invalidate();
     C.refresh(WCMG_F64, c.stream);
     C.refresh(WCMG_F32, c.stream);

@@ -95,6 +95,24 @@ void launch_blocks_to_device(const cd64* src, long Vc, int nb, int prec, void* d
   WCMG_CHECK_LAUNCH();
 }
 
+// complex128 -> complex64, optionally rounded on to BF16 (nearest even) and
+// widened back: the values that BF16 block storage holds
+__global__ void k_c128_to_c64(const cd64* __restrict__ in, cf32* __restrict__ out, long n, int bf16) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float re = (float)in[e].re, im = (float)in[e].im;
+  if (bf16) {
+    re = bf16_to_f32(f32_to_bf16(re));
+    im = bf16_to_f32(f32_to_bf16(im));
+  }
+  out[e] = mkc(re, im);
+}
+
+void launch_c128_to_c64(const cd64* in, cf32* out, long n, int bf16, hipStream_t st) {
+  hipLaunchKernelGGL(k_c128_to_c64, dim3(nblocks(n)), dim3(kBlock), 0, st, in, out, n, bf16);
+  WCMG_CHECK_LAUNCH();
+}
+
 void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st) {
   hipLaunchKernelGGL(k_c64_to_c128, dim3(nblocks(n)), dim3(kBlock), 0, st, in, out, n);
   WCMG_CHECK_LAUNCH();

@@ -63,6 +63,8 @@ void launch_sap(cplx<R>* x, const cplx<R>* b, const cplx<R>* U, const R* clov, c
 size_t device_block_bytes(long Vc, int nb, int prec);
 void launch_blocks_to_device(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
 void launch_c64_to_c128(const cf32* in, cd64* out, long n, hipStream_t st);
+// bf16 != 0: the complex64 output holds the BF16-rounded values
+void launch_c128_to_c64(const cd64* in, cf32* out, long n, int bf16, hipStream_t st);
 void launch_coarse_apply(int prec, const void* blk, const void* in, void* out, const int* nbr, long Vc, int nb,
                          int dmask, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
 

@@ -91,9 +91,10 @@ def lib():
         for name in ("wcmg_set_gauge", "wcmg_set_clover", "wcmg_get_clover"):
             getattr(l, name).argtypes = [vp, vp]
         l.wcmg_set_null_vectors.argtypes = [vp, ip, vp, ip]
-        for name in ("wcmg_get_null_vectors", "wcmg_get_prolongator", "wcmg_rebuild_from_vectors",
-                     "wcmg_get_coarse_op", "wcmg_set_coarse_op"):
+        for name in ("wcmg_get_null_vectors", "wcmg_get_prolongator", "wcmg_rebuild_from_vectors"):
             getattr(l, name).argtypes = [vp, ip, vp]
+        for name in ("wcmg_get_coarse_op", "wcmg_set_coarse_op"):
+            getattr(l, name).argtypes = [vp, ip, vp, ip]
         l.wcmg_setup.argtypes = [vp]
         l.wcmg_setup_export.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
         l.wcmg_setup_import.argtypes = [vp, vp, C.c_size_t]
@@ -285,15 +286,19 @@ class Context:
                                                o.ctypes.data_as(C.c_void_p)))
         return c, o
 
-    def coarse_op(self, level) -> torch.Tensor:
+    def coarse_op(self, level, prec=F64) -> torch.Tensor:
+        """wcmg_get_coarse_op: complex128 for F64, complex64 for F32 and BF16
+        (the BF16-rounded values of the cycle's block storage)."""
         nb = self.ns[level]
-        out = torch.empty((self.sites(level), 9, nb, nb), dtype=torch.complex128, device="cuda")
-        self._chk(lib().wcmg_get_coarse_op(self.h, level, _ptr(out)))
+        out = torch.empty((self.sites(level), 9, nb, nb), dtype=_cdtype(prec), device="cuda")
+        self._chk(lib().wcmg_get_coarse_op(self.h, level, _ptr(out), int(prec)))
         return out
 
     def set_coarse_op(self, level, blocks: torch.Tensor):
-        assert blocks.dtype == torch.complex128
-        self._chk(lib().wcmg_set_coarse_op(self.h, level, _ptr(blocks.contiguous())))
+        """wcmg_set_coarse_op from complex128 (F64) or complex64 (F32) blocks."""
+        prec = F64 if blocks.dtype == torch.complex128 else F32
+        assert blocks.dtype in (torch.complex128, torch.complex64)
+        self._chk(lib().wcmg_set_coarse_op(self.h, level, _ptr(blocks.contiguous()), prec))
 
     # ---- operators
     def apply_D(self, level, x: torch.Tensor, prec=F64) -> torch.Tensor:

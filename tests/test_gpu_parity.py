@@ -568,3 +568,27 @@ def test_dslash_site_arithmetic_equals_neighbour_table(L, block, levels):
     H = oracle.Hierarchy(L, U, m0=-0.08, n_levels=1, blocks=())
     ref = np.stack([H.apply(0, psi[r]).reshape(V, 4, 3) for r in range(3)])
     assert rel(outs[0][0], ref) < 1e-13
+
+
+def test_coarse_op_get_set_precisions():
+    """wcmg_get_coarse_op in FP64 / FP32 / BF16 equals the FP64 master, its
+    FP32 rounding and its BF16 rounding; wcmg_set_coarse_op from FP32 blocks
+    widens them (the FP64 master then equals them exactly) and the cycle's
+    FP32 coarse apply uses them; BF16 input is refused."""
+    w = wc()
+    L, block, nv = (4, 4, 4, 8), (2, 2, 2, 2), 8
+    ctx, H, U = make_pair(L, 0.3, 241, blocks=(block,), nv=(nv,))
+    ctx.set_null_vectors(0, dev(syn.complex_gaussian((nv, 512, 12), 242)))
+    ctx.setup()
+    m64 = host(ctx.coarse_op(1))
+    assert np.array_equal(host(ctx.coarse_op(1, w.F32)), m64.astype(np.complex64))
+    assert np.array_equal(host(ctx.coarse_op(1, w.BF16)).astype(np.complex128), bf16_round(m64))
+    new = syn.complex_gaussian(m64.shape, 243).astype(np.complex64)
+    ctx.set_coarse_op(1, dev(new))
+    assert np.array_equal(host(ctx.coarse_op(1)), new.astype(np.complex128))
+    phi = syn.complex_gaussian((1, 32, 16), 244)
+    ref = oracle.coarse_apply((2, 2, 2, 4), new.astype(np.complex128), phi)
+    assert rel(host(ctx.apply_D(1, dev(phi.astype(np.complex64)), w.F32)), ref) < 1e-5
+    import ctypes as C
+    st = w.lib().wcmg_set_coarse_op(ctx.h, 1, C.c_void_p(dev(new).data_ptr()), w.BF16)
+    assert st == 1
