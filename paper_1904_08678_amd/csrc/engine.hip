@@ -459,7 +459,8 @@ void Context::prolong_(int l, const cplx<R>* coarse, cplx<R>* fine, int accumula
   const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
   const char* fam = sizeof(R) == 8 ? "prolong_f64" : "prolong_f32";
   prof.begin_kernel(fam);
-  launch_prolong<R>(coarse, fine, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, accumulate, nrhs, run, stream);
+  launch_prolong<R>(coarse, fine, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, accumulate, nrhs, run, stream, 0,
+                    T.agg_sites.as<int>(), T.A);
   prof.end(fam, stream);
 }
 

@@ -379,7 +379,8 @@ void Context::cycleB(int l, const cplx<R>* r, cplx<R>* x, int B, const int* run,
     if (!capturing) prof.begin_kernel(fam);
     const Transfer& T = tr[l];
     const cplx<R>* P = sizeof(R) == 8 ? (const cplx<R>*)T.P64.p : (const cplx<R>*)T.P32.p;
-    launch_prolong<R>(ec, x, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, 0, B, run, stream, rs);
+    launch_prolong<R>(ec, x, P, geo[l].lay, T.coarse_of.as<int>(), T.Vc, T.nb, 0, B, run, stream, rs,
+                      T.agg_sites.as<int>(), T.A);
     if (!capturing) prof.end(fam, stream);
   }
   if (l == 0 && p.smoother == 1) sap<R>(r, x, p.post_smooth, B, run, rs);

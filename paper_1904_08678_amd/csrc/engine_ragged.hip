@@ -273,7 +273,7 @@ void solve_ragged(const std::vector<Context*>& cs, const std::vector<const cd64*
       for (int r = 0; r < B; ++r) c.coarse_iters += its[k][r];
       const Transfer& T = c.tr[0];
       launch_prolong<float>(ec[k], x32[k], T.P32.as<cf32>(), c.geo[0].lay, T.coarse_of.as<int>(), T.Vc, T.nb, 0, B,
-                            run[k], stream, rs);
+                            run[k], stream, rs, T.agg_sites.as<int>(), T.A);
       if (c.p.smoother == 1) c.sap<float>(r32[k], x32[k], c.p.post_smooth, B, run[k], rs);
       else c.mrB<float>(0, r32[k], x32[k], B, c.p.post_smooth, run[k], rs);
       launch_belem<cf32, cd64>(out[k], nn, x32[k], nn, nullptr, 0, nullptr, 0, nn, B, 1, run[k], rs, stream);

@@ -92,8 +92,11 @@ template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs = 0);
 template <typename R>
+// agg_sites (optional, [Vc][A] device sites of each aggregate): lets several
+// right-hand sides of an FP32 level-0 field take the per-aggregate form
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
-                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0);
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs = 0,
+                    const int* agg_sites = nullptr, int A = 0);
 void launch_block_orthonormalise(cd64* vecs, FieldLayout lay, const int* agg_sites, int A, long Vc, int nv,
                                  int* breakdown, hipStream_t st);
 void launch_prolongator_columns(const cd64* P, FieldLayout lay, int nv, cd64* out, hipStream_t st);

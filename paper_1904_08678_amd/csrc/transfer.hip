@@ -12,6 +12,8 @@
 // half chi of vector i, orthonormalised aggregate by aggregate, is column
 // b = chi * nv + i of P (Sec. 2.2).  Chirality is implicit: nothing is stored
 // twice and no explicit zeros are kept.
+#include <type_traits>
+
 #include "wilson_ops.h"
 
 namespace wcmg {
@@ -105,6 +107,134 @@ __global__ void __launch_bounds__(256) k_prolong(const cplx<R>* __restrict__ coa
       if (accumulate) t = cadd(t, fine[e]);
       fine[e] = t;
     }
+}
+
+// Several right-hand sides of a level-0 FP32 field (layout [B][12][V]) per
+// launch, each aggregate's slice of P read once: one workgroup of 8 waves per
+// aggregate; wave w takes chirality w / 4 and the right-hand sides
+// r = w % 4 + 4 j (j < RPW), a lane per site.  The four waves of a chirality
+// read the same P entries together (from cache after the first), so P
+// crosses HBM once per launch instead of once per right-hand side.  Padding
+// workgroups (the grid is a multiple of the 8 XCDs) return at once.
+__device__ inline long agg_of_block(long Vc) {
+  const long G = gridDim.x, h = blockIdx.x;
+  const long c = (h % 8) * (G / 8) + h / 8;  // each XCD a contiguous range of aggregates
+  return c < Vc ? c : -1;
+}
+
+// coarse_r(c, chi * nv + i) = sum_{x in c} sum_{k < 6} conj(P_i(x)_{6 chi + k}) fine_r(x)_{6 chi + k}
+// 16 waves: wave w takes chirality w / 8, vectors i of half (w / 4) % 2 and
+// the right-hand sides w % 4 + 4 j, so each lane keeps NV/2 x RPW
+// accumulators (more waves resident to cover the memory latency).
+template <int NB, int RPW>
+__global__ void __launch_bounds__(1024, 8) k_restrict_mrhs(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
+                                                         const cf32* __restrict__ P, long V,
+                                                         const int* __restrict__ agg_sites, int A, long Vc,
+                                                         int nrhs, const int* __restrict__ run, int rs) {
+  constexpr int NV = NB / 2, NH = NV / 2;
+  const long c = agg_of_block(Vc);
+  if (c < 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int chi = wave >> 3, ih = (wave >> 2) & 1, g = wave & 3;
+  bool act[RPW];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int r = g + 4 * j;
+    act[j] = r < nrhs && (!run || run[(long)r * rs]);
+    any = any || act[j];
+  }
+  const long fs = 12 * V;
+  cf32 acc[NH][RPW];
+#pragma unroll
+  for (int i = 0; i < NH; ++i)
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) acc[i][j] = mkc(0.f, 0.f);
+  // one block of 64 sites per pass; the barrier keeps the waves that read the
+  // same entries within one block of each other; waves without work join it
+  for (int o0 = 0; o0 < A; o0 += 64) {
+    const int o = o0 + lane;
+    const long s = any && o < A ? agg_sites[c * A + o] : -1;
+#pragma unroll 1
+    for (int k = 0; k < 6 && s >= 0; ++k) {
+      const long e = (long)(chi * 6 + k) * V + s;
+      cf32 v[RPW];
+#pragma unroll
+      for (int j = 0; j < RPW; ++j) v[j] = act[j] ? fine[(long)(g + 4 * j) * fs + e] : mkc(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < NH; ++i) {
+        const cf32 p = P[(long)(ih * NH + i) * fs + e];
+#pragma unroll
+        for (int j = 0; j < RPW; ++j) cfmac(acc[i][j], p, v[j]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!any) return;  // wave-uniform
+#pragma unroll
+  for (int i = 0; i < NH; ++i)
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+      float re = acc[i][j].re, im = acc[i][j].im;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+      }
+      if (lane == 0 && act[j]) coarse[((long)(g + 4 * j) * Vc + c) * NB + chi * NV + ih * NH + i] = mkc(re, im);
+    }
+}
+
+// fine_r(x)_{6 chi + k} (+)= sum_i P_i(x)_{6 chi + k} coarse_r(c(x), chi * nv + i), the
+// same workgroup shape; the wave keeps its right-hand sides' coarse components
+// of its chirality in registers.
+template <int NB, int RPW>
+__global__ void __launch_bounds__(512, 4) k_prolong_mrhs(const cf32* __restrict__ coarse, cf32* __restrict__ fine,
+                                                       const cf32* __restrict__ P, long V,
+                                                       const int* __restrict__ agg_sites, int A, long Vc,
+                                                       int accumulate, int nrhs, const int* __restrict__ run, int rs) {
+  constexpr int NV = NB / 2;
+  const long c = agg_of_block(Vc);
+  if (c < 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int chi = wave >> 2, g = wave & 3;
+  bool act[RPW];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int r = g + 4 * j;
+    act[j] = r < nrhs && (!run || run[(long)r * rs]);
+    any = any || act[j];
+  }
+  const long fs = 12 * V;
+  cf32 phi[NV][RPW];
+#pragma unroll
+  for (int j = 0; j < RPW; ++j)
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      phi[i][j] = act[j] ? coarse[((long)(g + 4 * j) * Vc + c) * NB + chi * NV + i] : mkc(0.f, 0.f);
+  for (int o0 = 0; o0 < A; o0 += 64) {  // as in k_restrict_mrhs: waves kept in step, idle ones join the barrier
+    const int o = o0 + lane;
+    const long s = any && o < A ? agg_sites[c * A + o] : -1;
+#pragma unroll 1
+    for (int k = 0; k < 6 && s >= 0; ++k) {
+      const long e = (long)(chi * 6 + k) * V + s;
+      cf32 p[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) p[i] = P[(long)i * fs + e];
+#pragma unroll
+      for (int j = 0; j < RPW; ++j) {
+        if (!act[j]) continue;
+        cf32 t = mkc(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cfma(t, p[i], phi[i][j]);
+        cf32* out = fine + (long)(g + 4 * j) * fs + e;
+        if (accumulate) t = cadd(t, *out);
+        *out = t;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Per aggregate and chirality: modified Gram-Schmidt of the nv vectors in
@@ -563,25 +693,60 @@ bool supported_nb(int nb) {
   return nb == 4 || nb == 6 || nb == 8 || nb == 12 || nb == 16 || nb == 20 || nb == 24 || nb == 32 || nb == 40;
 }
 
+// The multi-RHS forms serve FP32 level-0 fields with 2..16 right-hand sides
+// and Nb in {8, 12, 16, 24}; RPW right-hand sides per wave.
+static bool transfer_mrhs(int nb, int nrhs, const FieldLayout& lay) {
+  return lay.soa && lay.ns == 12 && nrhs >= 2 && nrhs <= 16 && (nb == 8 || nb == 12 || nb == 16 || nb == 24);
+}
+#define RPW_SWITCH(nrhs, ...)                                                   \
+  switch ((nrhs + 3) / 4) {                                                     \
+    case 1: { constexpr int RPWc = 1; __VA_ARGS__; } break;                     \
+    case 2: { constexpr int RPWc = 2; __VA_ARGS__; } break;                     \
+    case 3: { constexpr int RPWc = 3; __VA_ARGS__; } break;                     \
+    default: { constexpr int RPWc = 4; __VA_ARGS__; } break;                    \
+  }
+#define NB_SWITCH_MRHS(nb, ...)                                                 \
+  switch (nb) {                                                                 \
+    case 8: { constexpr int NBc = 8; __VA_ARGS__; } break;                      \
+    case 12: { constexpr int NBc = 12; __VA_ARGS__; } break;                    \
+    case 16: { constexpr int NBc = 16; __VA_ARGS__; } break;                    \
+    default: { constexpr int NBc = 24; __VA_ARGS__; } break;                    \
+  }
+
 template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st, fine, coarse, P,
-                             lay, agg_sites, A, Vc, nrhs, run, rs));
+  if (std::is_same<R, float>::value && transfer_mrhs(nb, nrhs, lay)) {
+    const dim3 g((unsigned)((Vc + 7) / 8 * 8)), b(512);
+    NB_SWITCH_MRHS(nb, RPW_SWITCH(nrhs, WCMG_LAUNCH((k_restrict_mrhs<NBc, RPWc>), g, dim3(1024), 0, st, (const cf32*)fine,
+                                                    (cf32*)coarse, (const cf32*)P, lay.V, agg_sites, A, Vc, nrhs, run,
+                                                    rs)));
+  } else {
+    NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st, fine, coarse, P,
+                               lay, agg_sites, A, Vc, nrhs, run, rs));
+  }
   WCMG_CHECK_LAUNCH();
 }
 template <typename R>
 void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, FieldLayout lay, const int* coarse_of,
-                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs) {
-  NB_SWITCH(nb, WCMG_LAUNCH((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
-                             coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
+                    long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs,
+                    const int* agg_sites, int A) {
+  if (std::is_same<R, float>::value && agg_sites && transfer_mrhs(nb, nrhs, lay)) {
+    const dim3 g((unsigned)((Vc + 7) / 8 * 8)), b(512);
+    NB_SWITCH_MRHS(nb, RPW_SWITCH(nrhs, WCMG_LAUNCH((k_prolong_mrhs<NBc, RPWc>), g, b, 0, st, (const cf32*)coarse,
+                                                    (cf32*)fine, (const cf32*)P, lay.V, agg_sites, A, Vc, accumulate,
+                                                    nrhs, run, rs)));
+  } else {
+    NB_SWITCH(nb, WCMG_LAUNCH((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
+                               coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
+  }
   WCMG_CHECK_LAUNCH();
 }
 #define INST_TR(R)                                                                                                 \
   template void launch_restrict<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, int, long, int, \
                                    int, const int*, hipStream_t, int);                                             \
   template void launch_prolong<R>(const cplx<R>*, cplx<R>*, const cplx<R>*, FieldLayout, const int*, long, int, int, \
-                                  int, const int*, hipStream_t, int);
+                                  int, const int*, hipStream_t, int, const int*, int);
 INST_TR(double)
 INST_TR(float)
 

@@ -592,3 +592,34 @@ def test_coarse_op_get_set_precisions():
     import ctypes as C
     st = w.lib().wcmg_set_coarse_op(ctx.h, 1, C.c_void_p(dev(new).data_ptr()), w.BF16)
     assert st == 1
+
+
+@pytest.mark.parametrize("nrhs", [2, 5, 12, 16])
+def test_restrict_prolong_multi_rhs_fp32(nrhs):
+    """Several right-hand sides of an FP32 level-0 field in one launch (each
+    aggregate's P read once for all of them, waves split by chirality and
+    right-hand-side group) against the oracle, and against one launch per
+    field; lattice 8x4x4x8 with 4x2x2x4 aggregates (8 aggregates, 64 sites
+    each) and 6x4x4x6 with 3x2x2x2 (24 aggregates of 24 sites)."""
+    w = wc()
+    for L, block, seed in (((8, 4, 4, 8), (4, 2, 2, 4), 251), ((6, 4, 4, 6), (3, 2, 2, 2), 261)):
+        nv = 12
+        ctx, H, U = make_pair(L, 0.3, seed, blocks=(block,), nv=(nv,))
+        V = int(np.prod(L))
+        start = syn.complex_gaussian((nv, V, 12), seed + 1)
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        H.set_start(0, start)
+        H.setup()
+        Pv = H.P(0)
+        v = syn.complex_gaussian((nrhs, V, 12), seed + 2)
+        got = host(ctx.restrict(0, dev(v.astype(np.complex64)), w.F32))
+        assert rel(got, oracle.restrict(L, block, 12, Pv, v)) < 1e-5
+        one = np.stack([host(ctx.restrict(0, dev(v[r:r + 1].astype(np.complex64)), w.F32))[0] for r in range(nrhs)])
+        assert rel(got, one) < 1e-6
+        Vc = V // int(np.prod(block))
+        phi = syn.complex_gaussian((nrhs, Vc, 2 * nv), seed + 3)
+        got = host(ctx.prolong(0, dev(phi.astype(np.complex64)), w.F32))
+        assert rel(got, oracle.prolong(L, block, 12, Pv, phi)) < 1e-5
+        one = np.stack([host(ctx.prolong(0, dev(phi[r:r + 1].astype(np.complex64)), w.F32))[0] for r in range(nrhs)])
+        assert rel(got, one) < 1e-6
