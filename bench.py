@@ -15,9 +15,14 @@ coarse blocks; FP64 outer solver; each coarsest GMRES solve is one
 cooperative launch).  `value` is the solve time of the mixed solve (seconds to
 1e-10); the plain FP64 solve, the same solve with reference forms of the
 coarsest GMRES (four kernels per step) and of the outer Arnoldi step (CGS2),
-the coarse-apply bandwidth on a large synthetic coarse lattice, the roofline
-of the dominant solve kernel and the CPU oracle are reported beside it.  The warmup step times every kernel family (the kernel
-table); the timed steps record HIP events only around the dominant kernel.
+the coarse-apply bandwidth on a large synthetic coarse lattice (Nb 16, 24,
+32), the roofline of the dominant solve kernel, the latency line of the
+coarsest GMRES (time per Arnoldi step), the batched and ragged solves of point
+sources (24^3 x 48; 8^4 + 16^4 + 24^3 x 48), the three-level workload
+(32^3 x 64), the learned setup and the CPU oracle (the whole workload,
+unsampled, on the host cores) are reported beside it.  The warmup step times
+every kernel family (the kernel table); the timed steps record HIP events only
+around the dominant kernel.
 """
 from __future__ import annotations
 
@@ -159,12 +164,13 @@ def make_inputs(wl):
 COARSE_POINTS = 9  # blocks stored per coarse site (set by --coarse-points)
 
 
-def make_context(w, wl, mixed: bool, reserved: int = 0):
+def make_context(w, wl, mixed: bool, reserved: int = 0, **extra):
     kw = dict(dims=wl["L"], m0=wl["m0"], c_sw=wl["csw"], n_levels=2, block=(wl["block"],), n_vec=(wl["nv"],),
               relax_sweeps=wl["relax"], refine_iters=wl["refine"], outer_restart=20, outer_maxit=2000,
               coarse_points=COARSE_POINTS, reserved=(reserved,))
     if mixed:
         kw.update(cycle_prec=w.F32, coarse_store_prec=w.F32, setup_prec=w.F32)
+    kw.update(extra)
     return w.Context(**kw)
 
 
@@ -230,6 +236,36 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
     torch.cuda.empty_cache()
     return {"coarse_dims": list(dims), "Vc": Vc, "nb": nb, "per_store": out, "nrhs": nrhs_batch,
             "batched": batched}
+
+
+def coarse_gmres_latency(w, torch, wl, Ud, startd, reps=20, iters=(4, 16)):
+    """The coarsest GMRES as one cooperative launch is bound by the latency of
+    its grid barriers, not by a byte stream: its time per Arnoldi step is the
+    slope of the launch time over the number of steps (fixed iteration
+    counts, one restart cycle), the intercept the per-launch cost (blocks into
+    LDS, residual, final update)."""
+    import numpy as np
+    out = {}
+    r = torch.randn((int(np.prod(wl["L"])), 4, 3), dtype=torch.complex128, device="cuda")
+    for k in iters:
+        ctx2 = make_context(w, wl, mixed=True, coarse_fixed_iters=k)
+        ctx2.set_gauge(Ud)
+        ctx2.set_null_vectors(0, startd)
+        ctx2.setup()
+        ctx2.cycle(r)
+        ctx2.profile("coarse_gmres_persistent", True)
+        for _ in range(reps):
+            ctx2.cycle(r)
+        n, ms = ctx2.profile_stats("coarse_gmres_persistent")
+        out[k] = ms * 1e3 / max(n, 1)
+        ctx2.close()
+    k0, k1 = iters
+    slope = (out[k1] - out[k0]) / (k1 - k0)
+    return {"bound": "latency", "kernel": "coarse_gmres_persistent", "unit": "us",
+            "us_per_launch": {str(k): out[k] for k in iters}, "us_per_arnoldi_step": slope,
+            "us_per_launch_fixed": out[k0] - slope * k0,
+            "grid_barriers_per_step": "1, plus 1 when the step re-orthogonalises",
+            "coarse_sites": int(np.prod(wl["L"])) // int(np.prod(wl["block"])), "nb": 2 * wl["nv"]}
 
 
 def reference_forms(w, torch, wl, Ud, startd, bd):
@@ -555,26 +591,78 @@ def learned_setup(w, torch, L=(16, 16, 16, 16), ntrain=6, ntest=4, epochs=8, nv=
                             "frac_fp32_mfma": 2 * fl / (msb / max(nb_, 1)) / 1e9 / 157.3}}
 
 
-def cpu_baseline(wl, U, start, b, gpu_outer_iters, sample_iters=3):
-    """Oracle (plain FP64 C++) on the host cores: seconds per outer FGMRES
-    iteration at the same lattice and parameters, scaled to the GPU's outer
-    iteration count.  The oracle's own setup (20 relaxation sweeps, no
-    refinement) runs untimed first."""
+def cpu_baseline(wl, U, start, b, gpu_outer_iters, x_gpu=None):
+    """The oracle (plain FP64 C++, OpenMP over sites) on all host cores, the
+    whole workload, unsampled: its setup (20 MR sweeps, Gram-Schmidt, Galerkin
+    coarsening) and refinement timed apart from its FP64 FGMRES solve on the
+    same inputs as the GPU; also its outer iteration count and the distance
+    between its solution and the GPU's (x_gpu, the last timed solve)."""
     import numpy as np
     import oracle
     H = oracle.Hierarchy(wl["L"], U, m0=wl["m0"], csw=wl["csw"], blocks=(wl["block"],), nv=(wl["nv"],),
-                         relax_sweeps=wl["relax"], outer_restart=20, outer_maxit=sample_iters)
+                         relax_sweeps=wl["relax"], outer_restart=20, outer_maxit=2000)
     H.set_start(0, start)
-    H.setup()
     t0 = time.perf_counter()
-    x, it, rel, st = H.solve(b)
-    dt = time.perf_counter() - t0
-    per_iter = dt / max(it, 1)
-    return {"value": per_iter * gpu_outer_iters, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d outer FGMRES iterations of the oracle FP64 two-level solve on the same 16^3x32 input "
-                      "(%.2f s, %.3f s/iteration), scaled to the GPU's %d outer iterations; oracle setup "
-                      "(20 MR sweeps, no refinement) untimed" % (it, dt, per_iter, gpu_outer_iters),
-            "host_cpu": platform.processor() or platform.machine()}
+    H.setup()
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H.refine(wl["refine"])
+    t_ref = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xo, ito, rro, sto = H.solve(b)
+    t_sol = time.perf_counter() - t0
+    rec = {"value": t_sol, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+           "setup_s": t_init, "refine_s": t_ref, "outer_iters": ito, "true_rel_res": rro,
+           "gpu_outer_iters_minus_oracle": gpu_outer_iters - ito,
+           "sample": "the whole workload, unsampled: the oracle's setup (20 MR sweeps per vector, Gram-Schmidt, "
+                     "Galerkin) %.1f s and refinement %.1f s, then its FP64 FGMRES(20) solve to 1e-10 (value), "
+                     "%d outer iterations against the GPU's %d" % (t_init, t_ref, ito, gpu_outer_iters),
+           "host_cpu": platform.processor() or platform.machine()}
+    if x_gpu is not None:
+        rec["rel_diff_gpu_solution"] = float(np.linalg.norm(x_gpu.reshape(-1) - xo) / np.linalg.norm(xo))
+    return rec
+
+
+def oracle_m2(w, torch, wl=WORKLOAD):
+    """The whole workload on the oracle, unsampled -- setup (20 MR sweeps, one
+    refinement iteration) and FP64 solve -- timed, next to the GPU's mixed
+    and FP64 solves on the same inputs: outer iterations and the distance
+    between the solutions."""
+    import numpy as np
+    import oracle
+    U, start, b = make_inputs(wl)
+    H = oracle.Hierarchy(wl["L"], U, m0=wl["m0"], csw=wl["csw"], blocks=(wl["block"],), nv=(wl["nv"],),
+                         relax_sweeps=wl["relax"], outer_restart=20, outer_maxit=2000)
+    H.set_start(0, start)
+    t0 = time.perf_counter()
+    H.setup()
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H.refine(wl["refine"])
+    t_ref = time.perf_counter() - t0
+    print("[bench] oracle setup %.1f s + refinement %.1f s" % (t_init, t_ref), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    xo, ito, rro, sto = H.solve(b)
+    t_sol = time.perf_counter() - t0
+    print("[bench] oracle solve %.1f s, %d outer iterations, res %.2e" % (t_sol, ito, rro), file=sys.stderr,
+          flush=True)
+    out = {"workload": wl["name"], "cores": oracle.num_threads(),
+           "oracle": {"setup_s": t_init, "refine_s": t_ref, "solve_s": t_sol, "outer_iters": ito,
+                      "true_rel_res": rro, "status": sto}}
+    Ud, startd, bd = (torch.from_numpy(a).cuda() for a in (U, start, b))
+    for label, mixed in (("gpu_mixed", True), ("gpu_fp64", False)):
+        ctx = make_context(w, wl, mixed=mixed)
+        ctx.set_gauge(Ud)
+        ctx.set_null_vectors(0, startd)
+        ctx.setup()
+        x, info, st = ctx.solve(bd)
+        xg = x.cpu().numpy().reshape(-1)
+        out[label] = {"outer_iters": info[0]["outer_iters"], "true_rel_res": info[0]["true_rel_res"],
+                      "solve_s": info[0]["t_solve_s"], "setup_s": ctx.timers()["setup"],
+                      "outer_iters_minus_oracle": info[0]["outer_iters"] - ito,
+                      "rel_diff_to_oracle_solution": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))}
+        ctx.close()
+    return out
 
 
 def kernel_mode(args):
@@ -599,6 +687,9 @@ def kernel_mode(args):
         return
     if fam == "ragged_solve":
         print(json.dumps({"family": fam, **ragged_solve(w, torch)}))
+        return
+    if fam == "oracle_m2":
+        print(json.dumps({"family": fam, **oracle_m2(w, torch)}))
         return
     if fam == "learned_setup":
         # the learned-setup study at a chosen size: --lattice, --ntrain, --ntest, --epochs
@@ -672,12 +763,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-sap", action="store_true")
+    ap.add_argument("--no-three", action="store_true", help="skip the three-level workload (32^3x64)")
     ap.add_argument("--no-coarse-compare", action="store_true",
                     help="skip the solves with the reference forms of the coarsest GMRES and the outer Arnoldi step")
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, "
-                         "three_level, ragged_solve")
+                         "three_level, ragged_solve, oracle_m2")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--reserved", type=int, default=0, help="kernel mode: reserved[0] flags (reference forms)")
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
@@ -723,6 +815,8 @@ def main():
     roof_families = ["dslash_f64", "dslash_f32", "coarse_apply_f32", "restrict_f32", "prolong_f32"]
     families = roof_families + ["coarse_gmres_persistent"]
 
+    last_x = [None]
+
     def step(prof):
         ctx.setup()
         setup_s = ctx.timers()["setup"]
@@ -731,6 +825,7 @@ def main():
         x, info, st = ctx.solve(bd)
         for f in families:
             ctx.profile(f, False)
+        last_x[0] = x
         return setup_s, info[0], st
 
     # The warmup steps time every family (the kernel table, and the choice of
@@ -821,6 +916,8 @@ def main():
                                  "setup_s": float(np.mean(setups)), "solve_outer_iters": inf2[0]["outer_iters"],
                                  "true_rel_res": inf2[0]["true_rel_res"]}
     del c2, blob
+    print("[bench] coarsest GMRES: time per Arnoldi step", file=sys.stderr, flush=True)
+    latency = coarse_gmres_latency(w, torch, wl, Ud, startd)
     if not args.no_coarse_compare:
         print("[bench] reference forms of the coarsest GMRES and the outer Arnoldi step", file=sys.stderr, flush=True)
         extra["reference_forms"] = reference_forms(w, torch, wl, Ud, startd, bd)
@@ -832,6 +929,9 @@ def main():
     if not args.no_mk:
         print("[bench] coarse apply on the 16^3x32 coarse lattice (Vc=131072, Nb=24)", file=sys.stderr, flush=True)
         extra["coarse_apply_large"] = coarse_apply_mk(w, torch)
+        for nbx in (16, 32):
+            print("[bench] coarse apply on the 16^3x32 coarse lattice, Nb=%d" % nbx, file=sys.stderr, flush=True)
+            extra["coarse_apply_large_nb%d" % nbx] = coarse_apply_mk(w, torch, nb=nbx, reps=10)
         extra["coarse_apply_large"]["per_store"]["f32"]["traffic"] = counter_traffic("coarse_apply_f32_large")
         for st in ("f32", "bf16"):
             rec = extra["coarse_apply_large"]["batched"].get(st)
@@ -844,13 +944,16 @@ def main():
         extra["ragged_coarse_apply"] = ragged_batch(w, torch)
         print("[bench] ragged solve: 8^4 + 16^4 + 24^3x48, 12 point sources each", file=sys.stderr, flush=True)
         extra["ragged_solve"] = ragged_solve(w, torch)
+    if not args.no_three:
+        print("[bench] three-level workload, 32^3x64", file=sys.stderr, flush=True)
+        extra["three_level_32x64"] = three_level(w, torch, fp64=not args.no_fp64)
     if not args.no_learned:
         print("[bench] learned setup (16^4, 6 training / 4 held-out fields)", file=sys.stderr, flush=True)
         extra["learned_setup"] = learned_setup(w, torch)
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, U, start, b, infos[-1]["outer_iters"])
+        print("[bench] CPU oracle: the whole workload", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, U, start, b, infos[-1]["outer_iters"], last_x[0].cpu().numpy())
 
     line = {
         "metric": METRIC, "value": solve_s, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -861,7 +964,7 @@ def main():
                    "FP32 cycle and coarse blocks, FP64 outer FGMRES", "coarse_points": COARSE_POINTS},
         "converged": ok, "setup_s": float(np.mean(setups)), "outer_iters": infos[-1]["outer_iters"],
         "coarse_iters": infos[-1]["coarse_iters"], "true_rel_res": infos[-1]["true_rel_res"],
-        "roofline": roofline, "kernels": kernel_table, "cpu_baseline": cpu,
+        "roofline": roofline, "latency": latency, "kernels": kernel_table, "cpu_baseline": cpu,
     }
     line.update(extra)
     print(json.dumps(line))
