@@ -103,13 +103,16 @@ def three_level(w, torch, wl=WORKLOAD_THREE, fp64=True):
     return out
 
 
-def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int = 1) -> float:
+def algorithmic_bytes(family: str, V: int, Vc: int, nb: int, nv: int, nrhs: int = 1, link_rows: int = 3) -> float:
     """Bytes a launch must move at minimum (each operand read once, output written
-    once); with nrhs fields per launch the gauge data and P are read once."""
+    once); with nrhs fields per launch the gauge data and P are read once.
+    link_rows: rows of each link the Dslash reads (2 when it rebuilds the third)."""
     if family == "dslash_f64":
-        return (1152.0 + 384.0 * nrhs) * V   # links 576 + clover 576, in 192 + out 192 per field (FP64)
+        # links 4 x 3 rows x 48 B (two rows: 384), clover 576, in 192 + out 192 per field (FP64)
+        return (192.0 * link_rows + 576.0 + 384.0 * nrhs) * V
     if family == "dslash_f32":
-        return (576.0 + 192.0 * nrhs) * V    # links 288 + clover 288, in 96 + out 96 per field (FP32)
+        # links 4 x 3 rows x 24 B (two rows: 192), clover 288, in 96 + out 96 per field (FP32)
+        return (96.0 * link_rows + 288.0 + 192.0 * nrhs) * V
     if family.startswith("coarse_apply"):
         sb = {"coarse_apply_f64": 16, "coarse_apply_f32": 8, "coarse_apply_bf16": 4}[family]
         sv = 16 if family.endswith("f64") else 8
@@ -747,7 +750,7 @@ def kernel_mode(args):
             else:
                 ctx.prolong(0, xc, w.F32)
         n, ms = ctx.profile_stats(fam)
-    bpl = algorithmic_bytes(fam, V, V // 256, 24, 12, nr)
+    bpl = algorithmic_bytes(fam, V, V // 256, 24, 12, nr, link_rows=ctx.timers()["dslash_link_rows"])
     print(json.dumps({"family": fam, "nrhs": nr, "launches": n, "avg_ms": ms / max(n, 1), "bytes_per_launch": bpl,
                       "GB_s": bpl / (ms / max(n, 1)) / 1e6, "tuner": ctx.tune_table()}))
 
@@ -870,16 +873,20 @@ def main():
         table, table_iters = stats, sum(i["coarse_iters"] for i in infos)
     n, ms = stats[dom]
     avg_ms = ms / max(n, 1)
-    bpl = algorithmic_bytes(dom, V, Vc, nb, wl["nv"])
+    link_rows = ctx.timers()["dslash_link_rows"]
+    bpl = algorithmic_bytes(dom, V, Vc, nb, wl["nv"], link_rows=link_rows)
     achieved = bpl / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": counter_traffic(dom) if dom in TRAFFIC_SOURCES else None,
-                "launches": n, "avg_launch_ms": avg_ms, "bytes_per_launch": bpl}
+                "launches": n, "avg_launch_ms": avg_ms, "bytes_per_launch": bpl,
+                "bytes_per_site": bpl / V if dom.startswith("dslash") else None,
+                "dslash_link_rows": link_rows}
     # kernel table: from the warmup steps (every family timed there)
     kernel_table = {f: {"launches": table[f][0], "total_ms": table[f][1],
                         "avg_ms": table[f][1] / max(table[f][0], 1),
-                        "GB_s": algorithmic_bytes(f, V, Vc, nb, wl["nv"]) / (table[f][1] / max(table[f][0], 1)) / 1e6
+                        "GB_s": algorithmic_bytes(f, V, Vc, nb, wl["nv"], link_rows=link_rows) /
+                        (table[f][1] / max(table[f][0], 1)) / 1e6
                         if table[f][0] else None} for f in roof_families}
     n_cg, ms_cg = table["coarse_gmres_persistent"]
     kernel_table["coarse_gmres_persistent"] = {

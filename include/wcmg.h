@@ -349,8 +349,10 @@ int wcmg_tune_load(wcmg_ctx* ctx, const char* json);
 /* Per-phase timers in seconds: [0] setup total, [1] relaxation, [2] Gram-Schmidt,
  * [3] coarsening, [4] refinement, [5] last solve; [6] is a count: coarsest
  * GMRES solves that the single-launch form handed back to the multi-kernel
- * form after a grid-barrier timeout (0 in a healthy run).  n entries (<= 8)
- * are written. */
+ * form after a grid-barrier timeout (0 in a healthy run); [7] the link rows
+ * the fine Dslash reads per link: 2 when every link of the gauge field is
+ * SU(3) to 1e-12 (the third row is rebuilt as the conjugated cross product of
+ * the first two), else 3.  n entries (<= 8) are written. */
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
 
 /* Kernel timing: when enabled, launches of the named kernel family are

@@ -891,7 +891,8 @@ int wcmg_tune_load(wcmg_ctx* ctx, const char* json) {
 int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n) {
   return guarded(ctx, [&](Context& c) {
     require(out_host != nullptr && n >= 0, WCMG_ERR_ARG, "bad output");
-    for (int i = 0; i < n && i < 8; ++i) out_host[i] = i == 6 ? (double)c.cgp_fallbacks : c.timers[i];
+    for (int i = 0; i < n && i < 8; ++i)
+      out_host[i] = i == 6 ? (double)c.cgp_fallbacks : i == 7 ? (c.use_links2() ? 2.0 : 3.0) : c.timers[i];
   });
 }
 

@@ -181,8 +181,10 @@ struct FastDiv {
 struct SiteGeom {
   FastDiv divA, div_so[4], mod_b[4], div_sc[4], mod_Lc[4];
   uint32_t A = 1, so[4] = {1, 1, 1, 1}, sc[4] = {1, 1, 1, 1}, b[4] = {1, 1, 1, 1}, Lc[4] = {1, 1, 1, 1};
+  int anti = 0;  // antiperiodic fermion boundary in t (the sign on t-hops crossing it)
   SiteGeom() = default;
-  SiteGeom(const int L[4], const int blk[4]) {
+  SiteGeom(const int L[4], const int blk[4], int antiperiodic_t = 0) {
+    anti = antiperiodic_t;
     A = 1;
     uint32_t cs = 1;
     for (int m = 0; m < 4; ++m) {
@@ -209,6 +211,17 @@ struct SiteGeom {
     const uint32_t cstep = sc[MU] * A, cwrap = (Lc[MU] - 1) * cstep, owrap = (b[MU] - 1) * so[MU];
     fwd = om + 1 < b[MU] ? s + so[MU] : (cm + 1 < Lc[MU] ? s + cstep : s - cwrap) - owrap;
     bwd = om > 0 ? s - so[MU] : (cm > 0 ? s - cstep : s + cwrap) + owrap;
+  }
+  // as hop_sites, and whether s lies on the last (first) slice along MU
+  template <int MU>
+  __host__ __device__ void hop_sites_edge(uint32_t s, uint32_t& fwd, uint32_t& bwd, bool& last, bool& first) const {
+    const uint32_t c = divA.div(s), o = s - c * A;
+    const uint32_t om = mod_b[MU].mod(div_so[MU].div(o)), cm = mod_Lc[MU].mod(div_sc[MU].div(c));
+    const uint32_t cstep = sc[MU] * A, cwrap = (Lc[MU] - 1) * cstep, owrap = (b[MU] - 1) * so[MU];
+    fwd = om + 1 < b[MU] ? s + so[MU] : (cm + 1 < Lc[MU] ? s + cstep : s - cwrap) - owrap;
+    bwd = om > 0 ? s - so[MU] : (cm > 0 ? s - cstep : s + cwrap) + owrap;
+    last = om + 1 == b[MU] && cm + 1 == Lc[MU];
+    first = om == 0 && cm == 0;
   }
 };
 

@@ -189,6 +189,17 @@ struct Context {
   SiteGeom sgeo;  // the level-0 device site order as arithmetic (Dslash neighbours)
   // neighbours of the fine Dslash: site arithmetic, or the table (reserved[0] flag 32, the reference form)
   const SiteGeom* dslash_geo() const { return (p.reserved[0] & 32) ? nullptr : &sgeo; }
+  // two-row links of the fine Dslash (third row rebuilt), used when every link
+  // is SU(3) to 1e-12 and the site arithmetic is on; reserved[0] flag 64 keeps
+  // the full links (the reference form)
+  DevBuf U64c, U32c;
+  bool links_su3 = false;
+  bool use_links2() const { return links_su3 && !(p.reserved[0] & 96); }
+  template <typename R>
+  const cplx<R>* dslash_links2() const {
+    if (!use_links2()) return nullptr;
+    return sizeof(R) == 8 ? (const cplx<R>*)U64c.p : (const cplx<R>*)U32c.p;
+  }
   bool gauge_set = false, setup_done = false;
   // even-odd preconditioning: site parity (device order) and A^{-1} (packed)
   DevBuf par0, clovinv64, clovinv32;

@@ -261,7 +261,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
       for (long s = 0; s < G.V; ++s) nb_host[(d - 1) * G.V + s] = iperm[lex_neighbour(G.perm[s], G.L, d)];
     upload(G.nbr, nb_host);
     upload(perm0, G.perm);
-    sgeo = SiteGeom(G.L, b);
+    sgeo = SiteGeom(G.L, b, p.antiperiodic_t);
   }
   for (int l = 1; l < nlev; ++l) {
     LevelGeom& G = geo[l];
@@ -379,10 +379,10 @@ void Context::apply_op(int l, const cplx<R>* in, cplx<R>* out, int nrhs, const i
     prof.begin_kernel(fam);
     if (single)
       launch_wilson<float>((const cf32*)in, (cf32*)out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(),
-                           geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo());
+                           geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo(), dslash_links2<float>());
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                            geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo());
+                            geo[0].V, terms, nrhs, run, stream, dots, 0, nullptr, dslash_geo(), dslash_links2<double>());
     prof.end(fam, stream);
   } else {
     const int prec = store_prec_for(l, single);
@@ -401,10 +401,10 @@ void Context::residual0(const cplx<R>* b, const cplx<R>* x, cplx<R>* r, const in
   prof.begin_kernel(fam);
   if (single)
     launch_wilson<float>((const cf32*)x, (cf32*)r, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V,
-                         0x1ff, 1, run, stream, nullptr, 0, (const cf32*)b, dslash_geo());
+                         0x1ff, 1, run, stream, nullptr, 0, (const cf32*)b, dslash_geo(), dslash_links2<float>());
   else
     launch_wilson<double>((const cd64*)x, (cd64*)r, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                          geo[0].V, 0x1ff, 1, run, stream, nullptr, 0, (const cd64*)b, dslash_geo());
+                          geo[0].V, 0x1ff, 1, run, stream, nullptr, 0, (const cd64*)b, dslash_geo(), dslash_links2<double>());
   prof.end(fam, stream);
 }
 
@@ -425,6 +425,27 @@ void Context::set_gauge(const cd64* U) {
   launch_clover_build(U_lex.as<cd64>(), geo[0].L, p.c_sw, clover_lex.as<cd64>(), stream);
   launch_pack_links<double>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U64.as<cd64>(), stream);
   launch_pack_links<float>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U32.as<cf32>(), stream);
+  // two-row links for the Dslash when every link is SU(3) (third row = conj(row0 x row1))
+  {
+    const long nl = V0 * 4;
+    const int G = su3_defect_blocks(nl);
+    double* part = buf<double>("su3_defect", G);
+    launch_su3_defect(U_lex.as<cd64>(), nl, part, stream);
+    std::vector<double> h(G);
+    WCMG_HIP(hipMemcpyAsync(h.data(), part, G * sizeof(double), hipMemcpyDeviceToHost, stream));
+    sync();
+    double m = 0.0;
+    for (double d : h) m = d > m ? d : m;
+    links_su3 = m <= 1e-12;
+    if (links_su3) {
+      U64c.alloc(V0 * 24 * sizeof(cd64));
+      U32c.alloc(V0 * 24 * sizeof(cf32));
+      launch_pack_links2<double>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U64c.as<cd64>(),
+                                 stream);
+      launch_pack_links2<float>(U_lex.as<cd64>(), perm0.as<int>(), geo[0].L, p.antiperiodic_t, U32c.as<cf32>(),
+                                stream);
+    }
+  }
   pack_clover();
   gauge_set = true;
   setup_done = false;

@@ -133,7 +133,7 @@ void Context::dslash32_batch(const cf32* in, cf32* out, int B, const int* run, i
                          dots, stream);
     else
       launch_wilson<float>(in, out, U32.as<cf32>(), clov32.as<float>(), geo[0].nbr.as<int>(), geo[0].V, 0x1ff, B,
-                           run, stream, dots, rs, nullptr, dslash_geo());
+                           run, stream, dots, rs, nullptr, dslash_geo(), dslash_links2<float>());
   };
   int v = 0;
   if (dslash_per_rhs || B < 2) v = 0;
@@ -156,7 +156,7 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
       dslash32_batch((const cf32*)in, (cf32*)out, B, run, rs, nullptr);
     else
       launch_wilson<double>((const cd64*)in, (cd64*)out, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                            geo[0].V, 0x1ff, B, run, stream, nullptr, rs, nullptr, dslash_geo());
+                            geo[0].V, 0x1ff, B, run, stream, nullptr, rs, nullptr, dslash_geo(), dslash_links2<double>());
     if (!capturing) prof.end(fam, stream);
     return;
   }
@@ -204,7 +204,8 @@ void Context::mrB(int l, const cplx<R>* b, cplx<R>* x, int B, int steps, const i
         dslash32_batch((const cf32*)r, (cf32*)pp, B, run, rs, part);
       else
         launch_wilson<double>((const cd64*)r, (cd64*)pp, U64.as<cd64>(), clov64.as<double>(), geo[0].nbr.as<int>(),
-                              geo[0].V, 0x1ff, B, run, stream, part, rs, nullptr, dslash_geo());
+                              geo[0].V, 0x1ff, B, run, stream, part, rs, nullptr, dslash_geo(),
+                              dslash_links2<double>());
       launch_bdot_finish(part, G, 2, 2, B, dots, 1, 2, 0, run, rs, stream);
       launch_bmr_update<R>(x, r, pp, nn, dots, nn, B, run, rs, stream);
     }

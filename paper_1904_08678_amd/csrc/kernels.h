@@ -25,7 +25,14 @@ template <typename R>
 // neighbours from the site arithmetic of the level-0 device order instead of nbr.
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots = nullptr, int rs = 0,
-                   const cplx<R>* bsub = nullptr, const SiteGeom* geo = nullptr);
+                   const cplx<R>* bsub = nullptr, const SiteGeom* geo = nullptr, const cplx<R>* U2 = nullptr);
+// two-row links of the Dslash (U2 of launch_wilson, with geo) and the SU(3)
+// check that allows them: per-block maxima of |row2 - conj(row0 x row1)|
+template <typename R>
+void launch_pack_links2(const cd64* U, const int* perm, const int L[4], int antiperiodic, cplx<R>* out,
+                        hipStream_t st);
+int su3_defect_blocks(long n_links);
+void launch_su3_defect(const cd64* U, long n_links, double* part, hipStream_t st);
 int wilson_blocks(long V);
 // FP32 D on nrhs fields with the links and clover read once per launch; MR
 // partials (optional) at dots[2 * (r * wilson_blocks(V) + blk)]

@@ -250,24 +250,42 @@ __global__ void k_unpack_fermion(const cplx<Ti>* __restrict__ in, const int* __r
 // residual of in for the right-hand side bsub.
 // The two hops along MU (selected by the terms mask unless ALL), neighbours
 // from the site arithmetic (GEO) or from the table.
-template <typename R, int MU, bool GEO, bool ALL>
+// L2 (with GEO): two-row links U2 (hop_at2), the t-boundary sign of the
+// rebuilt third row from the site coordinates.
+template <typename R, int MU, bool GEO, bool ALL, bool L2>
 __device__ inline void hops_mu(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
                                const int* __restrict__ nbr, const SiteGeom& geo, long V, long s, int terms) {
   long yf, yb;
+  R sf = (R)1, sb = (R)1;
   if constexpr (GEO) {
     uint32_t f, b;
-    geo.hop_sites<MU>((uint32_t)s, f, b);
+    if constexpr (L2 && MU == 3) {
+      bool last, first;
+      geo.hop_sites_edge<MU>((uint32_t)s, f, b, last, first);
+      // U_t(s) carries the sign when s is on the last t slice, U_t(s - t) when s is on the first
+      if (geo.anti) {
+        sf = last ? (R)-1 : (R)1;
+        sb = first ? (R)-1 : (R)1;
+      }
+    } else {
+      geo.hop_sites<MU>((uint32_t)s, f, b);
+    }
     yf = f;
     yb = b;
   } else {
     yf = nbr[(long)(2 * MU) * V + s];
     yb = nbr[(long)(2 * MU + 1) * V + s];
   }
-  if (ALL || (terms & (1 << (2 * MU + 1)))) hop_at<R, MU, true>(acc, in, U, V, s, yf);
-  if (ALL || (terms & (1 << (2 * MU + 2)))) hop_at<R, MU, false>(acc, in, U, V, s, yb);
+  if constexpr (L2) {
+    if (ALL || (terms & (1 << (2 * MU + 1)))) hop_at2<R, MU, true>(acc, in, U, V, s, yf, sf);
+    if (ALL || (terms & (1 << (2 * MU + 2)))) hop_at2<R, MU, false>(acc, in, U, V, s, yb, sb);
+  } else {
+    if (ALL || (terms & (1 << (2 * MU + 1)))) hop_at<R, MU, true>(acc, in, U, V, s, yf);
+    if (ALL || (terms & (1 << (2 * MU + 2)))) hop_at<R, MU, false>(acc, in, U, V, s, yb);
+  }
 }
 
-template <typename R, bool ALL, bool GEO>
+template <typename R, bool ALL, bool GEO, bool L2>
 __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  const cplx<R>* __restrict__ U, const R* __restrict__ clov,
                                                  const int* __restrict__ nbr, SiteGeom geo, long V, int terms,
@@ -301,10 +319,10 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
       if (mu == 0) clover_chirality_p<R, 0>(acc, pin, clov, V, s);
       if (mu == 1) clover_chirality_p<R, 1>(acc, pin, clov, V, s);
     }
-    if (mu == 0) hops_mu<R, 0, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
-    else if (mu == 1) hops_mu<R, 1, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
-    else if (mu == 2) hops_mu<R, 2, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
-    else hops_mu<R, 3, GEO, ALL>(acc, in, U, nbr, geo, V, s, terms);
+    if (mu == 0) hops_mu<R, 0, GEO, ALL, L2>(acc, in, U, nbr, geo, V, s, terms);
+    else if (mu == 1) hops_mu<R, 1, GEO, ALL, L2>(acc, in, U, nbr, geo, V, s, terms);
+    else if (mu == 2) hops_mu<R, 2, GEO, ALL, L2>(acc, in, U, nbr, geo, V, s, terms);
+    else hops_mu<R, 3, GEO, ALL, L2>(acc, in, U, nbr, geo, V, s, terms);
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
@@ -557,32 +575,99 @@ INST_PACK(float, double)
 template <typename R, bool ALL>
 static void launch_wilson_t(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr,
                             const SiteGeom* geo, long V, int terms, int nrhs, const int* run, hipStream_t st,
-                            cd64* dots, int rs, const cplx<R>* bsub) {
+                            cd64* dots, int rs, const cplx<R>* bsub, const cplx<R>* U2) {
   const dim3 grid(item_rhs_grid(nblocks(V, 64), nrhs));
-  if (geo)
-    WCMG_LAUNCH((k_wilson<R, ALL, true>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, *geo, V, terms, nrhs,
-                dots, run, rs, bsub);
-  else
-    WCMG_LAUNCH((k_wilson<R, ALL, false>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, SiteGeom(), V, terms,
+  if (geo && U2)
+    WCMG_LAUNCH((k_wilson<R, ALL, true, true>), grid, dim3(kBlock), 0, st, in, out, U2, clov, nbr, *geo, V, terms,
                 nrhs, dots, run, rs, bsub);
+  else if (geo)
+    WCMG_LAUNCH((k_wilson<R, ALL, true, false>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, *geo, V, terms,
+                nrhs, dots, run, rs, bsub);
+  else
+    WCMG_LAUNCH((k_wilson<R, ALL, false, false>), grid, dim3(kBlock), 0, st, in, out, U, clov, nbr, SiteGeom(), V,
+                terms, nrhs, dots, run, rs, bsub);
 }
 
 template <typename R>
 void launch_wilson(const cplx<R>* in, cplx<R>* out, const cplx<R>* U, const R* clov, const int* nbr, long V,
                    int terms, int nrhs, const int* run, hipStream_t st, cd64* dots, int rs, const cplx<R>* bsub,
-                   const SiteGeom* geo) {
+                   const SiteGeom* geo, const cplx<R>* U2) {
   require(!bsub || (!dots && terms == 0x1ff), WCMG_ERR_ARG, "Dslash: the residual form takes the whole operator");
   require(!geo || V < (1L << 31), WCMG_ERR_DIMS, "Dslash: lattice too large for 32-bit site arithmetic");
   if (terms == 0x1ff)
-    launch_wilson_t<R, true>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub);
+    launch_wilson_t<R, true>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub, U2);
   else
-    launch_wilson_t<R, false>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub);
+    launch_wilson_t<R, false>(in, out, U, clov, nbr, geo, V, terms, nrhs, run, st, dots, rs, bsub, U2);
   WCMG_CHECK_LAUNCH();
 }
 template void launch_wilson<double>(const cd64*, cd64*, const cd64*, const double*, const int*, long, int, int,
-                                    const int*, hipStream_t, cd64*, int, const cd64*, const SiteGeom*);
+                                    const int*, hipStream_t, cd64*, int, const cd64*, const SiteGeom*, const cd64*);
 template void launch_wilson<float>(const cf32*, cf32*, const cf32*, const float*, const int*, long, int, int,
-                                   const int*, hipStream_t, cd64*, int, const cf32*, const SiteGeom*);
+                                   const int*, hipStream_t, cd64*, int, const cf32*, const SiteGeom*, const cf32*);
+
+// Two-row link storage (the Dslash's): rows 0 and 1 of every U_mu(s), device
+// site order, the antiperiodic sign folded in as in k_pack_links, in 16-byte
+// chunks [mu][6/K][V][K] of K = 16 / sizeof(cplx<R>) complex values.
+template <typename R>
+__global__ void k_pack_links2(const cd64* __restrict__ U, const int* __restrict__ perm, long V, int Lt, long Vs,
+                              int antiperiodic, cplx<R>* __restrict__ out) {
+  constexpr int K = 16 / sizeof(cplx<R>);
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  const long x = perm[s];
+  const bool last_t = (x / Vs) == Lt - 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    const double sg = (mu == 3 && antiperiodic && last_t) ? -1.0 : 1.0;
+    for (int e = 0; e < 6; ++e) {
+      const cd64 u = U[(x * 4 + mu) * 9 + e];
+      out[((long)(mu * (6 / K) + e / K) * V + s) * K + e % K] = mkc((R)(sg * u.re), (R)(sg * u.im));
+    }
+  }
+}
+
+// Largest deviation of row 2 from conj(row0 x row1) over the links in each
+// block of 256 (0 for SU(3) links up to rounding); part[blockIdx.x].
+__global__ void k_su3_defect(const cd64* __restrict__ U, long n_links, double* __restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (e < n_links) {
+    const cd64* u = U + e * 9;
+    const cd64 r2[3] = {cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4]))),
+                        cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5]))),
+                        cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3])))};
+    for (int c = 0; c < 3; ++c) {
+      const cd64 t = csub(u[6 + c], r2[c]);
+      d = fmax(d, fmax(fabs(t.re), fabs(t.im)));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, red[w]);
+    part[blockIdx.x] = m;
+  }
+}
+
+template <typename R>
+void launch_pack_links2(const cd64* U, const int* perm, const int L[4], int antiperiodic, cplx<R>* out,
+                        hipStream_t st) {
+  const long V = (long)L[0] * L[1] * L[2] * L[3];
+  const long Vs = (long)L[0] * L[1] * L[2];
+  hipLaunchKernelGGL(k_pack_links2<R>, dim3(nblocks(V)), dim3(kBlock), 0, st, U, perm, V, L[3], Vs, antiperiodic,
+                     out);
+  WCMG_CHECK_LAUNCH();
+}
+template void launch_pack_links2<double>(const cd64*, const int*, const int*, int, cd64*, hipStream_t);
+template void launch_pack_links2<float>(const cd64*, const int*, const int*, int, cf32*, hipStream_t);
+
+int su3_defect_blocks(long n_links) { return (int)nblocks(n_links); }
+void launch_su3_defect(const cd64* U, long n_links, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_su3_defect, dim3(nblocks(n_links)), dim3(kBlock), 0, st, U, n_links, part);
+  WCMG_CHECK_LAUNCH();
+}
 
 int wilson_blocks(long V) { return (int)nblocks(V, 64); }
 

@@ -97,6 +97,36 @@ __device__ inline void hop_at(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in
   hop_core<R, MU, FWD>(acc, p, u);
 }
 
+// The hop from the neighbour site y of s with two-row link storage: rows 0
+// and 1 of U in 16-byte chunks ([mu][6/K][V][K], K complex per chunk), row 2
+// rebuilt as conj(row0 x row1) (U in SU(3)) times sg, the sign that the
+// packing folded into rows 0 and 1 (the antiperiodic t boundary).
+template <typename R, int MU, bool FWD>
+__device__ inline void hop_at2(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U2,
+                               long V, long s, long y, R sg) {
+  cplx<R> p[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = in[(long)k * V + y];
+  const long ls = FWD ? s : y;
+  cplx<R> u[9];
+  if constexpr (sizeof(R) == 4) {
+    const float4* q = (const float4*)U2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 f = q[(long)(MU * 3 + c) * V + ls];
+      u[2 * c] = mkc(f.x, f.y);
+      u[2 * c + 1] = mkc(f.z, f.w);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = U2[(long)(MU * 6 + e) * V + ls];
+  }
+  u[6] = cscale(sg, cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4]))));
+  u[7] = cscale(sg, cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5]))));
+  u[8] = cscale(sg, cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3]))));
+  hop_core<R, MU, FWD>(acc, p, u);
+}
+
 template <typename R, int MU, bool FWD>
 __device__ inline void hop(cplx<R> (&acc)[12], const cplx<R>* __restrict__ in, const cplx<R>* __restrict__ U,
                            const int* __restrict__ nbr, long V, long s) {

@@ -392,10 +392,11 @@ class Context:
         self._chk(lib().wcmg_tune_load(self.h, json.dumps(table).encode()))
 
     def timers(self):
-        out = (C.c_double * 7)()
-        self._chk(lib().wcmg_timers(self.h, out, 7))
+        out = (C.c_double * 8)()
+        self._chk(lib().wcmg_timers(self.h, out, 8))
         d = dict(zip(["setup", "relax", "gram_schmidt", "coarsen", "refine", "solve"], list(out)[:6]))
         d["coarse_solve_fallbacks"] = int(out[6])
+        d["dslash_link_rows"] = int(out[7])
         return d
 
     def profile(self, family, enable=True):

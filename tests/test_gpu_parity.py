@@ -560,14 +560,36 @@ def test_dslash_site_arithmetic_equals_neighbour_table(L, block, levels):
     V = int(np.prod(L))
     psi = syn.complex_gaussian((3, V, 4, 3), 232)
     outs = []
-    for flags in (0, 32):
+    for flags in (64, 32):  # full links: site arithmetic against the table
         ctx = w.Context(dims=L, m0=-0.08, n_levels=levels, block=(block,), n_vec=(4,), reserved=(flags,))
         ctx.set_gauge(dev(U))
+        assert ctx.timers()["dslash_link_rows"] == 3
         outs.append((host(ctx.apply_D(0, dev(psi), w.F64)), host(ctx.apply_D(0, dev(psi.astype(np.complex64)), w.F32))))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     H = oracle.Hierarchy(L, U, m0=-0.08, n_levels=1, blocks=())
     ref = np.stack([H.apply(0, psi[r]).reshape(V, 4, 3) for r in range(3)])
     assert rel(outs[0][0], ref) < 1e-13
+
+
+@pytest.mark.parametrize("antiperiodic", [1, 0])
+def test_dslash_two_row_links(antiperiodic):
+    """SU(3) links: the Dslash reads two rows per link and rebuilds the third
+    (conjugated cross product, the t-boundary sign from the site coordinates);
+    FP64 to 1e-13 and FP32 to 1e-5 against the oracle, periodic and
+    antiperiodic t, with the residual form inside a solve.  U(3) links (a
+    phase on every link) keep all three rows and stay exact."""
+    w = wc()
+    L, block = (4, 4, 4, 8), (2, 2, 2, 2)
+    V = int(np.prod(L))
+    psi = syn.complex_gaussian((2, V, 4, 3), 272)
+    for U, rows in ((syn.gauge_field(L, 0.3, 271), 2), (syn.gauge_field(L, 0.3, 271) * np.exp(0.3j), 3)):
+        ctx = w.Context(dims=L, m0=-0.08, n_levels=2, block=(block,), n_vec=(4,), antiperiodic_t=antiperiodic)
+        ctx.set_gauge(dev(U))
+        assert ctx.timers()["dslash_link_rows"] == rows
+        H = oracle.Hierarchy(L, U, m0=-0.08, n_levels=1, blocks=(), antiperiodic=antiperiodic)
+        ref = np.stack([H.apply(0, psi[r]).reshape(V, 4, 3) for r in range(2)])
+        assert rel(host(ctx.apply_D(0, dev(psi), w.F64)), ref) < 1e-13
+        assert rel(host(ctx.apply_D(0, dev(psi.astype(np.complex64)), w.F32)), ref) < 1e-5
 
 
 def test_coarse_op_get_set_precisions():
