@@ -224,12 +224,28 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
             byts = (9.0 * nb * nb * sb + 2.0 * nb * nrhs_batch * 8) * Vc
             flops = 8.0 * 9 * nb * nb * nrhs_batch * Vc
             rec = {}
+            # every matrix-core tile forced, then the tuned choice (the default)
+            op.set_kernel(2)
+            tiles = {}
+            for tile in (0, 4, 8, 16, 5, 9):
+                if tile and dims[0] % (tile & ~1):
+                    continue
+                op.set_tile(tile)
+                op.time(x, y, reps=2)
+                tms = op.time(x, y, reps=max(3, reps // 2))
+                tiles[str(tile)] = {"ms": tms, "frac_hbm": byts / tms / 1e6 / HBM_PEAK_GBS}
+            op.set_tile(-1)
             for kern, kname in ((2, "matrix_cores"), (1, "vector")):
                 op.set_kernel(kern)
                 op.time(x, y, reps=2)
                 ms = op.time(x, y, reps=max(3, reps // 2))
                 rec[kname] = {"ms": ms, "GB_s": byts / ms / 1e6, "frac_hbm": byts / ms / 1e6 / HBM_PEAK_GBS,
                               "TFLOP_s": flops / ms / 1e9}
+            tab = op.tune_table()
+            ent = [v for k, v in tab.items() if "coarse_mfma_tile" in k]
+            rec["matrix_cores"]["tile"] = (0, 4, 8, 16, 5, 9)[ent[0]["choice"]] if ent else None
+            rec["matrix_cores"]["tiles"] = tiles
+            rec["matrix_cores"]["tuning_table"] = tab
             rec["bytes_per_launch"] = byts
             rec["flops_per_launch"] = flops
             batched[name] = rec

@@ -435,6 +435,24 @@ int wcmg_coarse_apply_noalloc(wcmg_coarse* op, const void* in, void* out, int nr
  * (Sec. 2.2, Sec. 4).  Switching to or from 3 must precede wcmg_coarse_set
  * (WCMG_ERR_STATE otherwise).  WCMG_ERR_ARG when unsupported. */
 int wcmg_coarse_set_kernel(wcmg_coarse* op, int kernel);
+/* Tile of the matrix-core kernel (kernel 2, or 0 with >= 4 right-hand sides):
+ *   -1 (default) tuned: on the first apply of each batch width the operator
+ *      times every tile that fits and keeps the fastest (identical results);
+ *    0 one wave per coarse site, neighbour vectors read straight from memory;
+ *    4, 8, 16 that many consecutive sites of one x-row per workgroup, the
+ *      neighbour vectors of each direction staged once in LDS for all of them
+ *      and the outputs written through LDS as whole rows;
+ *    5, 9 4 or 8 sites per workgroup with the staged neighbour vectors and
+ *      each wave storing its own outputs.
+ * The site count must divide the lattice's x extent (WCMG_ERR_ARG otherwise,
+ * or at apply time when the stage for that many right-hand sides exceeds
+ * 160 KB).  Every tile gives the same result, bit for bit. */
+int wcmg_coarse_set_tile(wcmg_coarse* op, int tile);
+/* The operator's tile choices as JSON text (format of wcmg_tune_table, keys
+ * "<arch> coarse_mfma_tile prec=.. Vc=.. Lx=.. nb=.. nrhs=..", choice =
+ * index into the tiles {0, 4, 8, 16, 5, 9}, ms = measured mean per tile, -1
+ * where it does not fit).  Same buffer contract as wcmg_tune_table. */
+int wcmg_coarse_tune_table(wcmg_coarse* op, char* buf, int len, int* needed);
 /* Time `reps` back-to-back applies between HIP events on the op's stream;
  * *avg_ms receives the mean launch duration. */
 int wcmg_coarse_time(wcmg_coarse* op, const void* in, void* out, int nrhs, int reps, double* avg_ms);

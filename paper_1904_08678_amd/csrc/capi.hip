@@ -939,6 +939,7 @@ void* scratch_address() {
 
 struct wcmg_coarse {
   CoarseOp op;
+  Tuner tuner;  // matrix-core tile choices of this operator
   int store = WCMG_F32;
   int kernel = 0;
   hipStream_t stream = nullptr;
@@ -974,6 +975,7 @@ int wcmg_coarse_create(const int32_t dims[4], int nb, int store_prec, void* stre
   try {
     int L[4] = {dims[0], dims[1], dims[2], dims[3]};
     h->op.init_geometry(L, nb, (hipStream_t)stream);
+    h->op.tuner = &h->tuner;
     h->store = store_prec;
     h->stream = (hipStream_t)stream;
   } catch (const Error& e) {
@@ -1022,6 +1024,24 @@ int wcmg_coarse_apply_noalloc(wcmg_coarse* h, const void* in, void* out, int nrh
   return guarded_c(h, [&](wcmg_coarse& o) {
     require(in && out && nrhs >= 1, WCMG_ERR_ARG, "bad fields");
     o.op.apply_batch_scratch(o.store, in, out, nrhs, o.kernel, scratch_address(), kNoAllocScratchBytes, o.stream);
+  });
+}
+
+int wcmg_coarse_set_tile(wcmg_coarse* h, int tile) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    require(tile == -1 || tile == 0 || tile == 4 || tile == 8 || tile == 16 || tile == 5 || tile == 9, WCMG_ERR_ARG,
+            "tile must be -1 (tuned), 0, 4, 5, 8, 9 or 16");
+    require(tile <= 0 || o.op.L[0] % (tile & ~1) == 0, WCMG_ERR_ARG, "the tile must divide the lattice's x extent");
+    o.op.mfma_tile = tile;
+  });
+}
+
+int wcmg_coarse_tune_table(wcmg_coarse* h, char* buf, int len, int* needed) {
+  return guarded_c(h, [&](wcmg_coarse& o) {
+    const std::string j = o.tuner.to_json();
+    if (needed) *needed = (int)j.size() + 1;
+    require(buf && len >= (int)j.size() + 1, WCMG_ERR_ARG, "tuning table does not fit the buffer");
+    std::memcpy(buf, j.c_str(), j.size() + 1);
   });
 }
 

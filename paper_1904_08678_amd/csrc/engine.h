@@ -84,6 +84,11 @@ struct CoarseOp {
   void invalidate() {
     for (int q = 0; q < 3; ++q) fresh[q] = mfma_fresh[q] = fresh5[q] = false;
   }
+  // matrix-core tile: -1 tuned (or the default when no tuner is attached), 0
+  // one wave per site, 4/8/16 sites per workgroup with LDS-staged neighbours
+  int mfma_tile = -1;
+  struct Tuner* tuner = nullptr;
+  int choose_tile(int prec, const void* in, void* out, int nrhs, const int* run, int run_stride, hipStream_t st);
   // nrhs right-hand sides (RHS-major); kernel: 0 auto, 1 per-row vector kernel, 2 matrix cores
   void apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,
                    hipStream_t st);
@@ -114,6 +119,10 @@ using BatchOp = std::function<void(const cplx<R>*, cplx<R>*, const int*, int)>;
 // times every applicable kernel variant once on the live operands, keeps the
 // fastest, and reuses that choice for the rest of the context's life.  The
 // table can be saved to and loaded from a small JSON file.
+// Architecture name of the current device (e.g. "gfx950"), the first part of
+// every tuning key.
+const std::string& device_arch();
+
 struct Tuner {
   bool enabled = true;
   std::map<std::string, int> choice;
@@ -123,7 +132,9 @@ struct Tuner {
   // variant for key: looked up, or measured with run(v) for v < nvar (each
   // candidate is launched reps + 1 times on stream st; its output is that of
   // a normal launch, so the caller's result is unaffected)
-  int pick(const std::string& key, int nvar, const std::function<void(int)>& run, hipStream_t st, int fallback);
+  // (variants with ok(v) false are not run; their time is recorded as -1)
+  int pick(const std::string& key, int nvar, const std::function<void(int)>& run, hipStream_t st, int fallback,
+           const std::function<bool(int)>& ok = nullptr);
   std::string to_json() const;
   void from_json(const std::string& text);
 };

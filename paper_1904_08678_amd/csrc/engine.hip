@@ -131,6 +131,43 @@ void CoarseOp::refresh_mfma(int prec, hipStream_t st) {
   mfma_fresh[prec] = true;
 }
 
+// Matrix-core tile candidates, in the order of the tuner's variant index:
+// one wave per site; 4, 8, 16 sites per workgroup with neighbours and outputs
+// staged in LDS; 4 or 8 sites with staged neighbours and per-wave stores.
+static const int kMfmaTiles[6] = {0, 4, 8, 16, 5, 9};
+constexpr int kNumMfmaTiles = 6;
+
+int CoarseOp::choose_tile(int prec, const void* in, void* out, int k, const int* run, int run_stride,
+                          hipStream_t st) {
+  auto ok = [&](int tile) { return mfma_tile_ok(tile, nb, V, L[0], k); };
+  if (mfma_tile >= 0) {
+    require(ok(mfma_tile), WCMG_ERR_ARG,
+            "matrix-core tile " + std::to_string(mfma_tile) + " does not fit this lattice or batch");
+    return mfma_tile;
+  }
+  const int dflt = ok(4) ? 1 : 0;  // variant index of the untuned default
+  if (!tuner) return kMfmaTiles[dflt];
+  const std::string key = device_arch() + " coarse_mfma_tile prec=" + std::to_string(prec) +
+                          " Vc=" + std::to_string(V) + " Lx=" + std::to_string(L[0]) + " nb=" + std::to_string(nb) +
+                          " nrhs=" + std::to_string(k);
+  auto it = tuner->choice.find(key);
+  if (it != tuner->choice.end()) {
+    const int v = it->second;
+    return (v >= 0 && v < kNumMfmaTiles && ok(kMfmaTiles[v])) ? kMfmaTiles[v] : kMfmaTiles[dflt];
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  WCMG_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone || !tuner->enabled) return kMfmaTiles[dflt];
+  const int v = tuner->pick(
+      key, kNumMfmaTiles,
+      [&](int v) {
+        launch_coarse_apply_mfma(prec, nb, mfma[prec].p, (const cf32*)in, (cf32*)out, nbr.as<int>(), V, k, run,
+                                 run_stride, st, kMfmaTiles[v], L[0]);
+      },
+      st, dflt, [&](int v) { return ok(kMfmaTiles[v]); });
+  return kMfmaTiles[v];
+}
+
 void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int kernel, const int* run, int run_stride,
                            hipStream_t st) {
   const bool can_mfma = prec != WCMG_F64 && mfma_supported_nb(nb);
@@ -141,8 +178,11 @@ void CoarseOp::apply_batch(int prec, const void* in, void* out, int nrhs, int ke
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
       const int k = std::min(16, nrhs - r0);
       const long off = (long)r0 * V * nb;
-      launch_coarse_apply_mfma(prec, nb, mfma[prec].p, (const cf32*)in + off, (cf32*)out + off, nbr.as<int>(), V, k,
-                               run ? run + (long)r0 * run_stride : nullptr, run_stride, st);
+      const cf32* i0 = (const cf32*)in + off;
+      cf32* o0 = (cf32*)out + off;
+      const int* run0 = run ? run + (long)r0 * run_stride : nullptr;
+      const int tile = choose_tile(prec, i0, o0, k, run0, run_stride, st);
+      launch_coarse_apply_mfma(prec, nb, mfma[prec].p, i0, o0, nbr.as<int>(), V, k, run0, run_stride, st, tile, L[0]);
     }
   } else {
     apply(prec, in, out, 0x1ff, 0, nrhs, run, st, run_stride);
@@ -270,6 +310,7 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
     cop.emplace_back(new CoarseOp());
     cop.back()->init_geometry(G.L, G.ns, stream);
     cop.back()->five = p.coarse_points == 5;
+    cop.back()->tuner = &tuner;
     // coarse level vectors and operator share the lexicographic neighbour table
   }
   // transfers

@@ -11,6 +11,8 @@
 // replayed; the captured cycle then runs without host checks (inner solves run
 // their full iteration limits, predicated off once converged).
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cmath>
 
 #include "engine.h"
@@ -27,8 +29,25 @@ Tuner::~Tuner() {
     if (e) (void)hipEventDestroy(e);
 }
 
+const std::string& device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  int dev = 0;
+  WCMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = names.find(dev);
+  if (it == names.end()) {
+    hipDeviceProp_t prop;
+    WCMG_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string a = prop.gcnArchName;
+    a = a.substr(0, a.find(':'));  // drop feature suffixes (":sramecc+:xnack-")
+    it = names.emplace(dev, a).first;
+  }
+  return it->second;
+}
+
 int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>& run, hipStream_t st,
-                int fallback) {
+                int fallback, const std::function<bool(int)>& ok) {
   auto it = choice.find(key);
   if (it != choice.end()) return it->second;
   if (!enabled || nvar <= 1) return fallback;
@@ -40,8 +59,9 @@ int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>
     WCMG_HIP(hipEventCreate(&ev[1]));
   }
   constexpr int reps = 3;
-  std::vector<double> t(nvar, 0.0);
+  std::vector<double> t(nvar, -1.0);
   for (int v = 0; v < nvar; ++v) {
+    if (ok && !ok(v)) continue;
     run(v);  // warm: first-touch, caches, code load
     WCMG_HIP(hipEventRecord(ev[0], st));
     for (int q = 0; q < reps; ++q) run(v);
@@ -51,9 +71,10 @@ int Tuner::pick(const std::string& key, int nvar, const std::function<void(int)>
     WCMG_HIP(hipEventElapsedTime(&e, ev[0], ev[1]));
     t[v] = e / reps;
   }
-  int best = 0;
-  for (int v = 1; v < nvar; ++v)
-    if (t[v] < t[best]) best = v;
+  int best = -1;
+  for (int v = 0; v < nvar; ++v)
+    if (t[v] >= 0.0 && (best < 0 || t[v] < t[best])) best = v;
+  if (best < 0) best = fallback;
   choice[key] = best;
   ms[key] = t;
   kernel_timing() = armed;
@@ -143,7 +164,7 @@ void Context::dslash32_batch(const cf32* in, cf32* out, int B, const int* run, i
 }
 
 std::string Context::dslash_key(int B) const {
-  return "dslash_f32 V=" + std::to_string(geo[0].V) + " nrhs=" + std::to_string(B);
+  return device_arch() + " dslash_f32 V=" + std::to_string(geo[0].V) + " nrhs=" + std::to_string(B);
 }
 
 template <typename R>
@@ -167,8 +188,8 @@ void Context::apply_opB(int l, const cplx<R>* in, cplx<R>* out, int B, const int
   if (can_mfma && coarse_kernel == 2) mfma = true;
   else if (can_mfma && coarse_kernel == 0) {
     C.refresh_mfma(prec, stream);
-    const std::string key = "coarse_apply prec=" + std::to_string(prec) + " Vc=" + std::to_string(C.V) +
-                            " nb=" + std::to_string(C.nb) + " nrhs=" + std::to_string(B);
+    const std::string key = device_arch() + " coarse_apply prec=" + std::to_string(prec) +
+                            " Vc=" + std::to_string(C.V) + " nb=" + std::to_string(C.nb) + " nrhs=" + std::to_string(B);
     if (capturing) mfma = tuner.choice.count(key) ? tuner.choice[key] == 1 : B >= 4;
     else
       mfma = tuner.pick(key, 2, [&](int v) { C.apply_batch(prec, in, out, B, v == 1 ? 2 : 1, run, rs, stream); },

@@ -90,8 +90,14 @@ void launch_coarse_apply5(int prec, const void* blk, const void* in, void* out, 
 bool mfma_supported_nb(int nb);
 size_t mfma_block_bytes(long Vc, int nb, int prec);
 void launch_blocks_to_mfma(const cd64* src, long Vc, int nb, int prec, void* dst, hipStream_t st);
+// tile 0: one wave per site, neighbour vectors read straight from memory;
+// tile 4, 8, 16: workgroups of that many consecutive sites of one x-row with the
+// neighbour vectors and the outputs staged in LDS; tile 5, 9: 4 or 8 sites with
+// staged neighbour vectors and per-wave output stores (nbr must be the
+// lexicographic table of a lattice of x extent Lx, which the site count divides)
 void launch_coarse_apply_mfma(int prec, int nb, const void* blk, const cf32* in, cf32* out, const int* nbr, long Vc,
-                              int nrhs, const int* run, int run_stride, hipStream_t st);
+                              int nrhs, const int* run, int run_stride, hipStream_t st, int tile = 0, int Lx = 0);
+bool mfma_tile_ok(int tile, int nb, long Vc, int Lx, int nrhs);
 
 // ---- transfer and coarsening (transfer.hip)
 bool supported_nb(int nb);

@@ -119,6 +119,8 @@ def lib():
         l.wcmg_coarse_apply.argtypes = [vp, vp, vp, ip]
         l.wcmg_coarse_apply_noalloc.argtypes = [vp, vp, vp, ip]
         l.wcmg_coarse_set_kernel.argtypes = [vp, ip]
+        l.wcmg_coarse_set_tile.argtypes = [vp, ip]
+        l.wcmg_coarse_tune_table.argtypes = [vp, C.c_char_p, ip, C.POINTER(C.c_int)]
         l.wcmg_coarse_time.argtypes = [vp, vp, vp, ip, ip, C.POINTER(C.c_double)]
         l.wcmg_coarse_last_error.argtypes = [vp]
         l.wcmg_coarse_last_error.restype = C.c_char_p
@@ -504,6 +506,21 @@ class CoarseOperator:
         kernel on five-point storage (set before `set`; the blocks must be
         sigma3-hermitian, as every Galerkin coarse operator is)."""
         self._chk(lib().wcmg_coarse_set_kernel(self.h, int(kernel)))
+
+    def set_tile(self, tile: int):
+        """Matrix-core tile: -1 tuned (default), 0 one wave per site, 4/8/16
+        sites of one x-row per workgroup with LDS-staged neighbour vectors and
+        outputs, 5/9 the 4- and 8-site tiles with per-wave output stores."""
+        self._chk(lib().wcmg_coarse_set_tile(self.h, int(tile)))
+
+    def tune_table(self) -> dict:
+        """This operator's tile choices: {configuration: {"choice": v, "ms": [...]}},
+        v indexing the tiles (0, 4, 8, 16, 5, 9)."""
+        need = C.c_int(0)
+        lib().wcmg_coarse_tune_table(self.h, None, 0, C.byref(need))
+        buf = C.create_string_buffer(max(need.value, 1))
+        self._chk(lib().wcmg_coarse_tune_table(self.h, buf, len(buf), C.byref(need)))
+        return json.loads(buf.value.decode())
 
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         nrhs = x.numel() // (self.Vc * self.nb)

@@ -188,11 +188,15 @@ def test_autotuner_table_and_forced_variants():
     x, info, st = ctx.solve_batched(dev(b))
     assert st == 0
     table = ctx.tune_table()
-    dkeys = [k for k in table if k.startswith("dslash_f32")]
-    ckeys = [k for k in table if k.startswith("coarse_apply")]
+    # keys name the device architecture first ("gfx950 dslash_f32 V=...")
+    dkeys = [k for k in table if k.split(" ")[1] == "dslash_f32"]
+    ckeys = [k for k in table if k.split(" ")[1] == "coarse_apply"]
+    tkeys = [k for k in table if k.split(" ")[1] == "coarse_mfma_tile"]
     assert dkeys and ckeys, table
     for k in dkeys + ckeys:
         assert table[k]["choice"] in (0, 1) and len(table[k]["ms"]) == 2
+    for k in tkeys:  # tiles 0, 4, 8, 16, 5, 9 on the 2^4 coarse lattice: only 0 fits
+        assert table[k]["choice"] == 0 and [m >= 0 for m in table[k]["ms"]] == [True] + [False] * 5
     base = [i["outer_iters"] for i in info]
     for v in (0, 1):
         c2, _, _ = _mixed_pair(L, 771, w.F32)
@@ -237,3 +241,36 @@ def test_ragged_coarse_apply(store):
     assert w.coarse_time_ragged(ops, ins, reps=3) > 0
     with pytest.raises(w.WcmgError):
         w.coarse_apply_ragged([ops[0], w.CoarseOperator((2, 2, 2, 2), 16, st)], ins[:1] * 2)
+
+
+@pytest.mark.parametrize("tile", [4, 8, 5])
+def test_batched_mfma_tile_forced_through_tuning_table(tile):
+    """The batched solve with the coarse level's matrix-core tile forced through
+    the tuning table (one wave per site against 4 or 8 sites of an x-row per
+    workgroup with LDS-staged neighbours), right-hand sides dropping out of the
+    launches as they converge: identical iterates, hence identical solutions and
+    iteration counts."""
+    import torch
+    w = wc()
+    L, block = (16, 8, 4, 4), (2, 2, 2, 2)
+    V = int(np.prod(L))
+    Lc = tuple(l // k for l, k in zip(L, block))
+    Vc = int(np.prod(Lc))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    b = syn.complex_gaussian((6, V, 4, 3), 353)
+    b[1] = syn.point_sources(V, site=21)[4]  # converges at another iteration than the Gaussian sources
+    out = []
+    for t in (0, tile):
+        ctx, H, U = make_pair(L, 0.3, 351, m0=-0.05, blocks=(block,), nv=(8,), cycle_prec=w.F32,
+                              coarse_store_prec=w.F32, setup_prec=w.F32)
+        ctx.set_null_vectors(0, dev(syn.complex_gaussian((8, V, 12), 352)))
+        ctx.setup()
+        key = "%s coarse_mfma_tile prec=%d Vc=%d Lx=%d nb=16 nrhs=6" % (arch, w.F32, Vc, Lc[0])
+        ctx.tune_load({key: {"choice": (0, 4, 8, 16, 5, 9).index(t)}})
+        x, info, st = ctx.solve_batched(dev(b), kernel="mfma")
+        assert st == 0
+        assert ctx.tune_table()[key]["choice"] == (0, 4, 8, 16, 5, 9).index(t)
+        out.append((host(x), [i["outer_iters"] for i in info]))
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.all(residuals(H, b, out[1][0]) <= 1.01e-10)

@@ -548,6 +548,47 @@ def test_coarse_apply_matrix_cores_parity(Lc, nb, nrhs):
         assert rel(got, got1) < 1e-5
 
 
+@pytest.mark.parametrize("Lc,nb,nrhs", [((16, 2, 2, 2), 24, 12), ((8, 3, 2, 3), 16, 5), ((4, 2, 2, 2), 40, 16),
+                                         ((8, 2, 2, 2), 8, 3), ((16, 2, 2, 2), 32, 16), ((8, 2, 2, 3), 24, 1)])
+def test_coarse_apply_mfma_tiles(Lc, nb, nrhs):
+    """Matrix-core tiles: one wave per site (tile 0) and 4, 8 or 16 sites of an
+    x-row per workgroup with the neighbour vectors staged in LDS give the same
+    result bit for bit (same products in the same order), with the outputs
+    stored through LDS (4, 8, 16) or per wave (5, 9); tile 0 against the
+    oracle; tiles that do not divide Lx are refused; the tuned default records
+    every tile that fits and picks one of them."""
+    w = wc()
+    Vc = int(np.prod(Lc))
+    blocks = syn.complex_gaussian((Vc, 9, nb, nb), 331)
+    phi = syn.complex_gaussian((nrhs, Vc, nb), 332)
+    x = dev(phi.astype(np.complex64))
+    for store in (w.F32, w.BF16):
+        op = w.CoarseOperator(Lc, nb, store)
+        op.set(dev(blocks))
+        op.set_kernel(2)
+        op.set_tile(0)
+        base = host(op.apply(x))
+        ref = oracle.coarse_apply(Lc, blocks if store == w.F32 else bf16_round(blocks), phi)
+        assert rel(base, ref) < 1e-5
+        for tile in (4, 8, 16, 5, 9):
+            if Lc[0] % (tile & ~1):
+                with pytest.raises(w.WcmgError):
+                    op.set_tile(tile)
+                continue
+            op.set_tile(tile)
+            got = host(op.apply(x))
+            assert np.array_equal(got, base), (store, tile, rel(got, base))
+        op.set_tile(-1)
+        got = host(op.apply(x))
+        assert np.array_equal(got, base)
+        table = op.tune_table()
+        keys = [k for k in table if "coarse_mfma_tile" in k and ("nrhs=%d" % min(nrhs, 16)) in k]
+        assert len(keys) == 1, table
+        ent = table[keys[0]]
+        fits = [t == 0 or Lc[0] % (t & ~1) == 0 for t in (0, 4, 8, 16, 5, 9)]
+        assert [m >= 0 for m in ent["ms"]] == fits and fits[ent["choice"]], ent
+
+
 @pytest.mark.parametrize("L,block,levels", [((8, 4, 4, 8), (4, 2, 2, 4), 2), ((6, 4, 6, 6), (2, 2, 2, 2), 2),
                                             ((4, 6, 4, 8), (2, 3, 2, 4), 2), ((3, 5, 2, 7), (1, 1, 1, 1), 1)])
 def test_dslash_site_arithmetic_equals_neighbour_table(L, block, levels):
