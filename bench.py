@@ -546,63 +546,121 @@ def learned_setup(w, torch, L=(16, 16, 16, 16), ntrain=6, ntest=4, epochs=8, nv=
     (network + k MR sweeps, no refinement) is compared with the plain setup at
     the same k and with the plain 2-iteration setup: setup s, outer iterations,
     solve s.  Forward and backward throughput of the network kernels (FP32
-    matrix cores) from HIP events."""
+    matrix cores) from HIP events.
+
+    One context serves every field: each field's links and plain-setup
+    vectors stay on the GPU and are loaded into it per training step (a
+    context per field would not fit at 24^3 x 48 with 64 fields).  Links and
+    start vectors are drawn on the GPU (gauge_field_device,
+    start_vectors_device)."""
     import numpy as np
     import synthetic as syn
     V = int(np.prod(L))
     s = syn.config_seeds(seed)
     eps = np.random.default_rng(s["net"]).uniform(0.2, 0.35, ntrain + ntest)
+    kw = dict(dims=L, m0=-0.08, c_sw=1.0, n_levels=2, block=((4, 4, 4, 4),), n_vec=(nv,), cycle_prec=w.F32,
+              coarse_store_prec=w.F32, setup_prec=w.F32, outer_restart=20, outer_maxit=2000)
 
-    def ctx_for(f, relax, refine):
-        c = w.Context(dims=L, m0=-0.08, c_sw=1.0, n_levels=2, block=((4, 4, 4, 4),), n_vec=(nv,),
-                      relax_sweeps=relax, refine_iters=refine, cycle_prec=w.F32, coarse_store_prec=w.F32,
-                      setup_prec=w.F32, outer_restart=20, outer_maxit=2000)
-        c.set_gauge(torch.from_numpy(syn.gauge_field(L, eps[f], s["gauge"] + f)).cuda())
-        c.set_null_vectors(0, torch.from_numpy(syn.start_vectors(nv, V, 12, s["start"] + f)).cuda())
-        return c
+    def gauge(f):
+        return syn.gauge_field_device(L, eps[f], s["gauge"] + f, "cuda")
 
-    ctxs = []
+    def start(f):
+        return syn.start_vectors_device(nv, V, 12, s["start"] + f, "cuda")
+
+    # targets: the plain 2-iteration setup of every field
+    t0 = time.perf_counter()
+    ctx = w.Context(relax_sweeps=20, refine_iters=2, **kw)
+    links, targets = [], []
     for f in range(ntrain + ntest):
-        c = ctx_for(f, 20, 2)
-        c.setup()
-        ctxs.append(c)
+        U = gauge(f)
+        ctx.set_gauge(U)
+        ctx.set_null_vectors(0, start(f))
+        ctx.setup()
+        links.append(U)
+        targets.append(ctx.null_vectors(0).clone())
+        if f % 8 == 7:
+            print("[bench] learned setup: %d fields set up" % (f + 1), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0
+    print("[bench] learned setup: %d plain setups %.1f s" % (ntrain + ntest, t_targets), file=sys.stderr, flush=True)
+
+    def load(f):
+        ctx.set_gauge(links[f])
+        ctx.set_null_vectors(0, start(f))
+        ctx.rebuild_from_vectors(0, targets[f])
+
     net = w.Network(nv, ch, act_prec=w.BF16, seed=s["net"])
-    init = [net.loss_grad(c, grad=False)[0] for c in ctxs[ntrain:]]
-    for c in ctxs[:1]:
-        c.profile("nn_forward", True)
-        c.profile("nn_backward", True)
+    init = []
+    for f in range(ntrain, ntrain + ntest):
+        load(f)
+        init.append(net.loss_grad(ctx, grad=False)[0])
+    ctx.profile("nn_forward", True)
+    ctx.profile("nn_backward", True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_load = 0.0
     curve = []
     for e in range(epochs):
-        curve.append(float(np.mean([net.train_step(c, lr=lr) for c in ctxs[:ntrain]])))
+        losses = []
+        for f in range(ntrain):
+            tl = time.perf_counter()
+            load(f)
+            torch.cuda.synchronize()
+            t_load += time.perf_counter() - tl
+            losses.append(net.train_step(ctx, lr=lr))
+        curve.append(float(np.mean(losses)))
+        print("[bench] learned setup: epoch %d loss %.4f" % (e, curve[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    nf, msf = ctxs[0].profile_stats("nn_forward")
-    nb_, msb = ctxs[0].profile_stats("nn_backward")
+    nf, msf = ctx.profile_stats("nn_forward")
+    nb_, msb = ctx.profile_stats("nn_backward")
     # useful complex multiply-adds of the three layers per site: 9 (Cin Cout) 12, 8 flops each
     fl = 8.0 * 9 * 12 * V * (nv * ch + ch * ch + ch * nv)
-    held = [net.loss_grad(c, grad=False)[0] for c in ctxs[ntrain:]]
+    held = []
+    for f in range(ntrain, ntrain + ntest):
+        load(f)
+        held.append(net.loss_grad(ctx, grad=False)[0])
+    ctx.close()
+    del links[:ntrain], targets[:ntrain]
+    torch.cuda.empty_cache()
     b = torch.from_numpy(syn.complex_gaussian((V, 4, 3), s["rhs"])).cuda()
     rows = []
-    for f in range(ntrain, ntrain + ntest):
+    for i, f in enumerate(range(ntrain, ntrain + ntest)):
         r = {}
-        for name, relax, refine in (("plain_20sweeps_2refine", 20, 2), ("plain_20sweeps", 20, 0), ("plain_5sweeps", 5, 0)):
-            c = ctx_for(f, relax, refine)
-            c.setup()
+        U = links[i]
+        for name, relax, refine, k in (("plain_20sweeps_2refine", 20, 2, None), ("plain_20sweeps", 20, 0, None),
+                                       ("plain_5sweeps", 5, 0, None), ("learned_5sweeps", 20, 0, 5),
+                                       ("learned_20sweeps", 20, 0, 20)):
+            c = w.Context(relax_sweeps=relax, refine_iters=refine, **kw)
+            c.set_gauge(U)
+            c.set_null_vectors(0, start(f))
+            if k is None:
+                c.setup()
+            else:
+                fb, q = c.setup_learned(net, relax_sweeps=k)
             x, info, st = c.solve(b)
             r[name] = {"setup_s": c.timers()["setup"], "outer_iters": info[0]["outer_iters"],
-                       "solve_s": info[0]["t_solve_s"]}
-        for name, k in (("learned_5sweeps", 5), ("learned_20sweeps", 20)):
-            c = ctx_for(f, 20, 0)
-            fb, q = c.setup_learned(net, relax_sweeps=k)
-            x, info, st = c.solve(b)
-            r[name] = {"setup_s": c.timers()["setup"], "outer_iters": info[0]["outer_iters"],
-                       "solve_s": info[0]["t_solve_s"], "fell_back": fb, "quality": q}
+                       "solve_s": info[0]["t_solve_s"], "converged": bool(info[0]["converged"]) and st == 0}
+            if k is not None:
+                r[name].update(fell_back=fb, quality=q)
+            c.close()
+            del x
+        r["total_s"] = {n: r[n]["setup_s"] + r[n]["solve_s"] for n in list(r)}
         rows.append(r)
+        print("[bench] learned setup: held-out field %d: %s" % (f, {n: (r[n]["outer_iters"], round(t, 4))
+                                                                    for n, t in r["total_s"].items()}),
+              file=sys.stderr, flush=True)
+    del links, targets
+    torch.cuda.empty_cache()
+    names = list(rows[0]["total_s"])
+    summary = {n: {"mean_outer_iters": float(np.mean([r[n]["outer_iters"] for r in rows])),
+                   "mean_setup_s": float(np.mean([r[n]["setup_s"] for r in rows])),
+                   "mean_solve_s": float(np.mean([r[n]["solve_s"] for r in rows])),
+                   "mean_total_s": float(np.mean([r["total_s"][n] for r in rows]))} for n in names}
     return {"lattice": list(L), "n_vec": nv, "channels": ch, "train_fields": ntrain, "held_out_fields": ntest,
-            "epochs": epochs, "train_s": t_train, "train_loss_curve": curve, "held_out_loss_untrained": init,
-            "held_out_loss_trained": held, "held_out": rows,
+            "epochs": epochs, "targets_s": t_targets, "train_s": t_train, "train_load_s": t_load,
+            "train_loss_curve": curve, "held_out_loss_untrained": init, "held_out_loss_trained": held,
+            "summary": summary, "held_out": rows,
             "nn_forward": {"launches": nf, "avg_ms": msf / max(nf, 1), "TFLOP_s": fl / (msf / max(nf, 1)) / 1e9,
                            "frac_fp32_mfma": fl / (msf / max(nf, 1)) / 1e9 / 157.3},
             "nn_backward": {"launches": nb_, "avg_ms": msb / max(nb_, 1),

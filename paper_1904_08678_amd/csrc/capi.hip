@@ -2,7 +2,9 @@
 // Every entry point converts internal exceptions into a wcmg_status and keeps
 // the message for wcmg_last_error.
 #include <chrono>
+#include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 
@@ -43,6 +45,14 @@ void check_level(const Context& c, int level, bool need_coarse) {
 void check_prec(int prec, bool allow_bf16) {
   require(prec == WCMG_F64 || prec == WCMG_F32 || (allow_bf16 && prec == WCMG_BF16), WCMG_ERR_ARG,
           "unsupported precision");
+}
+
+// ||b - D x|| / ||b|| from the squared norms; 0 for b = 0, NaN when either
+// norm is not finite (so that a NaN in b or x is reported, never taken for
+// convergence).
+double true_rel_res(double rr, double bb) {
+  if (!std::isfinite(rr) || !std::isfinite(bb)) return std::numeric_limits<double>::quiet_NaN();
+  return bb > 0 ? std::sqrt(rr / bb) : 0.0;
 }
 
 }  // namespace
@@ -562,7 +572,7 @@ int wcmg_solve(wcmg_ctx* ctx, const void* b, void* x, int nrhs, wcmg_solve_info*
       double bb = c.norm2_host<double>(b64, nn);
       launch_unpack_fermion<double, double>(x64, c.perm0.as<int>(), V, 1, (cd64*)x + k * nn, c.stream);
       c.sync();
-      double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      double rel = true_rel_res(rr, bb);
       double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       c.timers[5] = dt;
       bool conv = rel <= c.p.outer_tol;
@@ -631,7 +641,7 @@ int wcmg_solve_batched(wcmg_ctx* ctx, const void* b, void* x, int nrhs, int flag
       c.timers[5] = dt;
       for (int r = 0; r < B; ++r) {
         const double rr = hn[2 * r].re, bb = hn[2 * r + 1].re;
-        const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        const double rel = true_rel_res(rr, bb);
         const bool conv = rel <= c.p.outer_tol;
         if (!(rel == rel)) status = WCMG_ERR_NAN;
         else if (!conv && status == WCMG_OK) status = WCMG_ERR_NOCONV;
@@ -722,7 +732,7 @@ int wcmg_solve_ragged(wcmg_ctx* const* ctxs, int nprob, const void* const* b, vo
       c.timers[5] = dt;
       for (int r = 0; r < Bs[k]; ++r, ++slot) {
         const double rr = hn[k][2 * r].re, bb = hn[k][2 * r + 1].re;
-        const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        const double rel = true_rel_res(rr, bb);
         const bool conv = rel <= c.p.outer_tol;
         if (!(rel == rel)) status = WCMG_ERR_NAN;
         else if (!conv && status == WCMG_OK) status = WCMG_ERR_NOCONV;

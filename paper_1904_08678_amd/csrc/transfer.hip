@@ -127,7 +127,7 @@ __device__ inline long agg_of_block(long Vc) {
 // the right-hand sides w % 4 + 4 j, so each lane keeps NV/2 x RPW
 // accumulators (more waves resident to cover the memory latency).
 template <int NB, int RPW>
-__global__ void __launch_bounds__(1024, 8) k_restrict_mrhs(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
+__global__ void __launch_bounds__(1024) k_restrict_mrhs(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
                                                          const cf32* __restrict__ P, long V,
                                                          const int* __restrict__ agg_sites, int A, long Vc,
                                                          int nrhs, const int* __restrict__ run, int rs) {
@@ -155,17 +155,20 @@ __global__ void __launch_bounds__(1024, 8) k_restrict_mrhs(const cf32* __restric
   for (int o0 = 0; o0 < A; o0 += 64) {
     const int o = o0 + lane;
     const long s = any && o < A ? agg_sites[c * A + o] : -1;
-#pragma unroll 1
-    for (int k = 0; k < 6 && s >= 0; ++k) {
-      const long e = (long)(chi * 6 + k) * V + s;
-      cf32 v[RPW];
+    if (s >= 0) {
+      // two spin-colour components per step: their loads are in flight together
+#pragma unroll 2
+      for (int k = 0; k < 6; ++k) {
+        const long e = (long)(chi * 6 + k) * V + s;
+        cf32 v[RPW];
 #pragma unroll
-      for (int j = 0; j < RPW; ++j) v[j] = act[j] ? fine[(long)(g + 4 * j) * fs + e] : mkc(0.f, 0.f);
+        for (int j = 0; j < RPW; ++j) v[j] = act[j] ? fine[(long)(g + 4 * j) * fs + e] : mkc(0.f, 0.f);
 #pragma unroll
-      for (int i = 0; i < NH; ++i) {
-        const cf32 p = P[(long)(ih * NH + i) * fs + e];
+        for (int i = 0; i < NH; ++i) {
+          const cf32 p = P[(long)(ih * NH + i) * fs + e];
 #pragma unroll
-        for (int j = 0; j < RPW; ++j) cfmac(acc[i][j], p, v[j]);
+          for (int j = 0; j < RPW; ++j) cfmac(acc[i][j], p, v[j]);
+        }
       }
     }
     __syncthreads();
@@ -216,21 +219,23 @@ __global__ void __launch_bounds__(512, 4) k_prolong_mrhs(const cf32* __restrict_
   for (int o0 = 0; o0 < A; o0 += 64) {  // as in k_restrict_mrhs: waves kept in step, idle ones join the barrier
     const int o = o0 + lane;
     const long s = any && o < A ? agg_sites[c * A + o] : -1;
+    if (s >= 0) {
 #pragma unroll 1
-    for (int k = 0; k < 6 && s >= 0; ++k) {
-      const long e = (long)(chi * 6 + k) * V + s;
-      cf32 p[NV];
+      for (int k = 0; k < 6; ++k) {
+        const long e = (long)(chi * 6 + k) * V + s;
+        cf32 p[NV];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) p[i] = P[(long)i * fs + e];
+        for (int i = 0; i < NV; ++i) p[i] = P[(long)i * fs + e];
 #pragma unroll
-      for (int j = 0; j < RPW; ++j) {
-        if (!act[j]) continue;
-        cf32 t = mkc(0.f, 0.f);
+        for (int j = 0; j < RPW; ++j) {
+          if (!act[j]) continue;
+          cf32 t = mkc(0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) cfma(t, p[i], phi[i][j]);
-        cf32* out = fine + (long)(g + 4 * j) * fs + e;
-        if (accumulate) t = cadd(t, *out);
-        *out = t;
+          for (int i = 0; i < NV; ++i) cfma(t, p[i], phi[i][j]);
+          cf32* out = fine + (long)(g + 4 * j) * fs + e;
+          if (accumulate) t = cadd(t, *out);
+          *out = t;
+        }
       }
     }
     __syncthreads();

@@ -219,6 +219,10 @@ class Context:
         if st:
             raise WcmgError(st, lib().wcmg_last_error(self.h).decode())
 
+    def last_error(self) -> str:
+        """wcmg_last_error: the message of the last failed or non-converged call."""
+        return lib().wcmg_last_error(self.h).decode()
+
     def sites(self, level):
         d = self.level_dims[level]
         return int(d[0] * d[1] * d[2] * d[3])

@@ -24,8 +24,8 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "rng", "volume", "gell_mann", "gauge_field", "unit_gauge", "random_gauge_transform",
-    "complex_gaussian", "start_vectors", "point_sources", "config_seeds",
+    "rng", "volume", "gell_mann", "gauge_field", "gauge_field_device", "unit_gauge", "random_gauge_transform",
+    "complex_gaussian", "start_vectors", "start_vectors_device", "point_sources", "config_seeds",
 ]
 
 
@@ -123,17 +123,22 @@ def _reunitarise(U):
     return torch.stack([r0, r1, r2], dim=-2)
 
 
-def _su3_from_algebra(w: np.ndarray, scale: float) -> np.ndarray:
+def _su3_from_algebra(w: np.ndarray, scale: float, device=None):
     """exp(i scale H), H = sum_a w_a lambda_a / 2, for coefficients w [..., 8],
-    re-unitarised; evaluated in chunks (the closed form above, in FP64)."""
+    re-unitarised; evaluated in chunks (the closed form above, in FP64).
+    device None: a numpy array from CPU arithmetic; else a torch tensor
+    computed on that device from the same coefficients."""
     import torch
-    gm = torch.from_numpy(gell_mann().reshape(8, 9) / 2.0)
+    dv = torch.device("cpu") if device is None else torch.device(device)
+    gm = torch.from_numpy(gell_mann().reshape(8, 9) / 2.0).to(dv)
     flat = w.reshape(-1, 8)
-    out = np.empty((flat.shape[0], 3, 3), dtype=np.complex128)
+    out = (np.empty((flat.shape[0], 3, 3), dtype=np.complex128) if device is None
+           else torch.empty((flat.shape[0], 3, 3), dtype=torch.complex128, device=dv))
     step = 1 << 20
     for a in range(0, flat.shape[0], step):
-        H = (torch.from_numpy(flat[a:a + step]).to(torch.complex128) @ gm).reshape(-1, 3, 3)
-        out[a:a + step] = _reunitarise(_expi_traceless_hermitian(scale * H)).numpy()
+        H = (torch.from_numpy(flat[a:a + step]).to(dv).to(torch.complex128) @ gm).reshape(-1, 3, 3)
+        u = _reunitarise(_expi_traceless_hermitian(scale * H))
+        out[a:a + step] = u.numpy() if device is None else u
     return out.reshape(w.shape[:-1] + (3, 3))
 
 
@@ -149,6 +154,28 @@ def gauge_field(dims, eps: float, seed: int) -> np.ndarray:
     g = rng(seed)
     w = g.standard_normal((V, 4, 8))
     return np.ascontiguousarray(_su3_from_algebra(w, eps))
+
+
+def gauge_field_device(dims, eps: float, seed: int, device="cuda"):
+    """gauge_field's links (the same draws, the same closed form) evaluated on
+    a torch device: complex128 tensor [V][4][3][3]; equal to gauge_field up
+    to the device's rounding."""
+    V = volume(dims)
+    g = rng(seed)
+    w = g.standard_normal((V, 4, 8))
+    return _su3_from_algebra(w, eps, device).contiguous()
+
+
+def start_vectors_device(nv: int, n_sites: int, ns: int, seed: int, device="cuda"):
+    """Gaussian start vectors drawn on a torch device ([nv][n_sites][ns]
+    complex128; Re and Im each N(0,1)) from torch's generator of that device
+    seeded with `seed`: reproducible for a device type, not equal to
+    start_vectors' numpy draws."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    a = torch.randn((nv, n_sites, ns, 2), dtype=torch.float64, device=device, generator=g)
+    return torch.complex(a[..., 0], a[..., 1]).contiguous()
 
 
 def unit_gauge(dims) -> np.ndarray:

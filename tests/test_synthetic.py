@@ -28,3 +28,18 @@ def test_large_angle_and_gauge_transform():
         assert np.max(np.abs(syn._su3_from_algebra(w, eps) - ref)) < 1e-12
     g = syn.random_gauge_transform((2, 2, 2, 2), 9)
     assert np.max(np.abs(g @ np.conj(np.swapaxes(g, -1, -2)) - np.eye(3))) < 1e-14
+
+
+def test_device_generators_match_and_repeat():
+    """gauge_field_device evaluates gauge_field's closed form on a torch device
+    from the same draws (on the CPU device: identical values); the device start
+    vectors repeat for a seed and differ across seeds."""
+    a = syn.gauge_field((2, 2, 2, 4), 0.3, 17)
+    b = syn.gauge_field_device((2, 2, 2, 4), 0.3, 17, "cpu")
+    assert np.array_equal(a, b.numpy())
+    v1 = syn.start_vectors_device(3, 16, 12, 5, "cpu")
+    v2 = syn.start_vectors_device(3, 16, 12, 5, "cpu")
+    v3 = syn.start_vectors_device(3, 16, 12, 6, "cpu")
+    assert v1.shape == (3, 16, 12) and np.array_equal(v1.numpy(), v2.numpy())
+    assert not np.array_equal(v1.numpy(), v3.numpy())
+    assert abs(float((v1.abs() ** 2).mean()) - 2.0) < 0.5
