@@ -110,12 +110,8 @@ __global__ void __launch_bounds__(256) k_prolong(const cplx<R>* __restrict__ coa
 }
 
 // Several right-hand sides of a level-0 FP32 field (layout [B][12][V]) per
-// launch, each aggregate's slice of P read once: one workgroup of 8 waves per
-// aggregate; wave w takes chirality w / 4 and the right-hand sides
-// r = w % 4 + 4 j (j < RPW), a lane per site.  The four waves of a chirality
-// read the same P entries together (from cache after the first), so P
-// crosses HBM once per launch instead of once per right-hand side.  Padding
-// workgroups (the grid is a multiple of the 8 XCDs) return at once.
+// launch, each aggregate's slice of P read once.  Padding workgroups (the grid
+// is a multiple of the 8 XCDs) return at once.
 __device__ inline long agg_of_block(long Vc) {
   const long G = gridDim.x, h = blockIdx.x;
   const long c = (h % 8) * (G / 8) + h / 8;  // each XCD a contiguous range of aggregates
@@ -123,122 +119,125 @@ __device__ inline long agg_of_block(long Vc) {
 }
 
 // coarse_r(c, chi * nv + i) = sum_{x in c} sum_{k < 6} conj(P_i(x)_{6 chi + k}) fine_r(x)_{6 chi + k}
-// 16 waves: wave w takes chirality w / 8, vectors i of half (w / 4) % 2 and
-// the right-hand sides w % 4 + 4 j, so each lane keeps NV/2 x RPW
-// accumulators (more waves resident to cover the memory latency).
-template <int NB, int RPW>
-__global__ void __launch_bounds__(1024) k_restrict_mrhs(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
-                                                         const cf32* __restrict__ P, long V,
-                                                         const int* __restrict__ agg_sites, int A, long Vc,
-                                                         int nrhs, const int* __restrict__ run, int rs) {
+// One workgroup of four waves per aggregate and chirality (blockIdx.y).  A lane
+// is one of 16 consecutive sites of its wave's current group and one of four
+// (vector half, right-hand-side half) variants, so a load instruction covers
+// 16 sites of two arrays and every line of P and of the fields is requested
+// once; a lane keeps NH x RH accumulators, summed over its sites at the end
+// (shuffles within the 16 lanes of a variant, then the four waves in LDS).
+template <int NB, int RH>
+__global__ void __launch_bounds__(256) k_restrict_mrhs(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
+                                                    const cf32* __restrict__ P, long V,
+                                                    const int* __restrict__ agg_sites, int A, long Vc, int nrhs,
+                                                    const int* __restrict__ run, int rs) {
   constexpr int NV = NB / 2, NH = NV / 2;
+  __shared__ cf32 red[4][4][NH * RH];  // [wave][variant][accumulator]
   const long c = agg_of_block(Vc);
-  if (c < 0) return;
+  if (c < 0) return;  // the whole workgroup
+  const int chi = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int chi = wave >> 3, ih = (wave >> 2) & 1, g = wave & 3;
-  bool act[RPW];
-  bool any = false;
+  const int var = lane >> 4, sl = lane & 15;
+  const int ih = var >> 1, rh = var & 1;
+  bool act[RH];
 #pragma unroll
-  for (int j = 0; j < RPW; ++j) {
-    const int r = g + 4 * j;
+  for (int j = 0; j < RH; ++j) {
+    const int r = rh * RH + j;
     act[j] = r < nrhs && (!run || run[(long)r * rs]);
-    any = any || act[j];
   }
   const long fs = 12 * V;
-  cf32 acc[NH][RPW];
+  cf32 acc[NH][RH];
 #pragma unroll
   for (int i = 0; i < NH; ++i)
 #pragma unroll
-    for (int j = 0; j < RPW; ++j) acc[i][j] = mkc(0.f, 0.f);
-  // one block of 64 sites per pass; the barrier keeps the waves that read the
-  // same entries within one block of each other; waves without work join it
-  for (int o0 = 0; o0 < A; o0 += 64) {
-    const int o = o0 + lane;
-    const long s = any && o < A ? agg_sites[c * A + o] : -1;
-    if (s >= 0) {
-      // two spin-colour components per step: their loads are in flight together
-#pragma unroll 2
+    for (int j = 0; j < RH; ++j) acc[i][j] = mkc(0.f, 0.f);
+  for (int o0 = 16 * wave; o0 < A; o0 += 64) {
+    const int o = o0 + sl;
+    if (o < A) {
+      const long s = agg_sites[c * A + o];
+      constexpr int KU = 2;  // components whose loads are in flight together
+#pragma unroll KU
       for (int k = 0; k < 6; ++k) {
         const long e = (long)(chi * 6 + k) * V + s;
-        cf32 v[RPW];
+        cf32 v[RH];
 #pragma unroll
-        for (int j = 0; j < RPW; ++j) v[j] = act[j] ? fine[(long)(g + 4 * j) * fs + e] : mkc(0.f, 0.f);
+        for (int j = 0; j < RH; ++j) v[j] = act[j] ? fine[(long)(rh * RH + j) * fs + e] : mkc(0.f, 0.f);
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
           const cf32 p = P[(long)(ih * NH + i) * fs + e];
 #pragma unroll
-          for (int j = 0; j < RPW; ++j) cfmac(acc[i][j], p, v[j]);
+          for (int j = 0; j < RH; ++j) cfmac(acc[i][j], p, v[j]);
         }
       }
     }
-    __syncthreads();
   }
-  if (!any) return;  // wave-uniform
 #pragma unroll
   for (int i = 0; i < NH; ++i)
 #pragma unroll
-    for (int j = 0; j < RPW; ++j) {
+    for (int j = 0; j < RH; ++j) {
       float re = acc[i][j].re, im = acc[i][j].im;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
+      for (int off = 8; off > 0; off >>= 1) {  // the 16 site lanes of this variant
         re += __shfl_xor(re, off, 64);
         im += __shfl_xor(im, off, 64);
       }
-      if (lane == 0 && act[j]) coarse[((long)(g + 4 * j) * Vc + c) * NB + chi * NV + ih * NH + i] = mkc(re, im);
+      if (sl == 0) red[wave][var][i * RH + j] = mkc(re, im);
     }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 4 * NH * RH) {
+    const int v = t / (NH * RH), q = t - v * (NH * RH);
+    const int i = q / RH, j = q - i * RH;
+    const int r = (v & 1) * RH + j;
+    cf32 sum = red[0][v][q];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) sum = cadd(sum, red[w][v][q]);
+    if (r < nrhs && (!run || run[(long)r * rs]))
+      coarse[((long)r * Vc + c) * NB + chi * NV + (v >> 1) * NH + i] = sum;
+  }
 }
 
-// fine_r(x)_{6 chi + k} (+)= sum_i P_i(x)_{6 chi + k} coarse_r(c(x), chi * nv + i), the
-// same workgroup shape; the wave keeps its right-hand sides' coarse components
-// of its chirality in registers.
-template <int NB, int RPW>
-__global__ void __launch_bounds__(512, 4) k_prolong_mrhs(const cf32* __restrict__ coarse, cf32* __restrict__ fine,
-                                                       const cf32* __restrict__ P, long V,
-                                                       const int* __restrict__ agg_sites, int A, long Vc,
-                                                       int accumulate, int nrhs, const int* __restrict__ run, int rs) {
+// fine_r(x)_{6 chi + k} (+)= sum_i P_i(x)_{6 chi + k} coarse_r(c(x), chi * nv + i).
+// Four workgroups per aggregate, one per quarter of the spin-colour components
+// (blockIdx.y: components 3y .. 3y + 2, chirality y / 2): the aggregate's
+// coarse vectors of every right-hand side go to LDS (read back as
+// broadcasts); a thread takes a site and all right-hand sides, so P is read
+// once, in whole lines, with few registers per thread.
+template <int NB>
+__global__ void __launch_bounds__(256) k_prolong_mrhs(const cf32* __restrict__ coarse, cf32* __restrict__ fine,
+                                                   const cf32* __restrict__ P, long V,
+                                                   const int* __restrict__ agg_sites, int A, long Vc, int accumulate,
+                                                   int nrhs, const int* __restrict__ run, int rs) {
   constexpr int NV = NB / 2;
+  __shared__ cf32 cv[16][NB];
+  __shared__ int live[16];
   const long c = agg_of_block(Vc);
-  if (c < 0) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int chi = wave >> 2, g = wave & 3;
-  bool act[RPW];
-  bool any = false;
-#pragma unroll
-  for (int j = 0; j < RPW; ++j) {
-    const int r = g + 4 * j;
-    act[j] = r < nrhs && (!run || run[(long)r * rs]);
-    any = any || act[j];
+  if (c < 0) return;  // the whole workgroup
+  for (int t = threadIdx.x; t < nrhs * NB; t += blockDim.x) {
+    const int r = t / NB, q = t - r * NB;
+    cv[r][q] = coarse[((long)r * Vc + c) * NB + q];
   }
+  if (threadIdx.x < 16) live[threadIdx.x] = threadIdx.x < nrhs && (!run || run[(long)threadIdx.x * rs]);
+  __syncthreads();
   const long fs = 12 * V;
-  cf32 phi[NV][RPW];
-#pragma unroll
-  for (int j = 0; j < RPW; ++j)
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-      phi[i][j] = act[j] ? coarse[((long)(g + 4 * j) * Vc + c) * NB + chi * NV + i] : mkc(0.f, 0.f);
-  for (int o0 = 0; o0 < A; o0 += 64) {  // as in k_restrict_mrhs: waves kept in step, idle ones join the barrier
-    const int o = o0 + lane;
-    const long s = any && o < A ? agg_sites[c * A + o] : -1;
-    if (s >= 0) {
+  const int chi = blockIdx.y >> 1;
+  for (int o = threadIdx.x; o < A; o += blockDim.x) {
+    const long s = agg_sites[c * A + o];
 #pragma unroll 1
-      for (int k = 0; k < 6; ++k) {
-        const long e = (long)(chi * 6 + k) * V + s;
-        cf32 p[NV];
+    for (int k = 3 * blockIdx.y; k < 3 * blockIdx.y + 3; ++k) {
+      const long e = (long)k * V + s;
+      cf32 p[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) p[i] = P[(long)i * fs + e];
+      for (int i = 0; i < NV; ++i) p[i] = P[(long)i * fs + e];
+      for (int r = 0; r < nrhs; ++r) {
+        if (!live[r]) continue;
+        cf32 t = mkc(0.f, 0.f);
 #pragma unroll
-        for (int j = 0; j < RPW; ++j) {
-          if (!act[j]) continue;
-          cf32 t = mkc(0.f, 0.f);
-#pragma unroll
-          for (int i = 0; i < NV; ++i) cfma(t, p[i], phi[i][j]);
-          cf32* out = fine + (long)(g + 4 * j) * fs + e;
-          if (accumulate) t = cadd(t, *out);
-          *out = t;
-        }
+        for (int i = 0; i < NV; ++i) cfma(t, p[i], cv[r][chi * NV + i]);
+        cf32* out = fine + (long)r * fs + e;
+        if (accumulate) t = cadd(t, *out);
+        *out = t;
       }
     }
-    __syncthreads();
   }
 }
 
@@ -699,16 +698,20 @@ bool supported_nb(int nb) {
 }
 
 // The multi-RHS forms serve FP32 level-0 fields with 2..16 right-hand sides
-// and Nb in {8, 12, 16, 24}; RPW right-hand sides per wave.
+// and Nb in {8, 12, 16, 24}.
 static bool transfer_mrhs(int nb, int nrhs, const FieldLayout& lay) {
   return lay.soa && lay.ns == 12 && nrhs >= 2 && nrhs <= 16 && (nb == 8 || nb == 12 || nb == 16 || nb == 24);
 }
-#define RPW_SWITCH(nrhs, ...)                                                   \
-  switch ((nrhs + 3) / 4) {                                                     \
-    case 1: { constexpr int RPWc = 1; __VA_ARGS__; } break;                     \
-    case 2: { constexpr int RPWc = 2; __VA_ARGS__; } break;                     \
-    case 3: { constexpr int RPWc = 3; __VA_ARGS__; } break;                     \
-    default: { constexpr int RPWc = 4; __VA_ARGS__; } break;                    \
+// right-hand sides per half in the restriction: ceil(nrhs / 2) rounded up to 1, 2, 4, 6 or 8
+#define RH_SWITCH(nrhs, ...)                                                    \
+  switch ((nrhs + 1) / 2) {                                                     \
+    case 1: { constexpr int RHc = 1; __VA_ARGS__; } break;                      \
+    case 2: { constexpr int RHc = 2; __VA_ARGS__; } break;                      \
+    case 3:                                                                     \
+    case 4: { constexpr int RHc = 4; __VA_ARGS__; } break;                      \
+    case 5:                                                                     \
+    case 6: { constexpr int RHc = 6; __VA_ARGS__; } break;                      \
+    default: { constexpr int RHc = 8; __VA_ARGS__; } break;                     \
   }
 #define NB_SWITCH_MRHS(nb, ...)                                                 \
   switch (nb) {                                                                 \
@@ -722,10 +725,10 @@ template <typename R>
 void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, FieldLayout lay, const int* agg_sites,
                      int A, long Vc, int nb, int nrhs, const int* run, hipStream_t st, int rs) {
   if (std::is_same<R, float>::value && transfer_mrhs(nb, nrhs, lay)) {
-    const dim3 g((unsigned)((Vc + 7) / 8 * 8)), b(512);
-    NB_SWITCH_MRHS(nb, RPW_SWITCH(nrhs, WCMG_LAUNCH((k_restrict_mrhs<NBc, RPWc>), g, dim3(1024), 0, st, (const cf32*)fine,
-                                                    (cf32*)coarse, (const cf32*)P, lay.V, agg_sites, A, Vc, nrhs, run,
-                                                    rs)));
+    const dim3 g((unsigned)((Vc + 7) / 8 * 8), 2);
+    NB_SWITCH_MRHS(nb, RH_SWITCH(nrhs, WCMG_LAUNCH((k_restrict_mrhs<NBc, RHc>), g, dim3(256), 0, st, (const cf32*)fine,
+                                                   (cf32*)coarse, (const cf32*)P, lay.V, agg_sites, A, Vc, nrhs, run,
+                                                   rs)));
   } else {
     NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st, fine, coarse, P,
                                lay, agg_sites, A, Vc, nrhs, run, rs));
@@ -737,10 +740,9 @@ void launch_prolong(const cplx<R>* coarse, cplx<R>* fine, const cplx<R>* P, Fiel
                     long Vc, int nb, int accumulate, int nrhs, const int* run, hipStream_t st, int rs,
                     const int* agg_sites, int A) {
   if (std::is_same<R, float>::value && agg_sites && transfer_mrhs(nb, nrhs, lay)) {
-    const dim3 g((unsigned)((Vc + 7) / 8 * 8)), b(512);
-    NB_SWITCH_MRHS(nb, RPW_SWITCH(nrhs, WCMG_LAUNCH((k_prolong_mrhs<NBc, RPWc>), g, b, 0, st, (const cf32*)coarse,
-                                                    (cf32*)fine, (const cf32*)P, lay.V, agg_sites, A, Vc, accumulate,
-                                                    nrhs, run, rs)));
+    const dim3 g((unsigned)((Vc + 7) / 8 * 8), 4);
+    NB_SWITCH_MRHS(nb, WCMG_LAUNCH((k_prolong_mrhs<NBc>), g, dim3(256), 0, st, (const cf32*)coarse, (cf32*)fine,
+                                   (const cf32*)P, lay.V, agg_sites, A, Vc, accumulate, nrhs, run, rs));
   } else {
     NB_SWITCH(nb, WCMG_LAUNCH((k_prolong<R, NBc>), dim3(item_rhs_grid(nblocks(lay.V), nrhs)), dim3(kBlock), 0, st,
                                coarse, fine, P, lay, coarse_of, Vc, accumulate, nrhs, run, rs));
