@@ -456,6 +456,7 @@ __global__ void __launch_bounds__(512) k_wilson_mrhs(const cf32* __restrict__ in
     cf32 acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = mkc(0.f, 0.f);
+    cf32 self[12];  // the site's own spinor: clover term, then the dots
 #pragma unroll
     for (int chi = 0; chi < 2; ++chi) {
       float e[36];
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(512) k_wilson_mrhs(const cf32* __restrict__ in
       }
       cf32 p[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) p[k] = inb.ld(so, (chi * 6 + k) * cs);
+      for (int k = 0; k < 6; ++k) p[k] = self[chi * 6 + k] = inb.ld(so, (chi * 6 + k) * cs);
       if (chi == 0) clover_block_apply<float, 0>(acc, e, p);
       else clover_block_apply<float, 1>(acc, e, p);
     }
@@ -499,7 +500,7 @@ __global__ void __launch_bounds__(512) k_wilson_mrhs(const cf32* __restrict__ in
       if (dots) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-          const cf32 x = inb.ld(so, k * cs);
+          const cf32 x = self[k];
           pr += (double)acc[k].re * x.re + (double)acc[k].im * x.im;
           pi += (double)acc[k].re * x.im - (double)acc[k].im * x.re;
           pp += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;

@@ -657,6 +657,26 @@ def test_coarse_op_get_set_precisions():
     assert st == 1
 
 
+@pytest.mark.parametrize("L,block,nv,nrhs", [((6, 6, 4, 4), (3, 3, 1, 1), 12, 12), ((8, 4, 4, 8), (4, 2, 2, 4), 4, 10),
+                                           ((8, 4, 4, 8), (4, 2, 2, 4), 6, 16), ((4, 4, 4, 4), (2, 2, 2, 2), 8, 12)])
+def test_restrict_multi_rhs_shapes(L, block, nv, nrhs):
+    """Restriction of 10..16 FP32 fields in one launch on other aggregate
+    shapes and block sizes: 9-site aggregates (3x3x1x1), aggregates of 16
+    sites, Nb = 8, 12, 16 and 24, against the oracle."""
+    w = wc()
+    seed = 281 + nv
+    ctx, H, U = make_pair(L, 0.3, seed, blocks=(block,), nv=(nv,))
+    V = int(np.prod(L))
+    start = syn.complex_gaussian((nv, V, 12), seed + 1)
+    ctx.set_null_vectors(0, dev(start))
+    ctx.setup()
+    H.set_start(0, start)
+    H.setup()
+    v = syn.complex_gaussian((nrhs, V, 12), seed + 2)
+    got = host(ctx.restrict(0, dev(v.astype(np.complex64)), w.F32))
+    assert rel(got, oracle.restrict(L, block, 12, H.P(0), v)) < 1e-5
+
+
 @pytest.mark.parametrize("nrhs", [2, 5, 12, 16])
 def test_restrict_prolong_multi_rhs_fp32(nrhs):
     """Several right-hand sides of an FP32 level-0 field in one launch (each
