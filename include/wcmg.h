@@ -110,8 +110,12 @@ typedef struct {
                               4 the coarsest GMRES as four kernels per Arnoldi step instead of one
                               cooperative launch; 8 the outer Arnoldi step as classical Gram-Schmidt applied
                               twice instead of the single-reduction step; 16 the cooperative launch's barrier
-                              waits give up at once (every such solve then takes the four-kernel fallback: a
-                              test of that path) */
+                              waits give up at once and every launch is checked before the next step (every
+                              such solve then takes the four-kernel fallback: a test of that path); 32 the
+                              fine Dslash reads neighbours from a table instead of site arithmetic; 64 full
+                              3x3 links instead of two rows; 128 the first cooperative launch's waits give up
+                              at once and its failure is found at the next progress check (the launches in
+                              between return x = 0: a test of the deferred check) */
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;

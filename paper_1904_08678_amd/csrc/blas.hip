@@ -765,4 +765,18 @@ void launch_gmres_cycle_end(int* st_, hipStream_t st) {
   WCMG_CHECK_LAUNCH();
 }
 
+// Copies n state words to host-mapped memory (out[1..n]) and then writes the
+// publication number to out[0]: a host that reads the number reads the words
+// of that publication.
+__global__ void __launch_bounds__(64) k_publish_state(const int* __restrict__ st, int n, int* out, int seq) {
+  for (int i = threadIdx.x; i < n; i += 64) __hip_atomic_store(out + 1 + i, st[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+void launch_publish_state(const int* st_, int n, int* out, int seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish_state, dim3(1), dim3(64), 0, st, st_, n, out, seq);
+  WCMG_CHECK_LAUNCH();
+}
+
 }  // namespace wcmg

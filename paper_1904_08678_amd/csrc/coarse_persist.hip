@@ -36,12 +36,16 @@
 // lines from this XCD's L2, and the first workgroup of an XCD to read a line
 // brings it in for the others (agent-scope loads would bypass L2 and send
 // every workgroup's reads of the same partials to memory).  The phase
-// numbers continue from launch to launch, so the flags need no clearing, and
-// workgroup 0 reports a normal end in a host-mapped mailbox.  A waiting
-// thread gives up after a wall-clock timeout: the error word is set, every
-// workgroup leaves without reporting, and the host clears the flags and
-// redoes the solve with the multi-kernel form, so a fault in the launch
-// configuration cannot hang the device.
+// numbers continue from launch to launch (a device word holds the phase
+// reached, read by every workgroup at the start and written by workgroup 0
+// at the end), so the flags need no clearing, and workgroup 0 reports a normal
+// end in a host-mapped mailbox: the launch's sequence number and its
+// iteration count in a ring of report slots, so the host can check a launch
+// later without stopping the stream.  A waiting thread gives up after a
+// wall-clock timeout: the error word is set and every workgroup leaves
+// without reporting; a launch that starts with the error word set returns
+// x = 0 at once; the host clears the flags when it next checks.  A fault in
+// the launch configuration cannot hang the device.
 #include "coarse_common.h"
 
 namespace wcmg {
@@ -49,7 +53,8 @@ namespace {
 constexpr int kPMaxM1 = 41;     // restart + 1 (restart <= 40)
 constexpr int kPSpw = 2;        // coarse sites per workgroup, at most
 constexpr int kPStride = 48;    // partial slots (cd64) per workgroup and phase buffer
-constexpr int kBarWords = 64;   // bar[2]: error word, bar[3..6]: report; flags follow
+constexpr int kBarWords = 64;   // bar[2]: error word, bar[3..6]: report, bar[8]: phase; flags follow
+constexpr int kBarPhase = 8;    // the phase the flags have reached, carried from launch to launch
 constexpr int kFlagWords = 32;  // one 128-byte line per workgroup flag
 constexpr int kPRtri = kPMaxM1 * (kPMaxM1 - 1) / 2;  // packed upper triangle, 40 columns
 
@@ -156,7 +161,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
     const Chunk16* __restrict__ blk, const int* __restrict__ nbr, long Vc, const cplx<typename BlkTraits<P>::R>* b,
     cplx<typename BlkTraits<P>::R>* x, cplx<typename BlkTraits<P>::R>* zg, cplx<typename BlkTraits<P>::R>* r,
     cd64* part, cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
-    unsigned phase0, int* mailbox, long long tick_limit) {
+    int seq, int* mailbox, long long tick_limit) {
   typedef PShape<P, NB> Sh;
   typedef typename Sh::R R;
   constexpr int K = Sh::K, NCH = Sh::NCH, NQ = Sh::NQ, ROWS = Sh::rows, SL = Sh::S;
@@ -182,6 +187,15 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   const long t = row0 + lr;
   const int lrc = min(lr, ROWS - 1);       // LDS row for unconditional reads (used only when own)
 
+  // a wait of an earlier launch timed out and the flags have not been cleared
+  // since: no barrier can be trusted, so this solve returns x = 0 (a weaker
+  // preconditioner for the outer solve) and reports nothing
+  if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+    if (own) x[t] = mkc((R)0, (R)0);
+    return;
+  }
+  const unsigned phase0 = __hip_atomic_load(bar + kBarPhase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
   if (tid == 0) {
     fail = 0;
     ctl[1] = parent ? *parent : 1;
@@ -200,10 +214,13 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
   // barrier has been passed, unless a wait timed out somewhere)
   auto report = [&](unsigned final_phase) {
     if (blockIdx.x == 0 && tid == 0 && __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      __hip_atomic_store(bar + kBarPhase, final_phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int* slot = mailbox + kCgpSlot0 + 2 * (seq & (kCgpSlots - 1));
+      __hip_atomic_store(slot + 1, ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(mailbox + 1, ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       __hip_atomic_store(mailbox + 3, ctl[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(mailbox + 4, (int)final_phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(mailbox, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(mailbox, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   };
   if (!ctl[1]) {  // uniform: every workgroup reads the same flag
@@ -564,7 +581,7 @@ bool cgp_shape_fits() {
 template <int P, int NB>
 bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* z, void* r, cd64* part,
                 cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
-                unsigned phase0, int* mailbox, long long tick_limit, hipStream_t stream) {
+                int seq, int* mailbox, long long tick_limit, hipStream_t stream) {
   if constexpr (!PShape<P, NB>::fits) {
     return false;
   } else {
@@ -584,7 +601,7 @@ bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x
     cplx<R>* rr = (cplx<R>*)r;
     void* args[] = {(void*)&bk,   (void*)&nbr, (void*)&Vc,    (void*)&bc,    (void*)&xx,    (void*)&zz,
                     (void*)&rr,   (void*)&part, (void*)&misc, (void*)&st,    (void*)&parent, (void*)&m,
-                    (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&phase0,
+                    (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&seq,
                     (void*)&mailbox, (void*)&tick_limit};
     WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
     return true;
@@ -622,7 +639,7 @@ size_t cg_persistent_bar_words(long Vc) { return (size_t)kBarWords + (size_t)kFl
 
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
-                          int limit, int fixed, unsigned* bar, unsigned phase0, int* mailbox, double timeout_s,
+                          int limit, int fixed, unsigned* bar, int seq, int* mailbox, double timeout_s,
                           hipStream_t stream) {
   if (!cg_persistent_fits(prec, nb, Vc)) return false;
   int dev = 0, khz = 0;
@@ -631,7 +648,7 @@ bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, lon
   const long long tick_limit = (long long)(timeout_s * 1000.0 * (khz > 0 ? khz : 100000));
 #define CGP(PP, NBc) \
   return cgp_launch<PP, NBc>(blk, nbr, Vc, b, x, z, r, part, misc, st, parent, m, tol, limit, fixed, bar, \
-                             phase0, mailbox, tick_limit, stream)
+                             seq, mailbox, tick_limit, stream)
   if (prec == WCMG_F32) {
     switch (nb) {
       case 8: CGP(WCMG_F32, 8);

@@ -220,18 +220,68 @@ struct Context {
   // SAP domains (level-0 aggregates) of each colour: sap_doms [2][Vc/2]
   DevBuf sap_doms;
   long sap_ndoms = 0;
-  // cooperative coarsest GMRES: solves redone by the multi-kernel form after a
-  // grid-barrier timeout, and the last timeout's report
+  // cooperative coarsest GMRES: launches that did not report a normal end (a
+  // grid-barrier wait timed out, or the launch started after a time-out and
+  // returned x = 0), and the last timeout's report
   long cgp_fallbacks = 0;
   std::string cgp_last_report;
   // the cooperative coarsest GMRES: its barrier flags count phases across
-  // launches (per level and precision: the phase the next launch starts
-  // from, 0 = flags must be cleared first), and it reports completion in a
-  // coherent host-mapped mailbox instead of through copies
-  std::map<std::string, unsigned> cgp_phase;
+  // launches (the buffer keeps the phase reached), and it reports completion
+  // in report slots of a coherent host-mapped mailbox, checked when the host
+  // next waits for the stream (settle_coarse) instead of after every launch
+  struct CgpLaunch {
+    int seq;
+    unsigned* bar;
+    long nbar, V;
+  };
+  std::vector<CgpLaunch> cgp_pending;
+  int cgp_seq = 0;
+  bool cgp_forced = false;  // reserved[0] flag 128 has made its one launch time out
   std::map<std::string, void*> cgp_bar_at;
-  int* mailbox = nullptr;
+  int* mailbox = nullptr;  // kCgpMailboxInts words
   int* mailbox_dev = nullptr;
+  // checks the cooperative coarsest solves launched up to sequence number
+  // `upto` (all of them must have completed): adds their iteration counts,
+  // and after a time-out clears the barrier buffer
+  void settle_coarse(int upto = 0x7fffffff);
+  // Solver state words published to host-mapped memory by a small kernel, so
+  // the host can read a step's state while later steps are already queued.
+  // One pair of slots per state buffer (a solver nested in another's
+  // preconditioner has its own), each [publication number, words...].
+  struct StateMailbox {
+    int* h = nullptr;
+    int* d = nullptr;
+    int cap = 0;      // words per slot
+    int seq = 0;      // last publication number
+    int cgp[2] = {0, 0};  // coarsest-solve launches issued before each slot's publication
+    std::vector<int> words;
+  };
+  std::map<const int*, StateMailbox> state_mb;
+  // queues the publication of st[0..n); returns its number
+  int publish_state(const int* st, int n);
+  // waits for publication `seq` of st (the last or the one before it) and
+  // returns a copy of its words; the coarsest solves issued before it are
+  // then checked
+  const int* wait_state(const int* st, int seq);
+  // A solver's progress checks: ahead() publishes the state and returns the
+  // one published at the previous check (nullptr at the first), so the host
+  // never waits for the steps it has just queued; now() publishes and waits.
+  struct StateChecks {
+    Context& c;
+    const int* st;
+    int n;
+    int pend = 0;
+    const int* ahead() {
+      const int s = c.publish_state(st, n);
+      const int* sv = pend ? c.wait_state(st, pend) : nullptr;
+      pend = s;
+      return sv;
+    }
+    const int* now() {
+      pend = 0;
+      return c.wait_state(st, c.publish_state(st, n));
+    }
+  };
   // workspaces
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   std::map<std::string, std::unique_ptr<GmresState>> gm;

@@ -1,5 +1,7 @@
 // Multigrid engine: geometry, operators, setup (initial and iterative),
 // MR smoother, (flexible) GMRES, V- and K-cycles (Sec. 2.1 of the paper).
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -358,7 +360,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
   bpart.alloc((size_t)16 * kPartialSlots * sizeof(cd64));
   scratch64.alloc(64 * sizeof(cd64));
   WCMG_HIP(hipHostMalloc((void**)&pinned, 256 * sizeof(int), hipHostMallocDefault));
-  WCMG_HIP(hipHostMalloc((void**)&mailbox, 16 * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+  WCMG_HIP(hipHostMalloc((void**)&mailbox, kCgpMailboxInts * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+  for (int q = 0; q < kCgpMailboxInts; ++q) mailbox[q] = 0;
   WCMG_HIP(hipHostGetDevicePointer((void**)&mailbox_dev, mailbox, 0));
   const long V0 = geo[0].V;
   U_lex.alloc(V0 * 36 * sizeof(cd64));
@@ -374,6 +377,8 @@ Context::~Context() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
   if (mailbox) (void)hipHostFree(mailbox);
+  for (auto& kv : state_mb)
+    if (kv.second.h) (void)hipHostFree(kv.second.h);
 }
 
 template <typename T>
@@ -404,7 +409,97 @@ GmresState& Context::gmres_state(const std::string& tag, int m, long n, int prec
   return G;
 }
 
-void Context::sync() { WCMG_HIP(hipStreamSynchronize(stream)); }
+void Context::sync() {
+  WCMG_HIP(hipStreamSynchronize(stream));
+  settle_coarse();
+}
+
+int Context::publish_state(const int* st, int n) {
+  StateMailbox& M = state_mb[st];
+  if (M.cap < n) {
+    // a larger buffer: earlier publications must have landed before the copy
+    WCMG_HIP(hipStreamSynchronize(stream));
+    const int cap = std::max(n, 16);
+    int* h = nullptr;
+    WCMG_HIP(hipHostMalloc((void**)&h, 2 * (cap + 1) * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+    for (int q = 0; q < 2 * (cap + 1); ++q) h[q] = 0;
+    if (M.h) {
+      for (int k = 0; k < 2; ++k)
+        for (int q = 0; q <= M.cap; ++q) h[k * (cap + 1) + q] = M.h[k * (M.cap + 1) + q];
+      (void)hipHostFree(M.h);
+    }
+    M.h = h;
+    WCMG_HIP(hipHostGetDevicePointer((void**)&M.d, h, 0));
+    M.cap = cap;
+  }
+  const int seq = ++M.seq;
+  M.cgp[seq & 1] = cgp_seq;
+  launch_publish_state(st, n, M.d + (seq & 1) * (M.cap + 1), seq, stream);
+  if ((int)M.words.size() < n) M.words.resize(n);
+  return seq;
+}
+
+const int* Context::wait_state(const int* st, int seq) {
+  StateMailbox& M = state_mb[st];
+  require(M.h && seq > 0 && seq <= M.seq && seq + 1 >= M.seq, WCMG_ERR_STATE, "state publication out of range");
+  volatile int* slot = M.h + (seq & 1) * (M.cap + 1);
+  for (long spins = 1; slot[0] != seq; ++spins) {
+#if defined(__x86_64__)
+    __builtin_ia32_pause();
+#endif
+    if (spins % 1024 == 0) {
+      // the stream is checked now and then, so an error or a lost
+      // publication ends the wait
+      const hipError_t e = hipStreamQuery(stream);
+      if (e == hipSuccess) {
+        std::atomic_thread_fence(std::memory_order_acquire);
+        require(slot[0] == seq, WCMG_ERR_HIP, "solver state publication did not arrive");
+        break;
+      }
+      if (e != hipErrorNotReady) WCMG_HIP(e);
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  const int n = (int)M.words.size();
+  for (int q = 0; q < n && q < M.cap; ++q) M.words[q] = slot[1 + q];
+  settle_coarse(M.cgp[seq & 1]);
+  return M.words.data();
+}
+
+void Context::settle_coarse(int upto) {
+  if (cgp_pending.empty()) return;
+  std::atomic_thread_fence(std::memory_order_acquire);
+  volatile int* mb = mailbox;
+  std::vector<CgpLaunch> keep, failed;
+  for (const CgpLaunch& L : cgp_pending) {
+    if (L.seq > upto) {
+      keep.push_back(L);
+      continue;
+    }
+    volatile int* slot = mb + kCgpSlot0 + 2 * (L.seq & (kCgpSlots - 1));
+    if (slot[0] == L.seq) {
+      coarse_iters += slot[1];
+    } else {
+      cgp_fallbacks++;
+      bool seen = false;
+      for (const CgpLaunch& F : failed) seen = seen || F.bar == L.bar;
+      if (!seen) failed.push_back(L);
+    }
+  }
+  cgp_pending.swap(keep);
+  for (const CgpLaunch& F : failed) {
+    // a wait timed out: keep the report, clear the flags, phase and error word
+    WCMG_HIP(hipStreamSynchronize(stream));
+    unsigned rep[8];
+    WCMG_HIP(hipMemcpy(rep, F.bar, sizeof(rep), hipMemcpyDeviceToHost));
+    if (rep[2] != 0)
+      cgp_last_report = "workgroup " + std::to_string(rep[3]) + " of " + std::to_string((F.V + 1) / 2) +
+                        " timed out at phase " + std::to_string(rep[4]) + " waiting for workgroup " +
+                        std::to_string(rep[5]) + " (its flag: " + std::to_string(rep[6]) + ")";
+    WCMG_HIP(hipMemsetAsync(F.bar, 0, F.nbar * sizeof(unsigned), stream));
+    WCMG_HIP(hipStreamSynchronize(stream));
+  }
+}
 
 int Context::store_prec_for(int l, bool single) const {
   (void)l;
@@ -598,10 +693,12 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
   launch_dot<R>(b, 0, 1, nullptr, b, nn, part, 1, misc + 0, 1, 0, live, stream);
   const int limit = fixed > 0 ? fixed : maxit;
   const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
-  auto read_state = [&]() {
-    WCMG_HIP(hipMemcpyAsync(pinned, st, 5 * sizeof(int), hipMemcpyDeviceToHost, stream));
-    sync();
-  };
+  // Progress checks: within a cycle the host reads the state published at
+  // the previous check while the steps since are already queued (a stopped
+  // solve makes them no-ops through the run flag); at a cycle's end it waits
+  // for the current state.
+  StateChecks chk{*this, st, 5};
+  const int* last = nullptr;
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     if (cyc == 0 && x0_zero) {
       launch_convert<R, R>(b, V, nn, live, stream);
@@ -637,8 +734,8 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
         launch_gmres_sr_finish(st, S, m, j, tmp, tmp2, part, G2, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
         if (j + 1 < m) launch_update_scale<R>(wj, V, nn, j + 1, tmp, misc + 3, nn, run, stream);
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-          read_state();
-          if (!pinned[0]) break;
+          const int* sv = chk.ahead();
+          if (sv && !sv[0]) break;
         }
         continue;
       }
@@ -662,22 +759,19 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
       launch_gmres_givens(st, S, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
       if (j + 1 < m) launch_scale_inv_norm<R>(V + (long)(j + 1) * nn, w, misc + 3, nn, run, stream);
       if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-        read_state();
-        if (!pinned[0]) break;
+        const int* sv = chk.ahead();
+        if (sv && !sv[0]) break;
       }
     }
     launch_gmres_solve_y(st, S, m, stream);
     launch_multi_axpy<R>(x, M ? Z : V, nn, m, st + 2, y, 1, 1.0, nn, nullptr, stream);
     launch_gmres_cycle_end(st, stream);
     if (check_every > 0) {
-      read_state();
-      if (!pinned[1]) break;
+      last = chk.now();
+      if (!last[1]) break;
     }
   }
-  if (check_every > 0) {
-    read_state();
-    return pinned[3];
-  }
+  if (check_every > 0) return (last ? last : chk.now())[3];
   return -1;
 }
 
@@ -714,49 +808,46 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
   const int fixed = p.coarse_fixed_iters;
   const int limit = fixed > 0 ? fixed : p.coarse_maxit;
   const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
-  auto read_state = [&]() {
-    WCMG_HIP(hipMemcpyAsync(pinned, st, 5 * sizeof(int), hipMemcpyDeviceToHost, stream));
-    sync();
-  };
+  StateChecks chk{*this, st, 5};  // as in gmres()
+  const int* last = nullptr;
   const char* fam = prec == WCMG_F64 ? "coarse_gmres_step_f64" : prec == WCMG_F32 ? "coarse_gmres_step_f32"
                                                                                      : "coarse_gmres_step_bf16";
   // one cooperative launch for the whole solve when the blocks fit the LDS
-  // (reserved[0] flag 4 turns it off); the state is read back to check the
-  // barrier words, so only with host checks
+  // (reserved[0] flag 4 turns it off); only where the host checks progress,
+  // since its report is checked by the host (not under stream capture)
   if (!five && check_every > 0 && !(p.reserved[0] & 4) && cg_persistent_fits(prec, nb, C.V)) {
     cd64* partP = buf<cd64>("cgp_part" + t, (long)cg_persistent_part_elems(C.V));
     const long nbar = (long)cg_persistent_bar_words(C.V);
     unsigned* bar = buf<unsigned>("cgp_bar" + t, nbar);
     cplx<R>* zP = buf<cplx<R>>("cgp_z" + t, 2 * nn);
-    cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
-    // the flags keep counting phases from launch to launch; they are cleared
-    // only for a new buffer or after a timed-out launch
-    unsigned& phase = cgp_phase[t];
-    if (cgp_bar_at[t] != (void*)bar) phase = 0;
-    if (phase == 0) WCMG_HIP(hipMemsetAsync(bar, 0, nbar * sizeof(unsigned), stream));
-    cgp_bar_at[t] = (void*)bar;
-    volatile int* mb = mailbox;
-    mb[0] = kCgpPending;
+    // a new buffer starts with cleared flags and phase (launches on the old
+    // one are checked first)
+    if (cgp_bar_at[t] != (void*)bar) {
+      sync();
+      WCMG_HIP(hipMemsetAsync(bar, 0, nbar * sizeof(unsigned), stream));
+      cgp_bar_at[t] = (void*)bar;
+    }
+    // reserved[0] flag 16: waits that give up at once; each launch is then
+    // checked at once and a timed-out solve redone by the multi-kernel form.
+    // Flag 128: the first launch's waits give up at once, checked later.
+    const bool give_up = (p.reserved[0] & 16) != 0;
+    const bool force_late = (p.reserved[0] & 128) && !cgp_forced;
+    cgp_forced = cgp_forced || force_late;
+    const int seq = ++cgp_seq;
     prof.begin("coarse_gmres_persistent", stream);
     const bool launched = launch_cg_persistent(prec, nb, blk, C.nbr.as<int>(), C.V, b, x, zP, r, partP, misc, st,
-                                               parent, m, p.coarse_tol, limit, fixed, bar, phase, mailbox_dev,
-                                               (p.reserved[0] & 16) ? 0.0 : 5.0, stream);
+                                               parent, m, p.coarse_tol, limit, fixed, bar, seq, mailbox_dev,
+                                               give_up || force_late ? 0.0 : 5.0, stream);
     prof.end("coarse_gmres_persistent", stream);
     if (launched) {
+      cgp_pending.push_back(CgpLaunch{seq, bar, nbar, C.V});
+      // checked (and counted) when the host next waits for the stream; the
+      // report slots bound how many launches may stay unchecked
+      if (!give_up && (int)cgp_pending.size() < kCgpSlots / 2) return -1;
+      const long before = cgp_fallbacks;
       sync();
-      if (mb[0] == 0) {
-        phase = (unsigned)mb[4];
-        return mb[3];
-      }
-      // a barrier wait timed out (the mailbox was not written): keep the
-      // report, clear the flags before the next launch, redo the solve below
-      WCMG_HIP(hipMemcpyAsync(pinned + 8, bar, 8 * sizeof(unsigned), hipMemcpyDeviceToHost, stream));
-      sync();
-      phase = 0;
-      cgp_fallbacks++;
-      cgp_last_report = "workgroup " + std::to_string(pinned[11]) + " of " + std::to_string((C.V + 1) / 2) +
-                        " timed out at phase " + std::to_string(pinned[12]) + " waiting for workgroup " +
-                        std::to_string(pinned[13]) + " (its flag: " + std::to_string(pinned[14]) + ")";
+      if (cgp_fallbacks == before) return -1;
+      // this launch timed out: redo the solve below
     }
   }
   launch_gmres_init(st, parent, stream);
@@ -782,22 +873,19 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
       launch_cg_orth<R>(V, j, w, nn, partB, (int)G2, S, m, 1, partC, run, stream);
       launch_cg_givens(st, S, m, j, partC, (int)G2, p.coarse_tol, limit, fixed, stream);
       if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-        read_state();
-        if (!pinned[0]) break;
+        const int* sv = chk.ahead();
+        if (sv && !sv[0]) break;
       }
     }
     launch_gmres_solve_y(st, S, m, stream);
     launch_multi_axpy<R>(x, V, nn, m, st + 2, y, 1, 1.0, nn, nullptr, stream);
     launch_gmres_cycle_end(st, stream);
     if (check_every > 0) {
-      read_state();
-      if (!pinned[1]) break;
+      last = chk.now();
+      if (!last[1]) break;
     }
   }
-  if (check_every > 0) {
-    read_state();
-    return pinned[3];
-  }
+  if (check_every > 0) return (last ? last : chk.now())[3];
   return -1;
 }
 

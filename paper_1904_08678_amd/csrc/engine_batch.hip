@@ -271,13 +271,12 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
   launch_bdot<R>(b, 0, nn, 1, b, nn, nn, B, part, misc + 0, 1, ss, 0, live, 8, stream);
   const int limit = fixed > 0 ? fixed : maxit;
   const int max_cycles = check_every > 0 ? limit : (limit + m - 1) / m;
-  auto read_state = [&]() {
-    WCMG_HIP(hipMemcpyAsync(pinned + 64, st, 8 * B * sizeof(int), hipMemcpyDeviceToHost, stream));
-    sync();
-  };
-  auto any = [&](int word) {
+  // progress checks as in Context::gmres: 8 state words per right-hand side
+  StateChecks chk{*this, st, 8 * B};
+  const int* last = nullptr;
+  auto any = [&](const int* sv, int word) {
     for (int r = 0; r < B; ++r)
-      if (pinned[64 + 8 * r + word]) return true;
+      if (sv[8 * r + word]) return true;
     return false;
   };
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
@@ -313,8 +312,8 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
         launch_bgmres_givens(st, S, ss, B, m, j, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
         if (j + 1 < m) launch_bupdate_scale<R>(wj, nn, V, bn, nn, j + 1, tmp, ss, misc + 3, ss, nn, B, run, 8, stream);
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-          read_state();
-          if (!any(0)) break;
+          const int* sv = chk.ahead();
+          if (sv && !any(sv, 0)) break;
         }
         continue;
       }
@@ -338,22 +337,22 @@ void Context::gmresB(BatchGmres& G, const BatchOp<R>& A, const BatchOp<R>* M, co
         launch_belem<cplx<R>, cplx<R>>(V + (j + 1) * bn, nn, w, nn, nullptr, 0, misc + 3, ss, nn, B, 3, run, 8,
                                        stream);
       if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-        read_state();
-        if (!any(0)) break;
+        const int* sv = chk.ahead();
+        if (sv && !any(sv, 0)) break;
       }
     }
     launch_bgmres_solve_y(st, S, ss, B, m, stream);
     launch_bmulti_axpy<R>(x, nn, M ? Z : V, bn, nn, m, st + 2, 8, y, 1, ss, 1.0, nn, B, nullptr, nullptr, 0, stream);
     launch_bgmres_cycle_end(st, B, stream);
     if (check_every > 0) {
-      read_state();
-      if (!any(1)) break;
+      last = chk.now();
+      if (!any(last, 1)) break;
     }
   }
   if (check_every > 0) {
-    read_state();
+    if (!last) last = chk.now();
     if (iters)
-      for (int r = 0; r < B; ++r) iters[r] = pinned[64 + 8 * r + 3];
+      for (int r = 0; r < B; ++r) iters[r] = last[8 * r + 3];
   }
 }
 

@@ -185,18 +185,21 @@ template <typename R>
 void launch_update_scale(cplx<R>* y, const cplx<R>* V, long vstride, int m, const cd64* coef, const cd64* nrm2,
                          long n, const int* run, hipStream_t st);
 void launch_gmres_cycle_end(int* st_, hipStream_t st);
+// copies st[0..n) to out[1..n] (host-mapped memory), then out[0] = seq
+void launch_publish_state(const int* st_, int n, int* out, int seq, hipStream_t st);
 
 // ---- the coarsest GMRES in one cooperative launch (coarse_persist.hip):
 // false (nothing launched) when the operator's blocks, basis and image do not
 // fit the LDS of co-resident workgroups; part: cd64 [cg_persistent_part_elems];
-// bar: cg_persistent_bar_words zeroed words (bar[2] is set when a barrier
-// wait timed out, bar[3..6] then hold the first timed-out workgroup, the
-// phase, the workgroup it waited for and the flag value it saw; the flags
-// hold phase numbers, which continue from phase0, the final phase of the
-// previous launch on the same buffer); mailbox (host-mapped, coherent): at a
-// normal end workgroup 0 writes [1] live flag, [3] iterations, [4] final
-// phase, then [0] = 0; a launch that ended otherwise leaves [0] as the host
-// set it; misc: the
+// bar: cg_persistent_bar_words words, zeroed with the buffer (bar[2] is set
+// when a barrier wait timed out, bar[3..6] then hold the first timed-out
+// workgroup, the phase, the workgroup it waited for and the flag value it
+// saw; bar[8] holds the phase the flags have reached, which the next launch
+// on the buffer continues from; a launch that starts with bar[2] set writes
+// x = 0 and reports nothing); mailbox (host-mapped, coherent, kCgpMailboxInts
+// ints): at a normal end workgroup 0 writes the report slot of `seq`
+// (mailbox[kCgpSlot0 + 2 (seq mod kCgpSlots)] = seq, the next word the
+// iteration count), [1] live flag, [3] iterations, then [0] = seq; misc: the
 // solve's residual words, as the multi-kernel form writes them; z: 2 Vc Nb
 // vector elements; r: Vc Nb
 bool cg_persistent_fits(int prec, int nb, long Vc);
@@ -204,10 +207,11 @@ size_t cg_persistent_part_elems(long Vc);
 size_t cg_persistent_bar_words(long Vc);
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
-                          int limit, int fixed, unsigned* bar, unsigned phase0, int* mailbox, double timeout_s,
+                          int limit, int fixed, unsigned* bar, int seq, int* mailbox, double timeout_s,
                           hipStream_t stream);
-// mailbox word 0 while a cooperative coarsest solve has not reported
-constexpr int kCgpPending = 0x5a5a5a5a;
+constexpr int kCgpSlot0 = 16;       // first report slot in the mailbox
+constexpr int kCgpSlots = 64;       // report slots (a power of two)
+constexpr int kCgpMailboxInts = kCgpSlot0 + 2 * kCgpSlots;
 
 // ---- fused coarse GMRES (coarse_gmres.hip)
 bool cg_fused_supported(int nb);

@@ -490,6 +490,44 @@ def test_cooperative_coarse_gmres_timeout_falls_back():
     assert abs(i0["outer_iters"] - i4["outer_iters"]) <= 1
 
 
+def test_cooperative_coarse_gmres_late_check_after_timeout():
+    """The host checks a cooperative coarsest solve only at the next progress
+    check.  reserved[0] flag 128 makes the first launch's waits give up at
+    once (every kernel still exits normally): that launch and the ones queued
+    after it before the check return x = 0 (a weaker preconditioner for those
+    outer steps), the check counts them, clears the barrier words and
+    describes the time-out, and the later launches run normally.  The solve
+    still reaches 1e-10 in about the iterations of the unforced solve, and a
+    second solve on the context has no fallback."""
+    w = wc()
+    L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 1941)
+    start = syn.complex_gaussian((nv, V, 12), 1942)
+    b = syn.complex_gaussian((V, 4, 3), 1943)
+    res = []
+    for flags in (128, 0):
+        ctx = w.Context(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), cycle_prec=w.F32,
+                        coarse_store_prec=w.F32, setup_prec=w.F32, reserved=(flags,))
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        x, info, st = ctx.solve(dev(b))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        f1 = ctx.timers()["coarse_solve_fallbacks"]
+        err = w.lib().wcmg_last_error(ctx.h)
+        x2, info2, st2 = ctx.solve(dev(b))
+        assert st2 == 0 and info2[0]["true_rel_res"] <= 1e-10
+        f2 = ctx.timers()["coarse_solve_fallbacks"] - f1
+        res.append((host(x), info[0], f1, err, f2, info2[0]))
+    (x128, i128, f128, e128, g128, j128), (x0, i0, f0, _, g0, j0) = res
+    assert f128 >= 1 and f0 == 0 and g128 == 0 and g0 == 0
+    assert b"timed out" in e128, e128
+    assert i128["outer_iters"] <= i0["outer_iters"] + 3
+    # after the recovery the cooperative form runs as in a fresh context
+    assert j128["outer_iters"] == j0["outer_iters"]
+
+
 @pytest.mark.parametrize("levels,mixed,eo,restart", [(2, True, 0, 20), (2, False, 0, 20), (1, False, 0, 20),
                                                      (2, True, 1, 20), (2, True, 0, 5), (1, False, 0, 7)])
 def test_single_reduction_outer_step_matches_cgs2(levels, mixed, eo, restart):
