@@ -78,17 +78,26 @@ void gmres_multi(std::vector<Slot>& q, const JointOp<R>& A, const JointOp<R>* M,
                                      stream);
     launch_bdot<R>(b[k], 0, nn[k], 1, b[k], nn[k], nn[k], B, part(k), misc[k] + 0, 1, ss[k], 0, live[k], 8, stream);
   }
-  auto read_state = [&]() {
-    for (size_t k = 0; k < K; ++k)
-      WCMG_HIP(hipMemcpyAsync(q[k].c->pinned + 64, st[k], 8 * q[k].B * sizeof(int), hipMemcpyDeviceToHost, stream));
-    WCMG_HIP(hipStreamSynchronize(stream));
-  };
+  // progress checks as in Context::gmres, every problem's state published on
+  // the shared stream (through the first context)
+  std::vector<Context::StateChecks> chk;
+  for (size_t k = 0; k < K; ++k) chk.push_back(Context::StateChecks{*q[0].c, st[k], 8 * q[k].B});
+  std::vector<const int*> sv(K, nullptr);
   auto any = [&](int word) {
     for (size_t k = 0; k < K; ++k)
       for (int r = 0; r < q[k].B; ++r)
-        if (q[k].c->pinned[64 + 8 * r + word]) return true;
+        if (sv[k][8 * r + word]) return true;
     return false;
   };
+  auto check_ahead = [&]() {  // false while the previous check's state is not known
+    bool known = true;
+    for (size_t k = 0; k < K; ++k) known = (sv[k] = chk[k].ahead()) != nullptr && known;
+    return known;
+  };
+  auto check_now = [&]() {
+    for (size_t k = 0; k < K; ++k) sv[k] = chk[k].now();
+  };
+  bool have_last = false;
   std::vector<const cplx<R>*> cin(K);
   std::vector<cplx<R>*> cout(K);
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
@@ -175,8 +184,7 @@ void gmres_multi(std::vector<Slot>& q, const JointOp<R>& A, const JointOp<R>* M,
         }
       }
       if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-        read_state();
-        if (!any(0)) break;
+        if (check_ahead() && !any(0)) break;
       }
     }
     for (size_t k = 0; k < K; ++k) {
@@ -187,15 +195,16 @@ void gmres_multi(std::vector<Slot>& q, const JointOp<R>& A, const JointOp<R>* M,
       launch_bgmres_cycle_end(st[k], B, stream);
     }
     if (check_every > 0) {
-      read_state();
+      check_now();
+      have_last = true;
       if (!any(1)) break;
     }
   }
   if (check_every > 0) {
-    read_state();
+    if (!have_last) check_now();
     if (iters)
       for (size_t k = 0; k < K; ++k)
-        for (int r = 0; r < q[k].B; ++r) (*iters)[k][r] = q[k].c->pinned[64 + 8 * r + 3];
+        for (int r = 0; r < q[k].B; ++r) (*iters)[k][r] = sv[k][8 * r + 3];
   }
 }
 
