@@ -781,7 +781,7 @@ def kernel_mode(args):
         L = wl["L"]
         V = int(np.prod(L))
         s = syn.config_seeds(wl["seed"])
-        ctx = make_context(w, wl, mixed=True)
+        ctx = make_context(w, wl, mixed=True, reserved=args.reserved)
         ctx.set_gauge(torch.from_numpy(syn.gauge_field(L, wl["eps"], s["gauge"])).cuda())
         ctx.set_null_vectors(0, torch.from_numpy(syn.start_vectors(wl["nv"], V, 12, s["start"])).cuda())
         ctx.setup()
