@@ -792,6 +792,13 @@ def kernel_mode(args):
         print(json.dumps({"family": fam, "solve_s": time.perf_counter() - t0, "status": st,
                           "outer_iters": [i["outer_iters"] for i in info]}))
         return
+    if fam == "coarse_latency":
+        # the latency line of the cooperative coarsest GMRES on its own
+        U, start, _ = make_inputs(WORKLOAD)
+        res = coarse_gmres_latency(w, torch, WORKLOAD, torch.from_numpy(U).cuda(), torch.from_numpy(start).cuda(),
+                                   reps=args.reps)
+        print(json.dumps({"family": fam, **res}))
+        return
     if fam.startswith("coarse_mk"):
         store = {"f64": w.F64, "f32": w.F32, "bf16": w.BF16}[fam.split("_")[-1]]
         res = coarse_apply_mk(w, torch, stores=(store,), reps=args.reps, nrhs_batch=args.nrhs)
@@ -846,7 +853,7 @@ def main():
     ap.add_argument("--kernel", dest="family", default=None,
                     help="only launch one kernel family: dslash_f32, dslash_f64, restrict_f32, prolong_f32, "
                          "coarse_mk_f32, coarse_mk_bf16, coarse_mk_f64, copy, batched_solve, learned_setup, "
-                         "three_level, ragged_solve, oracle_m2")
+                         "three_level, ragged_solve, oracle_m2, coarse_latency")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--reserved", type=int, default=0, help="kernel mode: reserved[0] flags (reference forms)")
     ap.add_argument("--graph", action="store_true", help="batched_solve kernel mode: HIP-graph cycle")
