@@ -89,8 +89,15 @@ __device__ inline bool pbarrier(unsigned* bar, unsigned G, unsigned phase, int* 
   const long long t0 = wall_clock64();
   for (unsigned g = threadIdx.x; g < G && !bad; g += blockDim.x) {
     unsigned seen;
+    unsigned spins = 0;
     while ((seen = __hip_atomic_load(flags + (size_t)kFlagWords * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
            phase) {
+      // the error word and the clock are looked at every 16th poll only, so a
+      // poll is one memory round trip (every poll with a zero time limit)
+      if ((++spins & 15) != 0 && tick_limit > 0) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         bad = 1;
         break;
@@ -442,6 +449,7 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
       cplx<R> aw = apply_staged(sv);
       cplx<R> wv = zj;
       if (own)
+#pragma unroll 4
         for (int i = 0; i <= j; ++i) {
           const cplx<R> h = cneg(mkc((R)hs[i].re, (R)hs[i].im));
           cfma(wv, h, vl[i][lr]);
@@ -485,16 +493,19 @@ __global__ void __launch_bounds__(256) k_cg_persistent(
         const double hn2 = scal[0] > 0.0 ? scal[0] : 0.0;
         const double hn = sqrt(hn2);
         scal[0] = hn2;
+        // the entry being rotated down the column stays in registers, so the
+        // loads of the next rotation do not wait for this one's stores
+        cd64 a = hcol[0];
+#pragma unroll 4
         for (int i = 0; i < j; ++i) {
-          const cd64 a = hcol[i], bb = hcol[i + 1];
-          cd64 tt = cmul(csv[i], a);
-          cfma(tt, snv[i], bb);
-          cd64 uu = cmul(cneg(cconj(snv[i])), a);
-          cfma(uu, cconj(csv[i]), bb);
+          const cd64 bb = hcol[i + 1], ci = csv[i], si = snv[i];
+          cd64 tt = cmul(ci, a);
+          cfma(tt, si, bb);
+          cd64 uu = cmul(cneg(cconj(si)), a);
+          cfma(uu, cconj(ci), bb);
           hcol[i] = tt;
-          hcol[i + 1] = uu;
+          a = uu;
         }
-        const cd64 a = hcol[j];
         const double den = sqrt(a.re * a.re + a.im * a.im + hn2);
         const cd64 cc = den == 0.0 ? mkc(1.0, 0.0) : mkc(a.re / den, -a.im / den);
         const cd64 ss = den == 0.0 ? mkc(0.0, 0.0) : mkc(hn / den, 0.0);
