@@ -303,53 +303,62 @@ __global__ void k_mr_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, co
 
 // The MR update with the step length formed from the operator's
 // per-workgroup partials (part[2g] = <p, r>_g, part[2g+1] = <p, p>_g, g < G)
-// by every workgroup itself, in the order of k_dot_finish (per-thread strided
-// sums, wave sums, waves in order), so all workgroups hold the same alpha and
-// it equals the one a separate k_dot_finish launch would give.  xout !=
-// nullptr: the updated x is written there in FP64 (x itself is left as is).  A fixed grid
-// of kMrGrid workgroups keeps the partials' reads down; each thread updates
-// four elements per pass.
-constexpr int kMrGrid = 1024;
+// by every workgroup itself, in the order of k_dot_finish (the first 256
+// threads: per-thread strided sums, wave sums, waves in order), so all
+// workgroups hold the same alpha and it equals the one a separate
+// k_dot_finish launch would give.  xout != nullptr: the updated x is written
+// there in FP64 (x itself is left as is).  A fixed grid of kMrGrid workgroups
+// of kMrBlock threads (one per CU) keeps the partials' reads down; each thread
+// updates four elements per pass, and the first pass's operands are loaded
+// before the partials are summed, so the two latencies overlap.
+constexpr int kMrGrid = 256;
+constexpr int kMrBlock = 1024;
 template <typename R>
-__global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
-                                                         const cplx<R>* __restrict__ p, const cd64* __restrict__ part,
-                                                         int G, long n, const int* __restrict__ run,
-                                                         cd64* __restrict__ xout) {
+__global__ void __launch_bounds__(kMrBlock) k_mr_update_part(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
+                                                              const cplx<R>* __restrict__ p,
+                                                              const cd64* __restrict__ part, int G, long n,
+                                                              const int* __restrict__ run, cd64* __restrict__ xout) {
   if (run && !*run) return;
   __shared__ cd64 lds[2][4];
-  cd64 s0 = mkc(0.0, 0.0), s1 = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
-    s0 = cadd(s0, part[2L * g]);
-    s1 = cadd(s1, part[2L * g + 1]);
-  }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    lds[0][wave] = s0;
-    lds[1][wave] = s1;
-  }
-  __syncthreads();
-  cd64 t0 = mkc(0.0, 0.0), t1 = mkc(0.0, 0.0);
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    t0 = cadd(t0, lds[0][w]);
-    t1 = cadd(t1, lds[1][w]);
-  }
-  const double pp = t1.re;
-  const cd64 al = pp > 0.0 ? mkc(t0.re / pp, t0.im / pp) : mkc(0.0, 0.0);
-  const cplx<R> a = mkc((R)al.re, (R)al.im), na = cneg(a);
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
-    cplx<R> xi[4], ri[4], pi[4];
+  long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  cplx<R> xi[4], ri[4], pi[4];
+  auto load = [&](long b) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const long i = i0 + u * stride;
+      const long i = b + u * stride;
       if (i < n) {
         xi[u] = x[i];
         ri[u] = r[i];
         pi[u] = p[i];
       }
     }
+  };
+  load(i0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 256) {
+    cd64 s0 = mkc(0.0, 0.0), s1 = mkc(0.0, 0.0);
+    for (int g = threadIdx.x; g < G; g += 256) {
+      s0 = cadd(s0, part[2L * g]);
+      s1 = cadd(s1, part[2L * g + 1]);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      lds[0][wave] = s0;
+      lds[1][wave] = s1;
+    }
+  }
+  __syncthreads();
+  cd64 t0 = mkc(0.0, 0.0), t1 = mkc(0.0, 0.0);
+  for (int w = 0; w < 4; ++w) {
+    t0 = cadd(t0, lds[0][w]);
+    t1 = cadd(t1, lds[1][w]);
+  }
+  const double pp = t1.re;
+  const cd64 al = pp > 0.0 ? mkc(t0.re / pp, t0.im / pp) : mkc(0.0, 0.0);
+  const cplx<R> a = mkc((R)al.re, (R)al.im), na = cneg(a);
+  for (; i0 < n; i0 += 4 * stride) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const long i = i0 + u * stride;
@@ -361,6 +370,7 @@ __global__ void __launch_bounds__(256) k_mr_update_part(cplx<R>* __restrict__ x,
         r[i] = ri[u];
       }
     }
+    if (i0 + 4 * stride < n) load(i0 + 4 * stride);
   }
 }
 
@@ -682,7 +692,7 @@ void launch_mr_update(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* dots
 template <typename R>
 void launch_mr_update_part(cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cd64* part, int G, long n, const int* run,
                            hipStream_t st, cd64* xout) {
-  hipLaunchKernelGGL(k_mr_update_part<R>, dim3((unsigned)std::min<long>(kMrGrid, nblocks(n))), dim3(kBlock), 0, st, x,
+  hipLaunchKernelGGL(k_mr_update_part<R>, dim3((unsigned)std::min<long>(kMrGrid, nblocks(n, kMrBlock))), dim3(kMrBlock), 0, st, x,
                      r, p, part, G, n, run, xout);
   WCMG_CHECK_LAUNCH();
 }
