@@ -12,7 +12,7 @@ One step = the whole path on that input: setup (relaxation, chirality-split
 Gram-Schmidt, Galerkin coarsening, refinement) and the mixed-precision solve
 (FP32 smoother, restriction, prolongation and coarse arithmetic with FP32
 coarse blocks; FP64 outer solver; each coarsest GMRES solve is one
-cooperative launch).  `value` is the solve time of the mixed solve (seconds to
+persistent launch).  `value` is the solve time of the mixed solve (seconds to
 1e-10); the plain FP64 solve, the same solve with reference forms of the
 coarsest GMRES (four kernels per step) and of the outer Arnoldi step (CGS2),
 the coarse-apply bandwidth on a large synthetic coarse lattice (Nb 16, 24,
@@ -258,7 +258,7 @@ def coarse_apply_mk(w, torch, nb=24, dims=(16, 16, 16, 32), stores=None, reps=20
 
 
 def coarse_gmres_latency(w, torch, wl, Ud, startd, reps=20, iters=(4, 16)):
-    """The coarsest GMRES as one cooperative launch is bound by the latency of
+    """The coarsest GMRES as one persistent launch is bound by the latency of
     its grid barriers, not by a byte stream: its time per Arnoldi step is the
     slope of the launch time over the number of steps (fixed iteration
     counts, one restart cycle), the intercept the per-launch cost (blocks into
@@ -288,12 +288,15 @@ def coarse_gmres_latency(w, torch, wl, Ud, startd, reps=20, iters=(4, 16)):
 
 
 def reference_forms(w, torch, wl, Ud, startd, bd):
-    """The same mixed solve with reference forms of two solver steps: the
+    """The same mixed solve with reference forms of solver steps: the
     coarsest GMRES as four kernels per Arnoldi step instead of one
-    cooperative launch (flag 4), and the outer Arnoldi step as classical
-    Gram-Schmidt applied twice instead of one reduction per step (flag 8)."""
+    persistent launch (flag 4), the outer Arnoldi step as classical
+    Gram-Schmidt applied twice instead of one reduction per step (flag 8),
+    both, and the persistent launch through the cooperative-launch API
+    (flag 256)."""
     out = {}
-    for name, flags in (("coarse_gmres_four_kernels", 4), ("outer_cgs2", 8), ("both", 12)):
+    for name, flags in (("coarse_gmres_four_kernels", 4), ("outer_cgs2", 8), ("both", 12),
+                        ("coarse_gmres_cooperative_api", 256)):
         ctx = make_context(w, wl, mixed=True, reserved=flags)
         ctx.set_gauge(Ud)
         ctx.set_null_vectors(0, startd)
@@ -793,7 +796,7 @@ def kernel_mode(args):
                           "outer_iters": [i["outer_iters"] for i in info]}))
         return
     if fam == "coarse_latency":
-        # the latency line of the cooperative coarsest GMRES on its own
+        # the latency line of the persistent coarsest GMRES on its own
         U, start, _ = make_inputs(WORKLOAD)
         res = coarse_gmres_latency(w, torch, WORKLOAD, torch.from_numpy(U).cuda(), torch.from_numpy(start).cuda(),
                                    reps=args.reps)
@@ -894,7 +897,7 @@ def main():
     ctx = make_context(w, wl, mixed=True)
     ctx.set_gauge(Ud)
     ctx.set_null_vectors(0, startd)
-    # HBM-bound families (the roofline candidates), then the cooperative
+    # HBM-bound families (the roofline candidates), then the persistent
     # coarse GMRES, which is bound by its grid barriers, not by a stream
     roof_families = ["dslash_f64", "dslash_f32", "coarse_apply_f32", "restrict_f32", "prolong_f32"]
     families = roof_families + ["coarse_gmres_persistent"]

@@ -108,14 +108,16 @@ typedef struct {
   int32_t reserved[1];     /* reserved[0]: flags selecting reference forms, for comparisons (default 0):
                               1 no host progress checks inside cycles; 2 the generic coarsest GMRES;
                               4 the coarsest GMRES as four kernels per Arnoldi step instead of one
-                              cooperative launch; 8 the outer Arnoldi step as classical Gram-Schmidt applied
-                              twice instead of the single-reduction step; 16 the cooperative launch's barrier
+                              persistent launch; 8 the outer Arnoldi step as classical Gram-Schmidt applied
+                              twice instead of the single-reduction step; 16 the persistent launch's barrier
                               waits give up at once and every launch is checked before the next step (every
                               such solve then takes the four-kernel fallback: a test of that path); 32 the
                               fine Dslash reads neighbours from a table instead of site arithmetic; 64 full
-                              3x3 links instead of two rows; 128 the first cooperative launch's waits give up
+                              3x3 links instead of two rows; 128 the first persistent launch's waits give up
                               at once and its failure is found at the next progress check (the launches in
-                              between return x = 0: a test of the deferred check) */
+                              between return x = 0: a test of the deferred check); 256 the persistent coarsest
+                              GMRES launched through the cooperative-launch API (guaranteed co-residency; it
+                              synchronises with a separate device queue before and after each launch) */
 } wcmg_params;
 
 typedef struct wcmg_ctx wcmg_ctx;
@@ -367,7 +369,7 @@ int wcmg_timers(wcmg_ctx* ctx, double* out_host, int n);
  * (batched coarse apply on the matrix cores), "coarse_gmres_step_f64",
  * "coarse_gmres_step_f32", "coarse_gmres_step_bf16" (apply step of the fused
  * coarsest GMRES), "coarse_gmres_persistent" (a whole coarsest GMRES solve
- * as one cooperative launch), "restrict_f64", "restrict_f32", "prolong_f64",
+ * as one persistent launch), "restrict_f64", "restrict_f32", "prolong_f64",
  * "prolong_f32", "sap_f64", "sap_f32" (one SAP colour), "nn_forward",
  * "nn_backward" (network, on its own context).  Stats return the number of
  * timed launches and their total duration in milliseconds, then reset. */

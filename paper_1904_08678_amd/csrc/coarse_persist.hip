@@ -1,6 +1,6 @@
 // The coarsest-level GMRES (Sec. 2.1: GMRES is the coarse-grid solver) as one
-// cooperative launch for a whole solve, when the coarse operator fits the
-// chip's LDS: each workgroup owns at most two coarse sites, loads their nine
+// persistent launch for a whole solve (every workgroup resident at once, with
+// grid-wide barriers), when the coarse operator fits the chip's LDS: each workgroup owns at most two coarse sites, loads their nine
 // blocks into LDS once and keeps them there for every matrix-vector product
 // of every Arnoldi step and restart.  The Krylov basis V and its image
 // Z = A V stay in LDS too, for the workgroup's own rows.
@@ -46,6 +46,8 @@
 // without reporting; a launch that starts with the error word set returns
 // x = 0 at once; the host clears the flags when it next checks.  A fault in
 // the launch configuration cannot hang the device.
+#include <map>
+
 #include "coarse_common.h"
 
 namespace wcmg {
@@ -588,23 +590,36 @@ bool cgp_shape_fits() {
 }
 
 // Returns false (and launches nothing) when the workgroups cannot all be
-// co-resident or there is no cooperative launch.
+// co-resident.  The grid is launched as an ordinary kernel (one workgroup per
+// CU at most, nothing else on the stream while it runs, so all workgroups are
+// resident together); coop: through the cooperative-launch API instead, which
+// guarantees co-residency but synchronises with a separate device queue before
+// and after the launch.  Every barrier wait has a time limit either way.
 template <int P, int NB>
 bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* z, void* r, cd64* part,
                 cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
-                int seq, int* mailbox, long long tick_limit, hipStream_t stream) {
+                int seq, int* mailbox, long long tick_limit, bool coop_api, hipStream_t stream) {
   if constexpr (!PShape<P, NB>::fits) {
     return false;
   } else {
     typedef typename BlkTraits<P>::R R;
     auto kern = k_cg_persistent<P, NB>;
-    int dev = 0, cus = 0, coop = 0, per_cu = 0;
+    // device properties and the occupancy, per device (queried once)
+    struct Props {
+      int cus = 0, coop = 0, per_cu = -1;
+    };
+    static thread_local std::map<int, Props> props;
+    int dev = 0;
     WCMG_HIP(hipGetDevice(&dev));
-    WCMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    WCMG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-    WCMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
+    Props& pr = props[dev];
+    if (pr.per_cu < 0) {
+      WCMG_HIP(hipDeviceGetAttribute(&pr.cus, hipDeviceAttributeMultiprocessorCount, dev));
+      WCMG_HIP(hipDeviceGetAttribute(&pr.coop, hipDeviceAttributeCooperativeLaunch, dev));
+      WCMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pr.per_cu, kern, 256, 0));
+    }
     const long G = (Vc + kPSpw - 1) / kPSpw;
-    if (!coop || per_cu < 1 || G > (long)cus * per_cu || m + 1 > kPMaxM1 || m < 1) return false;
+    if ((coop_api && !pr.coop) || pr.per_cu < 1 || G > (long)pr.cus * pr.per_cu || m + 1 > kPMaxM1 || m < 1)
+      return false;
     const Chunk16* bk = (const Chunk16*)blk;
     const cplx<R>* bc = (const cplx<R>*)b;
     cplx<R>* xx = (cplx<R>*)x;
@@ -614,7 +629,10 @@ bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x
                     (void*)&rr,   (void*)&part, (void*)&misc, (void*)&st,    (void*)&parent, (void*)&m,
                     (void*)&tol,  (void*)&limit, (void*)&fixed, (void*)&bar, (void*)&seq,
                     (void*)&mailbox, (void*)&tick_limit};
-    WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
+    if (coop_api)
+      WCMG_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
+    else
+      WCMG_HIP(hipLaunchKernel((const void*)kern, dim3((unsigned)G), dim3(256), args, 0, stream));
     return true;
   }
 }
@@ -651,15 +669,17 @@ size_t cg_persistent_bar_words(long Vc) { return (size_t)kBarWords + (size_t)kFl
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
                           int limit, int fixed, unsigned* bar, int seq, int* mailbox, double timeout_s,
-                          hipStream_t stream) {
+                          bool coop_api, hipStream_t stream) {
   if (!cg_persistent_fits(prec, nb, Vc)) return false;
-  int dev = 0, khz = 0;
+  static thread_local std::map<int, int> rate;
+  int dev = 0;
   WCMG_HIP(hipGetDevice(&dev));
-  WCMG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (!rate.count(dev)) WCMG_HIP(hipDeviceGetAttribute(&rate[dev], hipDeviceAttributeWallClockRate, dev));
+  const int khz = rate[dev];
   const long long tick_limit = (long long)(timeout_s * 1000.0 * (khz > 0 ? khz : 100000));
 #define CGP(PP, NBc) \
   return cgp_launch<PP, NBc>(blk, nbr, Vc, b, x, z, r, part, misc, st, parent, m, tol, limit, fixed, bar, \
-                             seq, mailbox, tick_limit, stream)
+                             seq, mailbox, tick_limit, coop_api, stream)
   if (prec == WCMG_F32) {
     switch (nb) {
       case 8: CGP(WCMG_F32, 8);

@@ -812,7 +812,7 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
   const int* last = nullptr;
   const char* fam = prec == WCMG_F64 ? "coarse_gmres_step_f64" : prec == WCMG_F32 ? "coarse_gmres_step_f32"
                                                                                      : "coarse_gmres_step_bf16";
-  // one cooperative launch for the whole solve when the blocks fit the LDS
+  // one persistent launch for the whole solve when the blocks fit the LDS
   // (reserved[0] flag 4 turns it off); only where the host checks progress,
   // since its report is checked by the host (not under stream capture)
   if (!five && check_every > 0 && !(p.reserved[0] & 4) && cg_persistent_fits(prec, nb, C.V)) {
@@ -837,7 +837,8 @@ int Context::coarse_gmres(int lc, const cplx<R>* b, cplx<R>* x, const int* paren
     prof.begin("coarse_gmres_persistent", stream);
     const bool launched = launch_cg_persistent(prec, nb, blk, C.nbr.as<int>(), C.V, b, x, zP, r, partP, misc, st,
                                                parent, m, p.coarse_tol, limit, fixed, bar, seq, mailbox_dev,
-                                               give_up || force_late ? 0.0 : 5.0, stream);
+                                               give_up || force_late ? 0.0 : 5.0, (p.reserved[0] & 256) != 0,
+                                               stream);
     prof.end("coarse_gmres_persistent", stream);
     if (launched) {
       cgp_pending.push_back(CgpLaunch{seq, bar, nbar, C.V});

@@ -188,7 +188,9 @@ void launch_gmres_cycle_end(int* st_, hipStream_t st);
 // copies st[0..n) to out[1..n] (host-mapped memory), then out[0] = seq
 void launch_publish_state(const int* st_, int n, int* out, int seq, hipStream_t st);
 
-// ---- the coarsest GMRES in one cooperative launch (coarse_persist.hip):
+// ---- the coarsest GMRES in one persistent launch (coarse_persist.hip; coop_api:
+// through the cooperative-launch API, else an ordinary launch of at most one
+// workgroup per CU):
 // false (nothing launched) when the operator's blocks, basis and image do not
 // fit the LDS of co-resident workgroups; part: cd64 [cg_persistent_part_elems];
 // bar: cg_persistent_bar_words words, zeroed with the buffer (bar[2] is set
@@ -208,7 +210,7 @@ size_t cg_persistent_bar_words(long Vc);
 bool launch_cg_persistent(int prec, int nb, const void* blk, const int* nbr, long Vc, const void* b, void* x,
                           void* z, void* r, cd64* part, cd64* misc, int* st, const int* parent, int m, double tol,
                           int limit, int fixed, unsigned* bar, int seq, int* mailbox, double timeout_s,
-                          hipStream_t stream);
+                          bool coop_api, hipStream_t stream);
 constexpr int kCgpSlot0 = 16;       // first report slot in the mailbox
 constexpr int kCgpSlots = 64;       // report slots (a power of two)
 constexpr int kCgpMailboxInts = kCgpSlot0 + 2 * kCgpSlots;
