@@ -419,6 +419,7 @@ __global__ void k_gmres_init(int* st, const int* parent) {
   st[2] = 0;
   st[3] = 0;
   st[4] = 0;
+  st[6] = 0;  // arrival count of k_dot_finish_sr
 }
 
 // Start of a restart cycle: beta = ||r||; decide whether to iterate.
@@ -447,22 +448,31 @@ __global__ void k_gmres_cycle_start(int* st, cd64* S, int m, double tol, int lim
 // st[5] = 1 (repeat the projection) when that is below |w'|^2 / 4.
 // stage 1 (only when st[5]), with d2 the second sweep's sums: column j += d2,
 // hn^2 = |w1|^2 - |d2|^2, and d = d2 for the final update.
+// Stage 0 of the single-reduction step's bookkeeping (one thread): the
+// Hessenberg column from the first projection's sums d, the shift, |w1|^2,
+// and whether the projection is repeated (st[5]).
+__device__ inline void gmres_sr_stage0(int* st, cd64* S, int m, int j, const cd64* d) {
+  cd64* H = S;
+  cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
+  st[5] = 0;
+  if (!st[0]) return;
+  const double n0 = d[j + 1].re;
+  double n1 = n0;
+  for (int i = 0; i <= j; ++i) {
+    H[i * m + j] = d[i];
+    n1 -= d[i].re * d[i].re + d[i].im * d[i].im;
+  }
+  if (j == 0) misc[4] = mkc(d[0].re, 0.0);
+  else H[j * m + j].re += misc[4].re;
+  misc[3] = mkc(n1 > 0.0 ? n1 : 0.0, 0.0);
+  st[5] = n1 < 0.25 * n0 ? 1 : 0;
+}
+
 __global__ void k_gmres_sr(int* st, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage) {
   cd64* H = S;
   cd64* misc = S + (m + 1) * m + 2 * m + (m + 1) + m;
   if (stage == 0) {
-    st[5] = 0;
-    if (!st[0]) return;
-    const double n0 = d[j + 1].re;
-    double n1 = n0;
-    for (int i = 0; i <= j; ++i) {
-      H[i * m + j] = d[i];
-      n1 -= d[i].re * d[i].re + d[i].im * d[i].im;
-    }
-    if (j == 0) misc[4] = mkc(d[0].re, 0.0);
-    else H[j * m + j].re += misc[4].re;
-    misc[3] = mkc(n1 > 0.0 ? n1 : 0.0, 0.0);
-    st[5] = n1 < 0.25 * n0 ? 1 : 0;
+    gmres_sr_stage0(st, S, m, j, d);
   } else {
     if (!st[0] || !st[5]) return;
     double n2 = d2[j + 1].re;
@@ -472,6 +482,40 @@ __global__ void k_gmres_sr(int* st, cd64* S, int m, int j, cd64* d, const cd64* 
       d[i] = d2[i];
     }
     misc[3] = mkc(n2 > 0.0 ? n2 : 0.0, 0.0);
+  }
+}
+
+// k_dot_finish of the first projection's j + 2 sums (one workgroup per sum,
+// into d) followed by stage 0 of the step's bookkeeping, run by the last
+// workgroup to finish (arrival count in st[6], zeroed by k_gmres_init and by
+// that workgroup), so the two need one launch.
+__global__ void __launch_bounds__(256) k_dot_finish_sr(const cd64* __restrict__ partial, int G, int j, cd64* d,
+                                                        int* st, cd64* S, int m) {
+  const int k = blockIdx.x, nk = j + 2;
+  if (!st[0]) {
+    if (k == 0 && threadIdx.x == 0) st[5] = 0;
+    return;
+  }
+  __shared__ cd64 lds[4];
+  __shared__ int last;
+  cd64 s = mkc(0.0, 0.0);
+  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, partial[(long)g * nk + k]);
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cd64 t = mkc(0.0, 0.0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = cadd(t, lds[w]);
+    d[k] = t;
+    __threadfence();  // the sum is visible before the arrival is counted
+    last = atomicAdd(st + 6, 1) == nk - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();  // and the other workgroups' sums are seen after it
+    st[6] = 0;
+    gmres_sr_stage0(st, S, m, j, d);
   }
 }
 
@@ -543,9 +587,9 @@ __global__ void k_gmres_givens(int* st, cd64* S, int m, int j, double tol, int l
 // j + 2 entries each) are summed in k_dot_finish's order, then the stage-1
 // bookkeeping of k_gmres_sr, then the Givens update of column j.  d2: j + 2
 // entries of scratch for the sums (written and read by thread 0 only).
-__global__ void __launch_bounds__(256) k_gmres_sr_finish(int* st, cd64* S, int m, int j, cd64* d, cd64* d2,
-                                                          const cd64* __restrict__ part2, int G2, double tol,
-                                                          int limit, int fixed, int stop_on_estimate) {
+__device__ inline void gmres_sr_finish_body(int* st, cd64* S, int m, int j, cd64* d, cd64* d2,
+                                            const cd64* __restrict__ part2, int G2, double tol, int limit,
+                                            int fixed, int stop_on_estimate) {
   __shared__ cd64 lds[4];
   if (!st[0]) return;
   const bool reorth = st[5] != 0;  // the same value in every thread
@@ -579,10 +623,29 @@ __global__ void __launch_bounds__(256) k_gmres_sr_finish(int* st, cd64* S, int m
   }
   gmres_givens_body(st, S, m, j, tol, limit, fixed, stop_on_estimate);
 }
+
+// Copies n state words to out[1..n] (host-mapped memory), then writes the
+// publication number to out[0] (one thread).
+__device__ inline void publish_words(const int* st, int n, int* out, int seq) {
+  for (int i = 0; i < n; ++i) __hip_atomic_store(out + 1 + i, st[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+  __hip_atomic_store(out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// pub != nullptr: afterwards st[0..pub_n) is published as k_publish_state
+// would (publication pub_seq), in the same launch.
+__global__ void __launch_bounds__(256) k_gmres_sr_finish(int* st, cd64* S, int m, int j, cd64* d, cd64* d2,
+                                                          const cd64* __restrict__ part2, int G2, double tol,
+                                                          int limit, int fixed, int stop_on_estimate, int* pub,
+                                                          int pub_seq, int pub_n) {
+  gmres_sr_finish_body(st, S, m, j, d, d2, part2, G2, tol, limit, fixed, stop_on_estimate);
+  if (pub && threadIdx.x == 0) publish_words(st, pub_n, pub, pub_seq);
+}
 void launch_gmres_sr_finish(int* st_, cd64* S, int m, int j, cd64* d, cd64* d2, const cd64* part2, int G2,
-                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st) {
+                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st, int* pub, int pub_seq,
+                            int pub_n) {
   hipLaunchKernelGGL(k_gmres_sr_finish, dim3(1), dim3(kBlock), 0, st, st_, S, m, j, d, d2, part2, G2, tol, limit,
-                     fixed, stop_on_est);
+                     fixed, stop_on_est, pub, pub_seq, pub_n);
   WCMG_CHECK_LAUNCH();
 }
 
@@ -741,6 +804,10 @@ void launch_gmres_cycle_start(int* st_, cd64* S, int m, double tol, int limit, i
 void launch_gmres_givens(int* st_, cd64* S, int m, int j, double tol, int limit, int fixed, int stop_on_est,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, st, st_, S, m, j, tol, limit, fixed, stop_on_est);
+  WCMG_CHECK_LAUNCH();
+}
+void launch_dot_finish_sr(const cd64* partial, int G, int j, cd64* d, int* st_, cd64* S, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_finish_sr, dim3(j + 2), dim3(kBlock), 0, st, partial, G, j, d, st_, S, m);
   WCMG_CHECK_LAUNCH();
 }
 void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st) {

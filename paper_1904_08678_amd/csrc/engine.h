@@ -259,6 +259,9 @@ struct Context {
   std::map<const int*, StateMailbox> state_mb;
   // queues the publication of st[0..n); returns its number
   int publish_state(const int* st, int n);
+  // the next publication of st[0..n) without the copy: its number, and in
+  // *slot the device address a kernel writes it to (as publish_state's copy)
+  int reserve_state(const int* st, int n, int** slot);
   // waits for publication `seq` of st (the last or the one before it) and
   // returns a copy of its words; the coarsest solves issued before it are
   // then checked
@@ -271,8 +274,9 @@ struct Context {
     const int* st;
     int n;
     int pend = 0;
-    const int* ahead() {
-      const int s = c.publish_state(st, n);
+    const int* ahead() { return ahead_issued(c.publish_state(st, n)); }
+    // as ahead(), for a publication s that a kernel of the step has made
+    const int* ahead_issued(int s) {
       const int* sv = pend ? c.wait_state(st, pend) : nullptr;
       pend = s;
       return sv;

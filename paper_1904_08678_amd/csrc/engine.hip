@@ -415,6 +415,13 @@ void Context::sync() {
 }
 
 int Context::publish_state(const int* st, int n) {
+  int* slot = nullptr;
+  const int seq = reserve_state(st, n, &slot);
+  launch_publish_state(st, n, slot, seq, stream);
+  return seq;
+}
+
+int Context::reserve_state(const int* st, int n, int** slot) {
   StateMailbox& M = state_mb[st];
   if (M.cap < n) {
     // a larger buffer: earlier publications must have landed before the copy
@@ -434,7 +441,7 @@ int Context::publish_state(const int* st, int n) {
   }
   const int seq = ++M.seq;
   M.cgp[seq & 1] = cgp_seq;
-  launch_publish_state(st, n, M.d + (seq & 1) * (M.cap + 1), seq, stream);
+  *slot = M.d + (seq & 1) * (M.cap + 1);
   if ((int)M.words.size() < n) M.words.resize(n);
   return seq;
 }
@@ -725,16 +732,20 @@ int Context::gmres(GmresState& G, const std::function<void(const cplx<R>*, cplx<
         cplx<R>* wj = V + (long)(j + 1) * nn;
         A(zj, wj, run);
         launch_arnoldi_dots<R>(V, nn, j, j > 0 ? misc + 4 : nullptr, part, j + 2, run, stream);
-        launch_dot_finish(part, Gb, j + 2, j + 2, tmp, 1, 0, run, stream);
-        launch_gmres_sr(st, S, m, j, tmp, tmp2, 0, stream);
+        launch_dot_finish_sr(part, Gb, j, tmp, st, S, m, stream);
         launch_multi_axpy<R>(wj, V, nn, j + 1, nullptr, tmp, 1, -1.0, nn, st + 5, stream, 1024);
         // the second projection is rare: a small grid, so that skipping it is cheap
         const int G2 = std::min(Gb, 256);
         launch_arnoldi_dots<R>(V, nn, j, nullptr, part, j + 2, st + 5, stream, G2);
-        launch_gmres_sr_finish(st, S, m, j, tmp, tmp2, part, G2, tol, limit, fixed, stop_on_est ? 1 : 0, stream);
+        // a progress check after this step: the finishing kernel publishes the state
+        const bool check = check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m;
+        int* slot = nullptr;
+        const int seq = check ? reserve_state(st, 5, &slot) : 0;
+        launch_gmres_sr_finish(st, S, m, j, tmp, tmp2, part, G2, tol, limit, fixed, stop_on_est ? 1 : 0, stream,
+                               slot, seq, 5);
         if (j + 1 < m) launch_update_scale<R>(wj, V, nn, j + 1, tmp, misc + 3, nn, run, stream);
-        if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < m) {
-          const int* sv = chk.ahead();
+        if (check) {
+          const int* sv = chk.ahead_issued(seq);
           if (sv && !sv[0]) break;
         }
         continue;

@@ -172,11 +172,18 @@ void launch_gmres_solve_y(const int* st_, cd64* S, int m, hipStream_t st);
 // single-reduction Arnoldi step (blas.hip): first sweep (shifted vector, its
 // dots with V_0..V_j and its norm), bookkeeping, last sweep (update + scale)
 void launch_gmres_sr(int* st_, cd64* S, int m, int j, cd64* d, const cd64* d2, int stage, hipStream_t st);
+// launch_dot_finish of the j + 2 first-projection sums (partials with stride
+// j + 2, into d) and launch_gmres_sr stage 0 in one launch (st: the solver's
+// state words, st[6] an arrival count that k_gmres_init zeroes)
+void launch_dot_finish_sr(const cd64* partial, int G, int j, cd64* d, int* st_, cd64* S, int m, hipStream_t st);
 // Stage 1 of launch_gmres_sr (its second-projection products summed from G2
 // partials part2[g * (j + 2) + k] inside, into d2) followed by
 // launch_gmres_givens, in one single-workgroup launch.
+// pub != nullptr: st[0..pub_n) is then published to pub as launch_publish_state
+// would (number pub_seq), in the same launch.
 void launch_gmres_sr_finish(int* st_, cd64* S, int m, int j, cd64* d, cd64* d2, const cd64* part2, int G2,
-                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st);
+                            double tol, int limit, int fixed, int stop_on_est, hipStream_t st, int* pub = nullptr,
+                            int pub_seq = 0, int pub_n = 0);
 template <typename R>
 // grid: workgroups (partials) to use, 0 = reduction_blocks(n)
 void launch_arnoldi_dots(cplx<R>* V, long n, int j, const cd64* shift, cd64* partial, int mstride, const int* run,
