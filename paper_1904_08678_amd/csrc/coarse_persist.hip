@@ -593,8 +593,10 @@ bool cgp_shape_fits() {
 // co-resident.  The grid is launched as an ordinary kernel (one workgroup per
 // CU at most, nothing else on the stream while it runs, so all workgroups are
 // resident together); coop: through the cooperative-launch API instead, which
-// guarantees co-residency but synchronises with a separate device queue before
-// and after the launch.  Every barrier wait has a time limit either way.
+// guarantees co-residency at a few microseconds more per launch.  Every barrier
+// wait has a time limit either way.  The device properties and the occupancy
+// are queried once per device: per launch they cost host time the device
+// waited for.
 template <int P, int NB>
 bool cgp_launch(const void* blk, const int* nbr, long Vc, const void* b, void* x, void* z, void* r, cd64* part,
                 cd64* misc, int* st, const int* parent, int m, double tol, int limit, int fixed, unsigned* bar,
