@@ -296,7 +296,9 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
   if (!item_rhs(nblk, nrhs, &blk, &r)) return;
   if (run && !run[r * rs]) return;
   __shared__ cplx<R> part[4][12][64];
-  __shared__ cd64 red[4];
+  __shared__ cd64 red[8];
+  // FP32 with dots: the own-site input of both chiralities, shared by the four waves
+  __shared__ cplx<R> pinl[sizeof(R) == 4 ? 12 : 1][64];
   const int lane = threadIdx.x & 63;
   const int mu = threadIdx.x >> 6;  // wave-uniform
   const long s = blk * 64 + lane;
@@ -326,6 +328,11 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
   }
 #pragma unroll
   for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[k];
+  if constexpr (sizeof(R) == 4) {
+    if (dots && mu < 2)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) pinl[6 * mu + c][lane] = pin[c];
+  }
   __syncthreads();
   if (!dots) {
     // wave mu writes components 3 mu .. 3 mu + 2 (spin mu), summed over the 4 waves in order
@@ -340,6 +347,43 @@ __global__ void __launch_bounds__(256) k_wilson(const cplx<R>* __restrict__ in, 
         if (bsub) v = csub(bsub[r * 12 * V + (long)k * V + s], v);
         out[(long)k * V + s] = v;
       }
+    }
+    return;
+  }
+  if constexpr (sizeof(R) == 4) {
+    // every wave writes the three components of spin mu and forms their
+    // products with the input (from LDS); the four waves' sums are added in order
+    double pr = 0.0, pi = 0.0, pp = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * mu + c;
+      cplx<R> v = part[0][k][lane];
+      v = cadd(v, part[1][k][lane]);
+      v = cadd(v, part[2][k][lane]);
+      v = cadd(v, part[3][k][lane]);
+      if (valid) {
+        out[(long)k * V + s] = v;
+        const cplx<R> x = pinl[k][lane];
+        pr += (double)v.re * x.re + (double)v.im * x.im;
+        pi += (double)v.re * x.im - (double)v.im * x.re;
+        pp += (double)v.re * v.re + (double)v.im * v.im;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pr += __shfl_xor(pr, off, 64);
+      pi += __shfl_xor(pi, off, 64);
+      pp += __shfl_xor(pp, off, 64);
+    }
+    if (lane == 0) {
+      red[2 * mu] = mkc(pr, pi);
+      red[2 * mu + 1] = mkc(pp, 0.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const long bi = r * nblk + blk;
+      dots[2 * bi] = cadd(cadd(red[0], red[2]), cadd(red[4], red[6]));
+      dots[2 * bi + 1] = cadd(cadd(red[1], red[3]), cadd(red[5], red[7]));
     }
     return;
   }

@@ -490,6 +490,33 @@ def test_cooperative_coarse_gmres_timeout_falls_back():
     assert abs(i0["outer_iters"] - i4["outer_iters"]) <= 1
 
 
+def test_persistent_coarse_gmres_launch_forms_agree():
+    """The persistent coarsest GMRES launched as an ordinary kernel (the
+    default) and through the cooperative-launch API (reserved[0] flag 256):
+    the same kernel and grid, so the solves are bit-identical, with the same
+    outer and coarse iteration counts and no barrier time-out."""
+    w = wc()
+    L, block, nv = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = int(np.prod(L))
+    U = syn.gauge_field(L, 0.25, 1951)
+    start = syn.complex_gaussian((nv, V, 12), 1952)
+    b = syn.complex_gaussian((V, 4, 3), 1953)
+    res = []
+    for flags in (0, 256):
+        ctx = w.Context(dims=L, m0=-0.05, n_levels=2, block=(block,), n_vec=(nv,), cycle_prec=w.F32,
+                        coarse_store_prec=w.F32, setup_prec=w.F32, reserved=(flags,))
+        ctx.set_gauge(dev(U))
+        ctx.set_null_vectors(0, dev(start))
+        ctx.setup()
+        x, info, st = ctx.solve(dev(b))
+        assert st == 0 and info[0]["true_rel_res"] <= 1e-10
+        assert ctx.timers()["coarse_solve_fallbacks"] == 0
+        res.append((host(x), info[0]))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1]["outer_iters"] == res[1][1]["outer_iters"]
+    assert res[0][1]["coarse_iters"] == res[1][1]["coarse_iters"] > 0
+
+
 def test_cooperative_coarse_gmres_late_check_after_timeout():
     """The host checks a cooperative coarsest solve only at the next progress
     check.  reserved[0] flag 128 makes the first launch's waits give up at
