@@ -76,6 +76,69 @@ __global__ void __launch_bounds__(512) k_restrict(const cplx<R>* __restrict__ fi
   }
 }
 
+// k_restrict for FP32 fields whose aggregates have at most 256 sites and an
+// even number of components per chirality: each thread takes one site, so no
+// FP64 accumulators are live while its loads are in flight, and it loads two
+// components' operands per pass (the same products in the same order, so the
+// result equals k_restrict's bit for bit).
+template <int NB>
+__global__ void __launch_bounds__(512) k_restrict_one(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
+                                                       const cf32* __restrict__ P, FieldLayout lay,
+                                                       const int* __restrict__ agg_sites, int A, long Vc, int nrhs,
+                                                       const int* __restrict__ run, int rs) {
+  long c, r;
+  if (!item_rhs(Vc, nrhs, &c, &r)) return;
+  if (run && !run[r * rs]) return;
+  constexpr int nv = NB / 2;
+  __shared__ cd64 lds[8][nv];
+  fine += r * lay.size();
+  coarse += r * Vc * NB;
+  const int h = lay.ns / 2;
+  const long pstride = lay.size();
+  const int chi = threadIdx.x >> 8;  // wave-uniform
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int o = threadIdx.x & 255;
+  cf32 pa[nv];
+#pragma unroll
+  for (int i = 0; i < nv; ++i) pa[i] = mkc(0.f, 0.f);
+  if (o < A) {
+    const long s = agg_sites[c * A + o];
+    for (int k = 0; k < h; k += 2) {
+      const long e0 = lay.at(s, chi * h + k), e1 = lay.at(s, chi * h + k + 1);
+      const cf32 v0 = fine[e0], v1 = fine[e1];
+      cf32 p0[nv], p1[nv];
+#pragma unroll
+      for (int i = 0; i < nv; ++i) {
+        p0[i] = P[i * pstride + e0];
+        p1[i] = P[i * pstride + e1];
+      }
+#pragma unroll
+      for (int i = 0; i < nv; ++i) {
+        cfmac(pa[i], p0[i], v0);
+        cfmac(pa[i], p1[i], v1);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < nv; ++i) {
+    double re = (double)pa[i].re, im = (double)pa[i].im;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) lds[wave][i] = mkc(re, im);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const int q = threadIdx.x / nv, i = threadIdx.x - q * nv;
+    cd64 t = mkc(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) t = cadd(t, lds[4 * q + w][i]);
+    coarse[c * NB + threadIdx.x] = ccast<float>(t);
+  }
+}
+
 // fine(x)_k (+)= sum_{i} P_i(x)_k coarse(c(x), chi(k) * nv + i); thread per site,
 // grid item_rhs_grid(site blocks, nrhs).
 template <typename R, int NB>
@@ -729,6 +792,10 @@ void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, Fie
     NB_SWITCH_MRHS(nb, RH_SWITCH(nrhs, WCMG_LAUNCH((k_restrict_mrhs<NBc, RHc>), g, dim3(256), 0, st, (const cf32*)fine,
                                                    (cf32*)coarse, (const cf32*)P, lay.V, agg_sites, A, Vc, nrhs, run,
                                                    rs)));
+  } else if (std::is_same<R, float>::value && A <= 256 && (lay.ns / 2) % 2 == 0) {
+    NB_SWITCH(nb, WCMG_LAUNCH((k_restrict_one<NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st,
+                               (const cf32*)fine, (cf32*)coarse, (const cf32*)P, lay, agg_sites, A, Vc, nrhs, run,
+                               rs));
   } else {
     NB_SWITCH(nb, WCMG_LAUNCH((k_restrict<R, NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st, fine, coarse, P,
                                lay, agg_sites, A, Vc, nrhs, run, rs));
