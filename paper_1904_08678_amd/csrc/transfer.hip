@@ -76,12 +76,12 @@ __global__ void __launch_bounds__(512) k_restrict(const cplx<R>* __restrict__ fi
   }
 }
 
-// k_restrict for FP32 fields whose aggregates have at most 256 sites and an
-// even number of components per chirality: each thread takes one site, so no
-// FP64 accumulators are live while its loads are in flight, and it loads two
-// components' operands per pass (the same products in the same order, so the
-// result equals k_restrict's bit for bit).
-template <int NB>
+// k_restrict for FP32 fields whose aggregates have at most 256 sites and a
+// number of components per chirality divisible by KP: each thread takes one
+// site, so no FP64 accumulators are live while its loads are in flight, and it
+// loads KP components' operands per pass (the same products in the same order,
+// so the result equals k_restrict's bit for bit).
+template <int NB, int KP>
 __global__ void __launch_bounds__(512) k_restrict_one(const cf32* __restrict__ fine, cf32* __restrict__ coarse,
                                                        const cf32* __restrict__ P, FieldLayout lay,
                                                        const int* __restrict__ agg_sites, int A, long Vc, int nrhs,
@@ -103,20 +103,22 @@ __global__ void __launch_bounds__(512) k_restrict_one(const cf32* __restrict__ f
   for (int i = 0; i < nv; ++i) pa[i] = mkc(0.f, 0.f);
   if (o < A) {
     const long s = agg_sites[c * A + o];
-    for (int k = 0; k < h; k += 2) {
-      const long e0 = lay.at(s, chi * h + k), e1 = lay.at(s, chi * h + k + 1);
-      const cf32 v0 = fine[e0], v1 = fine[e1];
-      cf32 p0[nv], p1[nv];
+    for (int k = 0; k < h; k += KP) {
+      long e[KP];
+      cf32 v[KP], pk[KP][nv];
 #pragma unroll
-      for (int i = 0; i < nv; ++i) {
-        p0[i] = P[i * pstride + e0];
-        p1[i] = P[i * pstride + e1];
+      for (int q = 0; q < KP; ++q) {
+        e[q] = lay.at(s, chi * h + k + q);
+        v[q] = fine[e[q]];
       }
 #pragma unroll
-      for (int i = 0; i < nv; ++i) {
-        cfmac(pa[i], p0[i], v0);
-        cfmac(pa[i], p1[i], v1);
-      }
+      for (int q = 0; q < KP; ++q)
+#pragma unroll
+        for (int i = 0; i < nv; ++i) pk[q][i] = P[i * pstride + e[q]];
+#pragma unroll
+      for (int i = 0; i < nv; ++i)
+#pragma unroll
+        for (int q = 0; q < KP; ++q) cfmac(pa[i], pk[q][i], v[q]);
     }
   }
 #pragma unroll
@@ -792,8 +794,12 @@ void launch_restrict(const cplx<R>* fine, cplx<R>* coarse, const cplx<R>* P, Fie
     NB_SWITCH_MRHS(nb, RH_SWITCH(nrhs, WCMG_LAUNCH((k_restrict_mrhs<NBc, RHc>), g, dim3(256), 0, st, (const cf32*)fine,
                                                    (cf32*)coarse, (const cf32*)P, lay.V, agg_sites, A, Vc, nrhs, run,
                                                    rs)));
+  } else if (std::is_same<R, float>::value && A <= 256 && (lay.ns / 2) % 3 == 0) {
+    NB_SWITCH(nb, WCMG_LAUNCH((k_restrict_one<NBc, 3>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st,
+                               (const cf32*)fine, (cf32*)coarse, (const cf32*)P, lay, agg_sites, A, Vc, nrhs, run,
+                               rs));
   } else if (std::is_same<R, float>::value && A <= 256 && (lay.ns / 2) % 2 == 0) {
-    NB_SWITCH(nb, WCMG_LAUNCH((k_restrict_one<NBc>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st,
+    NB_SWITCH(nb, WCMG_LAUNCH((k_restrict_one<NBc, 2>), dim3(item_rhs_grid(Vc, nrhs)), dim3(512), 0, st,
                                (const cf32*)fine, (cf32*)coarse, (const cf32*)P, lay, agg_sites, A, Vc, nrhs, run,
                                rs));
   } else {
