@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_dot_finish(const cd64* __restrict__ par
   if (k >= m) return;
   __shared__ cd64 lds[4];
   cd64 s = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, partial[(long)g * mstride + k]);
+  s = strided_sum<8>(threadIdx.x, blockDim.x, G, [&](int g) { return partial[(long)g * mstride + k]; });
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) lds[wave] = s;
@@ -338,9 +338,21 @@ __global__ void __launch_bounds__(kMrBlock) k_mr_update_part(cplx<R>* __restrict
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x < 256) {
     cd64 s0 = mkc(0.0, 0.0), s1 = mkc(0.0, 0.0);
-    for (int g = threadIdx.x; g < G; g += 256) {
-      s0 = cadd(s0, part[2L * g]);
-      s1 = cadd(s1, part[2L * g + 1]);
+    // rows threadIdx.x, + 256, ... in order, eight rows' loads in flight at once
+    for (int g0 = threadIdx.x; g0 < G; g0 += 8 * 256) {
+      cd64 a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int g = min(g0 + 256 * u, G - 1);
+        a[u] = part[2L * g];
+        b[u] = part[2L * g + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (g0 + 256 * u < G) {
+          s0 = cadd(s0, a[u]);
+          s1 = cadd(s1, b[u]);
+        }
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
@@ -499,7 +511,7 @@ __global__ void __launch_bounds__(256) k_dot_finish_sr(const cd64* __restrict__ 
   __shared__ cd64 lds[4];
   __shared__ int last;
   cd64 s = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, partial[(long)g * nk + k]);
+  s = strided_sum<8>(threadIdx.x, blockDim.x, G, [&](int g) { return partial[(long)g * nk + k]; });
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) lds[wave] = s;

@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(256) k_bdot_finish(const cd64* __restrict__ pa
   __shared__ cd64 lds[4];
   partial += (long)r * G * mstride;
   cd64 s = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, partial[(long)g * mstride + k]);
+  s = strided_sum<8>(threadIdx.x, blockDim.x, G, [&](int g) { return partial[(long)g * mstride + k]; });
   s = wsum2(s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) lds[wave] = s;

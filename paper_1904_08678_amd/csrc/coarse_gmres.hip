@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_cg_cycle_start(int* st, cd64* S, int m,
     return;
   }
   cd64 s = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, part[(long)g * m1]);
+  s = strided_sum<8>(threadIdx.x, blockDim.x, G, [&](int g) { return part[(long)g * m1]; });
   s = wsum(s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) lds[wave] = s;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_cg_givens(int* st, cd64* S, int m, int 
   if (!st[0]) return;
   const int m1 = m + 1;
   cd64 s = mkc(0.0, 0.0);
-  for (int g = threadIdx.x; g < G; g += blockDim.x) s = cadd(s, part[(long)g * m1]);
+  s = strided_sum<8>(threadIdx.x, blockDim.x, G, [&](int g) { return part[(long)g * m1]; });
   s = wsum(s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) lds[wave] = s;

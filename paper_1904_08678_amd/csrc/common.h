@@ -48,6 +48,22 @@ __host__ __device__ inline cplx<R> mkc(R a, R b) {
   c.im = b;
   return c;
 }
+
+// sum of f(g) over g = t, t + step, ... < G, added in that order, with U
+// terms' loads in flight at once (indices past the end clamped, not added)
+template <int U, typename F>
+__device__ inline cplx<double> strided_sum(int t, int step, int G, F f) {
+  cplx<double> s = mkc(0.0, 0.0);
+  for (int g0 = t; g0 < G; g0 += U * step) {
+    cplx<double> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = f(min(g0 + u * step, G - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (g0 + u * step < G) s = mkc(s.re + v[u].re, s.im + v[u].im);
+  }
+  return s;
+}
 template <typename R>
 __host__ __device__ inline cplx<R> cadd(cplx<R> a, cplx<R> b) { return mkc(a.re + b.re, a.im + b.im); }
 template <typename R>
