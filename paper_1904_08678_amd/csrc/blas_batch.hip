@@ -427,16 +427,18 @@ __global__ void k_bgmres_givens(int* st, cd64* S, long ss, int B, int m, int j, 
   cd64* misc = g + (m + 1) + m;
   const double hn = sqrt(misc[3].re);
   H[(j + 1) * m + j] = mkc(hn, 0.0);
+  // the entry rotated down the column stays in a register, so a rotation's
+  // loads do not wait for the previous one's stores (the same arithmetic)
+  cd64 a = H[j];
   for (int i = 0; i < j; ++i) {
-    cd64 a = H[i * m + j], b = H[(i + 1) * m + j];
-    cd64 t = cmul(cs[i], a);
-    cfma(t, sn[i], b);
-    cd64 u = cmul(cneg(cconj(sn[i])), a);
-    cfma(u, cconj(cs[i]), b);
+    const cd64 b = H[(i + 1) * m + j], ci = cs[i], si = sn[i];
+    cd64 t = cmul(ci, a);
+    cfma(t, si, b);
+    cd64 u = cmul(cneg(cconj(si)), a);
+    cfma(u, cconj(ci), b);
     H[i * m + j] = t;
-    H[(i + 1) * m + j] = u;
+    a = u;
   }
-  const cd64 a = H[j * m + j];
   const double den = sqrt(a.re * a.re + a.im * a.im + hn * hn);
   const cd64 c = den == 0.0 ? mkc(1.0, 0.0) : mkc(a.re / den, -a.im / den);
   const cd64 sv = den == 0.0 ? mkc(0.0, 0.0) : mkc(hn / den, 0.0);

@@ -212,16 +212,18 @@ __global__ void __launch_bounds__(256) k_cg_givens(int* st, cd64* S, int m, int 
   c.misc[3] = mkc(hn2, 0.0);
   const double hn = sqrt(hn2);
   cd64* H = c.H;
+  // the entry rotated down the column stays in a register, so a rotation's
+  // loads do not wait for the previous one's stores (the same arithmetic)
+  cd64 a = H[j];
   for (int i = 0; i < j; ++i) {
-    cd64 a = H[i * m + j], b = H[(i + 1) * m + j];
-    cd64 t = cmul(c.cs[i], a);
-    cfma(t, c.sn[i], b);
-    cd64 u = cmul(cneg(cconj(c.sn[i])), a);
-    cfma(u, cconj(c.cs[i]), b);
+    const cd64 b = H[(i + 1) * m + j], ci = c.cs[i], si = c.sn[i];
+    cd64 t = cmul(ci, a);
+    cfma(t, si, b);
+    cd64 u = cmul(cneg(cconj(si)), a);
+    cfma(u, cconj(ci), b);
     H[i * m + j] = t;
-    H[(i + 1) * m + j] = u;
+    a = u;
   }
-  const cd64 a = H[j * m + j];
   const double den = sqrt(a.re * a.re + a.im * a.im + hn2);
   const cd64 cc = den == 0.0 ? mkc(1.0, 0.0) : mkc(a.re / den, -a.im / den);
   const cd64 ss = den == 0.0 ? mkc(0.0, 0.0) : mkc(hn / den, 0.0);
