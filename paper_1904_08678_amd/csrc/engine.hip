@@ -373,6 +373,8 @@ Context::Context(const wcmg_params& prm, hipStream_t s) : p(prm), stream(s) {
 }
 
 Context::~Context() {
+  // kernels still queued may write the host-mapped mailboxes freed below
+  (void)hipStreamSynchronize(stream);
   drop_graph();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
